@@ -1,0 +1,19 @@
+"""Builds liboracle_cd.so from cd_serial.cpp (test infrastructure only)."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle_cd.so")
+
+
+def build(verbose=False):
+    src = os.path.join(HERE, "cd_serial.cpp")
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", LIB, src, "-lquadmath"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

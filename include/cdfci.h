@@ -1,0 +1,160 @@
+/*
+ * cdfci.h -- C ABI of the MI355X (gfx950) coordinate-descent FCI library.
+ *
+ * The library minimises f(c) = ||H + c c^T||_F^2 over the coefficients of a
+ * sparse determinant expansion (paper Sec. 2.3, eq. (optimization)); its
+ * minimisers are +-sqrt(-E0) v0 for the lowest eigenpair of H when E0 < 0.
+ * H is the second-quantised Hamiltonian of eq. (general-ham), given by a
+ * one-body matrix h and chemist two-body integrals (pq|rs), or by a periodic
+ * Hubbard lattice (Sec. 2.2).  The coefficient vector c and the residual
+ * b = H c are held together in a device-resident open-addressing hash table
+ * keyed by 128-bit determinants.
+ *
+ * Determinant keys: a pair of 64-bit occupation strings {alpha, beta}; bit p
+ * of the alpha word set means spatial orbital (or site) p holds a spin-up
+ * electron.  Spin-orbital order for fermionic phases is all alpha orbitals
+ * then all beta orbitals, each ascending; at most 63 spatial orbitals.
+ *
+ * Conventions for every entry point:
+ *   - return value 0 = success, negative = CDFCI_ERR_* (never an exception);
+ *     cdfci_strerror() gives text, cdfci_last_error() the last HIP message;
+ *   - pointers are host pointers unless said otherwise; the library copies
+ *     what it needs and never keeps a caller pointer past the call;
+ *   - one context belongs to one HIP stream and is not re-entrant: calls on
+ *     the same context must not overlap.
+ */
+#ifndef CDFCI_H
+#define CDFCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define CDFCI_OK 0
+#define CDFCI_ERR_INVALID_ARG -1   /* bad sizes / null pointers / state */
+#define CDFCI_ERR_UNSUPPORTED -2   /* N > 63, n > N, or a mode not built */
+#define CDFCI_ERR_TABLE_FULL -3    /* hash table passed its occupancy limit (Sec. 4.1.2) */
+#define CDFCI_ERR_NOT_NEGATIVE -4  /* starting energy >= 0: f has no nonzero minimiser (Sec. 2.3) */
+#define CDFCI_ERR_HIP -5           /* a HIP runtime call failed */
+#define CDFCI_ERR_BARRIER -6       /* a device-wide barrier exceeded its spin limit */
+#define CDFCI_ERR_WORKSPACE -7     /* caller workspace too small */
+
+typedef struct cdfci_ctx cdfci_ctx; /* opaque, library-owned */
+
+/* Options.  A zero-initialised struct gives the defaults noted per field. */
+typedef struct {
+  uint64_t table_slots;  /* hash slots (power of two); 0 = 2^22 */
+  double load_factor;    /* max stored entries / slots before TABLE_FULL; 0 = 0.79 (Sec. 4.3) */
+  double z_threshold;    /* compression threshold tau on b updates (Sec. 3.1); default 0 */
+  double dx_damping;     /* theta of the damped step accumulator (Sec. 4.1.3); 0 = 0.9 */
+  double dx_threshold;   /* stop when the accumulator falls below this; 0 = never */
+  int init_kind;         /* c^(0): 0 = model default (1 for integrals, 2 for lattices);
+                            1 = lowest-h_pp (aufbau) determinant with c = sqrt(-H_00);
+                            2 = Neel determinant + sqrt(-lambda) times the lowest eigenvector
+                            of H on it and the nonzero entries of its column */
+  int grid_blocks;       /* workgroups of the single-coordinate persistent kernel; 0 = auto */
+  int block_threads;     /* threads per workgroup (64..256, multiple of 64); 0 = 256 */
+  int reserved0;
+  void* workspace;          /* optional caller-owned device memory for the hash table and
+                               buffers (e.g. a torch tensor); NULL = library allocates */
+  size_t workspace_bytes;   /* size of `workspace` */
+  void* stream;             /* hipStream_t to enqueue on; NULL = default stream */
+} cdfci_opts;
+
+/* Per-call statistics (Sec. 4.1.3 report quantities). */
+typedef struct {
+  int64_t steps;          /* coordinate-descent iterations done by this call */
+  int64_t total_steps;    /* iterations since init */
+  int64_t elements;       /* Hamiltonian entries enumerated (zeros included) */
+  int64_t inserts;        /* new determinants stored */
+  uint64_t occupied;      /* determinants in the table */
+  int32_t max_probe;      /* longest probe sequence seen */
+  int32_t stopped;        /* 1 if the damped accumulator fell below dx_threshold */
+  double energy;          /* alpha / mu after the call */
+  double dx;              /* damped accumulator d */
+  double mu, alpha;       /* c^T c and c^T H c (maintained) */
+  double seconds;         /* device time of the call */
+} cdfci_stats;
+
+/* Device bytes the context needs for the given sizes and options. */
+int cdfci_workspace_size(int n_orb, int n_alpha, int n_beta, const cdfci_opts* opts, size_t* bytes);
+
+/* Create a context for an integral Hamiltonian (Sec. 2.2 eq. (general-ham),
+ * Sec. 4.1.1 HamiltonianMolecule).  h: n_orb*n_orb row-major, symmetric.
+ * eri: n_orb^4 row-major chemist (pq|rs), eri[((p*N+q)*N+r)*N+s], with the
+ * 8-fold permutational symmetry.  Both host pointers, copied to the device.
+ * Builds c^(0) per opts->init_kind and b^(0) = H c^(0) exactly (Alg. 1). */
+int cdfci_init(const double* h, const double* eri, int n_orb, int n_alpha, int n_beta,
+               const cdfci_opts* opts, cdfci_ctx** out);
+
+/* Create a context for a periodic Hubbard lattice (Sec. 2.2): dims[0..ndim)
+ * sites per direction (row-major site index), hopping -t on each distinct
+ * nearest-neighbour pair (a direction of length 2 gives one bond), on-site
+ * repulsion U. */
+int cdfci_init_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                       const cdfci_opts* opts, cdfci_ctx** out);
+
+/* Run up to nsteps iterations (Alg. 1 when k == 1, Alg. 2 when k > 1) and
+ * stop early if the damped step accumulator drops below dx_threshold
+ * (Sec. 4.1.3).  Enqueued on the context's stream; returns after completion.
+ * out may be NULL. */
+int cdfci_step(cdfci_ctx* ctx, int k, int64_t nsteps, cdfci_stats* out);
+
+/* Like cdfci_step (k == 1 only) and also records, per iteration, the energy,
+ * the chosen determinant and the step size into host arrays of length nsteps
+ * (any may be NULL).  For parity tests. */
+int cdfci_step_trace(cdfci_ctx* ctx, int64_t nsteps, double* energy, uint64_t* sel_alpha,
+                     uint64_t* sel_beta, double* eta, cdfci_stats* out);
+
+/* Energy estimate.  exact = 0: the maintained Rayleigh quotient alpha/mu
+ * (get_variational_energy, Sec. 4.1.2).  exact = 1: recomputed
+ * c^T H c / c^T c by applying H to the stored c on the device. */
+int cdfci_energy(cdfci_ctx* ctx, int exact, double* energy);
+
+/* Reverse pass of E = c^T H c / c^T c with c held fixed (pattern (a)):
+ * the truncated, normalised wavefunction is the top_n stored determinants by
+ * |c| (top_n <= 0: all).  Outputs, host, any may be NULL:
+ *   dh[p*N+q]    = grad_E * gamma_pq,  gamma_pq = sum_s <a+_ps a_qs>;
+ *   deri[pqrs]   = grad_E * Gamma_pqrs / 2,
+ *                  Gamma_pqrs = sum_st <a+_ps a+_rt a_st a_qs> (chemist order);
+ *   kappa[p*N+q] = grad_E * 2 (F_pq - F_qp), F_pq = sum_r h_pr gamma_rq
+ *                  + sum_rst (pr|st) Gamma_qrst, the gradient of E(U = exp(K))
+ *                  in K_pq (p > q) for rotated orbitals (Sec. 3.4, eq. (subopt)). */
+int cdfci_rdm_backward(cdfci_ctx* ctx, double grad_E, int64_t top_n, double* dh, double* deri,
+                       double* kappa);
+
+/* get_column (Sec. 4.1.1): every (D', H_{D',D}) for D' = D and all single and
+ * double excitations of D, in the library's enumeration order with the
+ * diagonal first and exact zeros kept.  keys: 2*cap uint64 (alpha, beta
+ * interleaved), vals: cap doubles.  *count = number of entries; if it
+ * exceeds cap nothing is written and CDFCI_ERR_INVALID_ARG is returned. */
+int cdfci_column(cdfci_ctx* ctx, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
+                 int64_t* count);
+
+/* get_entry (Sec. 4.1.1): H_{k1,k2} by the Slater-Condon rules, eq. (entry). */
+int cdfci_entry(cdfci_ctx* ctx, const uint64_t k1[2], const uint64_t k2[2], double* value);
+
+/* Copy the stored determinants out: keys 2*cap uint64 (alpha, beta), c and b
+ * values (true scale).  top_n > 0 keeps the top_n by |c|; top_n <= 0 keeps all
+ * entries.  *count = entries available; at most cap are written. */
+int cdfci_export(cdfci_ctx* ctx, int64_t top_n, uint64_t* keys, double* c, double* b, int64_t cap,
+                 int64_t* count);
+
+/* Profiling aid: device seconds that workgroup 0 of the single-coordinate
+ * kernel has spent, since init, in its four phases: [0] choose-and-step
+ * (H_DD, line search), [1] column scatter, [2] waiting at the device-wide
+ * barrier, [3] combining the partial results.  seconds: 4 doubles. */
+int cdfci_phase_times(cdfci_ctx* ctx, double* seconds);
+
+int cdfci_free(cdfci_ctx* ctx);
+const char* cdfci_strerror(int code);
+const char* cdfci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDFCI_H */

@@ -1,0 +1,205 @@
+"""Thin Python binding of include/cdfci.h.  Argument marshalling only: every
+step of the solver runs in the HIP library; PyTorch supplies device memory (the
+hash-table workspace) and the stream."""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import cdfci_opts, cdfci_stats
+
+
+class CDFCIError(RuntimeError):
+    def __init__(self, code, where):
+        L = _lib.load()
+        msg = L.cdfci_strerror(code).decode()
+        last = L.cdfci_last_error().decode()
+        super().__init__(f"{where}: {msg} ({code})" + (f" [{last}]" if last else ""))
+        self.code = code
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise CDFCIError(rc, where)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def make_opts(table_slots=1 << 22, load_factor=0.79, z_threshold=0.0, dx_damping=0.9,
+              dx_threshold=0.0, init_kind=0, grid_blocks=0, block_threads=256, workspace=None,
+              stream=None):
+    o = cdfci_opts()
+    o.table_slots = int(table_slots)
+    o.load_factor = float(load_factor)
+    o.z_threshold = float(z_threshold)
+    o.dx_damping = float(dx_damping)
+    o.dx_threshold = float(dx_threshold)
+    o.init_kind = int(init_kind)
+    o.grid_blocks = int(grid_blocks)
+    o.block_threads = int(block_threads)
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(int(workspace.data_ptr()))
+        o.workspace_bytes = int(workspace.numel() * workspace.element_size())
+    if stream is not None:
+        o.stream = ctypes.c_void_p(int(stream))
+    return o
+
+
+def cdfci_workspace_size(n_orb, n_alpha, n_beta, opts):
+    n = ctypes.c_size_t(0)
+    _check(_lib.load().cdfci_workspace_size(n_orb, n_alpha, n_beta, ctypes.byref(opts),
+                                            ctypes.byref(n)), "cdfci_workspace_size")
+    return n.value
+
+
+def _torch_workspace(n_orb, n_alpha, n_beta, opts):
+    """Allocate the table workspace with torch and bind torch's current stream."""
+    import torch
+
+    nbytes = cdfci_workspace_size(n_orb, n_alpha, n_beta, opts)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    opts.workspace = ctypes.c_void_p(int(ws.data_ptr()))
+    opts.workspace_bytes = nbytes
+    if not opts.stream:
+        opts.stream = ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+    return ws
+
+
+class Context:
+    """Owns a cdfci_ctx (and the torch workspace that backs its table)."""
+
+    def __init__(self, handle, workspace, N, na, nb):
+        self.handle = handle
+        self.workspace = workspace
+        self.N, self.na, self.nb = N, na, nb
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle:
+            _lib.load().cdfci_free(self.handle)
+            self.handle = None
+            self.workspace = None
+
+
+def cdfci_init(h, eri, n_alpha, n_beta, use_torch_workspace=True, **kw):
+    L = _lib.load()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    N = h.shape[0]
+    assert h.shape == (N, N) and eri.shape == (N, N, N, N)
+    opts = make_opts(**kw)
+    ws = _torch_workspace(N, n_alpha, n_beta, opts) if use_torch_workspace else None
+    ctx = ctypes.c_void_p()
+    _check(L.cdfci_init(_dp(h), _dp(eri), N, n_alpha, n_beta, ctypes.byref(opts), ctypes.byref(ctx)),
+           "cdfci_init")
+    return Context(ctx, ws, N, n_alpha, n_beta)
+
+
+def cdfci_init_hubbard(dims, t, U, n_alpha, n_beta, use_torch_workspace=True, **kw):
+    L = _lib.load()
+    d = (ctypes.c_int * len(dims))(*[int(x) for x in dims])
+    N = int(np.prod(dims))
+    opts = make_opts(**kw)
+    ws = _torch_workspace(N, n_alpha, n_beta, opts) if use_torch_workspace else None
+    ctx = ctypes.c_void_p()
+    _check(L.cdfci_init_hubbard(d, len(dims), float(t), float(U), n_alpha, n_beta,
+                                ctypes.byref(opts), ctypes.byref(ctx)), "cdfci_init_hubbard")
+    return Context(ctx, ws, N, n_alpha, n_beta)
+
+
+def cdfci_step(ctx, k=1, nsteps=1):
+    st = cdfci_stats()
+    _check(_lib.load().cdfci_step(ctx.handle, int(k), int(nsteps), ctypes.byref(st)), "cdfci_step")
+    return st.as_dict()
+
+
+def cdfci_step_trace(ctx, nsteps):
+    E = np.zeros(nsteps)
+    a = np.zeros(nsteps, np.uint64)
+    b = np.zeros(nsteps, np.uint64)
+    eta = np.zeros(nsteps)
+    st = cdfci_stats()
+    _check(_lib.load().cdfci_step_trace(ctx.handle, int(nsteps), _dp(E), _up(a), _up(b), _dp(eta),
+                                        ctypes.byref(st)), "cdfci_step_trace")
+    n = st.steps
+    return {"energy": E[:n], "sel_alpha": a[:n], "sel_beta": b[:n], "eta": eta[:n],
+            "stats": st.as_dict()}
+
+
+def cdfci_energy(ctx, exact=0):
+    e = ctypes.c_double(0.0)
+    _check(_lib.load().cdfci_energy(ctx.handle, int(exact), ctypes.byref(e)), "cdfci_energy")
+    return e.value
+
+
+def cdfci_rdm_backward(ctx, grad_E=1.0, top_n=0, want_eri=True):
+    N = ctx.N
+    dh = np.zeros((N, N))
+    deri = np.zeros((N, N, N, N)) if want_eri else None
+    kap = np.zeros((N, N))
+    _check(_lib.load().cdfci_rdm_backward(ctx.handle, float(grad_E), int(top_n), _dp(dh),
+                                          _dp(deri) if deri is not None else None, _dp(kap)),
+           "cdfci_rdm_backward")
+    return dh, deri, kap
+
+
+def cdfci_column(ctx, key):
+    L = _lib.load()
+    k = np.array([int(key[0]), int(key[1])], dtype=np.uint64)
+    cnt = ctypes.c_int64(0)
+    rc = L.cdfci_column(ctx.handle, _up(k), None, None, 0, ctypes.byref(cnt))
+    n = cnt.value
+    if n <= 0:
+        _check(rc, "cdfci_column")
+    keys = np.zeros(2 * n, np.uint64)
+    vals = np.zeros(n)
+    _check(L.cdfci_column(ctx.handle, _up(k), _up(keys), _dp(vals), n, ctypes.byref(cnt)),
+           "cdfci_column")
+    return keys[0::2].copy(), keys[1::2].copy(), vals
+
+
+def cdfci_entry(ctx, bra, ket):
+    k1 = np.array([int(bra[0]), int(bra[1])], dtype=np.uint64)
+    k2 = np.array([int(ket[0]), int(ket[1])], dtype=np.uint64)
+    v = ctypes.c_double(0.0)
+    _check(_lib.load().cdfci_entry(ctx.handle, _up(k1), _up(k2), ctypes.byref(v)), "cdfci_entry")
+    return v.value
+
+
+def cdfci_export(ctx, top_n=0):
+    L = _lib.load()
+    cnt = ctypes.c_int64(0)
+    _check(L.cdfci_export(ctx.handle, int(top_n), None, None, None, 0, ctypes.byref(cnt)),
+           "cdfci_export")
+    n = cnt.value
+    keys = np.zeros(2 * max(n, 1), np.uint64)
+    c = np.zeros(max(n, 1))
+    b = np.zeros(max(n, 1))
+    _check(L.cdfci_export(ctx.handle, int(top_n), _up(keys), _dp(c), _dp(b), n, ctypes.byref(cnt)),
+           "cdfci_export")
+    return keys[0:2 * n:2].copy(), keys[1:2 * n:2].copy(), c[:n], b[:n]
+
+
+def cdfci_phase_times(ctx):
+    t = np.zeros(4)
+    _check(_lib.load().cdfci_phase_times(ctx.handle, _dp(t)), "cdfci_phase_times")
+    return {"step": t[0], "scatter": t[1], "barrier": t[2], "combine": t[3]}
+
+
+def cdfci_free(ctx):
+    ctx.close()
+
+
+def cdfci_strerror(code):
+    return _lib.load().cdfci_strerror(int(code)).decode()

@@ -1,0 +1,1360 @@
+// Coordinate-descent FCI on MI355X: kernels and the C ABI (include/cdfci.h).
+//
+// Hot path of one single-coordinate iteration (paper Sec. 3.1, Algorithm 1),
+// executed by a persistent cooperative kernel with one device-wide barrier
+// per iteration:
+//   A  every workgroup redundantly: lists of the chosen determinant D, H_DD,
+//      exact line search (Appendix A), mu/alpha update in double-double;
+//      workgroup 0 stores c_D + eta;
+//   B  all lanes over the column of D (singles and doubles, Sec. 4.3): key,
+//      Slater-Condon entry, hash probe (insert under the compression rule),
+//      FP64 atomic b_j += eta H_jD, gather of c_j for the recalculation of b_D,
+//      gradient |4 b_j + 4 mu c_j| of the touched entry and a workgroup
+//      argmax (ties: smaller (beta, alpha) key);
+//   -- device-wide barrier --
+//   C  every workgroup redundantly: combine the per-workgroup argmax and the
+//      recalculation sum, giving b_D (Sec. 3.1 eq. (recalculate-b)) and the
+//      next coordinate; workgroup 0 applies b_D's correction atomically.
+// The next iteration's candidates are exactly the column just scattered plus
+// D itself (Alg. 1: argmax over I_H(i)), so selection fuses into the scatter.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cdfci.h"
+#include "device.h"
+
+using namespace cdfci;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(_e);                 \
+      return CDFCI_ERR_HIP;                                                             \
+    }                                                                                   \
+  } while (0)
+
+// Control block in device memory: the solver's scalar state between launches.
+struct Ctl {
+  double mu_hi, mu_lo, al_hi, al_lo;  // mu = c.c, alpha = c.Hc (double-double)
+  double d;                           // damped step accumulator
+  double energy;
+  uint64_t sel_a, sel_b;              // next coordinate to update
+  int64_t sel_slot;
+  double sel_c, sel_b_val;            // its c and b (b includes every correction)
+  int64_t steps;                      // iterations since init
+  unsigned long long occupied;        // stored determinants
+  unsigned long long inserts;
+  int error;
+  int stopped;
+  int max_probe;
+  unsigned barrier;                   // device-wide barrier arrival counter
+  int64_t steps_this_call;
+  // wall-clock ticks spent by workgroup 0 per phase (A, B, barrier wait, C)
+  unsigned long long t_phase[4];
+};
+
+// Per-workgroup result of phase B (one per workgroup and iteration parity).
+struct alignas(64) Partial {
+  double g;
+  uint64_t a, b;
+  int64_t slot;
+  double bnew, c;
+  double recalc;
+  int64_t info;  // inserts << 8 | error bits of the workgroup
+};
+
+struct Cand {
+  double g;
+  uint64_t a, b;
+  int64_t slot;
+  double bnew, c;
+};
+
+__device__ __forceinline__ bool better(const Cand& x, const Cand& y) {
+  if (x.g != y.g) return x.g > y.g;
+  return key_less(x.a, x.b, y.a, y.b);
+}
+
+__device__ __forceinline__ Cand shfl_cand(const Cand& c, int src) {
+  Cand o;
+  o.g = __shfl(c.g, src);
+  o.a = __shfl(c.a, src);
+  o.b = __shfl(c.b, src);
+  o.slot = __shfl(c.slot, src);
+  o.bnew = __shfl(c.bnew, src);
+  o.c = __shfl(c.c, src);
+  return o;
+}
+
+// Deterministic workgroup argmax + sum (identical result in every workgroup for
+// identical inputs).  Uses shared scratch of blockDim/64 entries.
+template <int MAXW>
+__device__ void block_reduce(Cand& best, double& sum, Cand* s_cand, double* s_sum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    Cand o = shfl_cand(best, lane ^ off);
+    double so = __shfl_xor(sum, off);
+    // `better` is a strict total order on (g, key), so both partners keep the
+    // same winner; the sum is formed lower-lane-first on both sides
+    const bool take = better(o, best);
+    best.g = take ? o.g : best.g;
+    best.a = take ? o.a : best.a;
+    best.b = take ? o.b : best.b;
+    best.slot = take ? o.slot : best.slot;
+    best.bnew = take ? o.bnew : best.bnew;
+    best.c = take ? o.c : best.c;
+    sum = (lane & off) ? (so + sum) : (sum + so);
+  }
+  if (lane == 0) {
+    s_cand[w] = best;
+    s_sum[w] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Cand b = s_cand[0];
+    double s = s_sum[0];
+    for (int i = 1; i < nw; ++i) {
+      if (better(s_cand[i], b)) b = s_cand[i];
+      s += s_sum[i];
+    }
+    s_cand[0] = b;
+    s_sum[0] = s;
+  }
+  __syncthreads();
+  best = s_cand[0];
+  sum = s_sum[0];
+  __syncthreads();
+}
+
+// Device-wide barrier with a spin bound; returns false on timeout.
+// Every access to data shared between workgroups inside the persistent kernel
+// is an agent-scope atomic (serviced at the coherence point), so the barrier
+// only has to order them: each wave drains its outstanding memory operations
+// (s_waitcnt) before the workgroup arrives, and nothing is read before the
+// arrival count is seen.  No L2 write-back or invalidate is issued.
+__device__ bool grid_barrier(unsigned* counter, unsigned target) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1 << 27)) {
+        ok = 0;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__device__ __forceinline__ void partial_store(Partial* p, const Cand& c, double recalc) {
+  st_co(&p->g, c.g);
+  st_co(&p->a, c.a);
+  st_co(&p->b, c.b);
+  st_co(&p->slot, c.slot);
+  st_co(&p->bnew, c.bnew);
+  st_co(&p->c, c.c);
+  st_co(&p->recalc, recalc);
+}
+__device__ __forceinline__ Cand partial_load(const Partial* p, double* recalc) {
+  Cand c;
+  c.g = ld_co(&p->g);
+  c.a = ld_co(&p->a);
+  c.b = ld_co(&p->b);
+  c.slot = ld_co(&p->slot);
+  c.bnew = ld_co(&p->bnew);
+  c.c = ld_co(&p->c);
+  *recalc = ld_co(&p->recalc);
+  return c;
+}
+
+constexpr int kMaxWaves = 4;  // workgroups of at most 256 threads
+
+// ---------------------------------------------------------------------------
+// Persistent single-coordinate kernel.
+
+struct Cd1Args {
+  Ham H;
+  Slot* T;
+  uint64_t mask;
+  uint64_t max_entries;
+  Ctl* ctl;
+  Partial* parts;  // 2 * gridDim.x
+  int64_t nsteps;
+  int64_t n_col;   // entries per column (diagonal included)
+  double tau, theta, dx_tol;
+  double* tr_E;
+  uint64_t* tr_a;
+  uint64_t* tr_b;
+  double* tr_eta;
+};
+
+__global__ void __launch_bounds__(256) k_cd1(Cd1Args A) {
+  __shared__ Lists L;
+  __shared__ Cand s_cand[kMaxWaves];
+  __shared__ double s_sum[kMaxWaves];
+  __shared__ double s_bc[8];
+  __shared__ unsigned long long s_info, s_ins_sum;
+  __shared__ int s_flags;
+
+  const Ham H = A.H;
+  Ctl* ctl = A.ctl;
+  const int G = gridDim.x;
+  const int tid = threadIdx.x;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int64_t gsz = (int64_t)G * blockDim.x;
+
+  // scalar state, identical in every workgroup
+  dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
+  double d = ctl->d;
+  uint64_t sa = ctl->sel_a, sb = ctl->sel_b;
+  int64_t sslot = ctl->sel_slot;
+  double sc = ctl->sel_c, sbv = ctl->sel_b_val;
+  const int64_t step0 = ctl->steps;
+  unsigned long long occupied = ctl->occupied, inserts = 0;
+  uint64_t pa = kEmpty, pb = kEmpty;  // previous coordinate (pending correction)
+  double pR = 0.0;
+  unsigned target = 0;  // the arrival counter is zeroed before every launch
+  int64_t step = 0;
+  int stopped = 0, flags = 0;
+  int my_probe = 0;
+
+  // phase timers of workgroup 0 (wall-clock ticks)
+  unsigned long long tp0 = 0, tp1 = 0, tp2 = 0, tp3 = 0, t_last = wall_clock64();
+#define CDFCI_TICK(acc)                          \
+  if (blockIdx.x == 0 && tid == 0) {             \
+    unsigned long long t_now = wall_clock64();   \
+    acc += t_now - t_last;                       \
+    t_last = t_now;                              \
+  }
+  for (; step < A.nsteps; ++step) {
+    // ---- phase A: lists of D, then (overlapped) this lane's first column
+    // entry and its probe, H_DD and the line search
+    make_lists_block(sa, sb, H.N, L);
+    __syncthreads();
+    const int64_t e0 = 1 + gtid;
+    uint64_t ja0 = 0, jb0 = 0;
+    double H0 = 0.0;
+    SlotVal sv0{0, 0, 0.0, 0.0};
+    int64_t slot0 = -1;
+    int probes0 = 0;
+    if (e0 < A.n_col) {
+      H0 = column_entry(H, L, sa, sb, e0, 0.0, &ja0, &jb0);
+      slot0 = table_find(A.T, A.mask, ja0, jb0, &probes0, &sv0);
+    }
+    {
+      double part = 0.0;
+      const int nt = diag_terms(L);
+      for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+      Cand dummy{0.0, 0, 0, 0, 0.0, 0.0};
+      block_reduce<kMaxWaves>(dummy, part, s_cand, s_sum);
+      if (tid == 0) {
+        const double Hii = part;
+        const double mud = dd_val(mu);
+        const double eta = line_search(4.0 * sbv + 4.0 * mud * sc,
+                                       2.0 * Hii + 4.0 * sc * sc + 2.0 * mud, 4.0 * sc);
+        // mu += 2 eta c_i + eta^2 ; alpha += 2 eta b_i + eta^2 H_ii (pre-step c_i, b_i)
+        dd e2 = two_prod(eta, eta);
+        dd mu_n = dd_add(dd_add(mu, two_prod(2.0 * eta, sc)), e2);
+        dd al_n = dd_add(dd_add(al, two_prod(2.0 * eta, sbv)), dd_mul_d(e2, Hii));
+        s_bc[0] = eta;
+        s_bc[1] = Hii;
+        s_bc[2] = mu_n.hi;
+        s_bc[3] = mu_n.lo;
+        s_bc[4] = al_n.hi;
+        s_bc[5] = al_n.lo;
+        s_info = 0;
+        s_ins_sum = 0;
+        s_flags = 0;
+      }
+    }
+    __syncthreads();
+    const double eta = s_bc[0], Hii = s_bc[1];
+    mu = dd{s_bc[2], s_bc[3]};
+    al = dd{s_bc[4], s_bc[5]};
+    const double mu1 = dd_val(mu);
+    const double cnew = sc + eta;
+    if (blockIdx.x == 0 && tid == 0) st_co(&A.T[sslot].c, cnew);
+
+    CDFCI_TICK(tp0);
+    // ---- phase B: scatter eta * H_{:,D}.  Within one iteration each b_j has a
+    // single writer (the lane that owns entry j), so b_j's new value is the
+    // probed value plus the increment and the atomic need not return; the
+    // previous coordinate, whose correction may still be in flight, uses its
+    // known recalculated value.
+    Cand best{-1.0, kEmpty, kEmpty, -1, 0.0, 0.0};
+    double recalc = 0.0;
+    unsigned my_ins = 0;
+    int err = 0;
+    for (int64_t e = e0; e < A.n_col; e += gsz) {
+      uint64_t ja, jb;
+      double Hj;
+      SlotVal sv;
+      int64_t slot;
+      int probes = 0;
+      if (e == e0) {
+        ja = ja0;
+        jb = jb0;
+        Hj = H0;
+        sv = sv0;
+        slot = slot0;
+        probes = probes0;
+      } else {
+        Hj = column_entry(H, L, sa, sb, e, 0.0, &ja, &jb);
+        slot = table_find(A.T, A.mask, ja, jb, &probes, &sv);
+      }
+      if (Hj == 0.0) continue;
+      const double delta = eta * Hj;
+      double cj = 0.0, bnew = 0.0;
+      const bool is_prev = (ja == pa && jb == pb);
+      if (slot >= 0) {
+        cj = sv.c;
+        bnew = is_prev ? pR : sv.b;
+        if (cj != 0.0 || fabs(delta) >= A.tau) {
+          atomic_add_f64(&A.T[slot].b, delta);
+          bnew += delta;
+        }
+      } else if (fabs(delta) >= A.tau) {
+        int ins = 0;
+        slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
+        if (slot >= 0) {
+          atomic_add_f64(&A.T[slot].b, delta);
+          cj = sv.c;
+          bnew = sv.b + delta;
+          my_ins += ins;
+        }
+      }
+      my_probe = max(my_probe, probes);
+      recalc += Hj * cj;
+      Cand cnd{fabs(4.0 * bnew + 4.0 * mu1 * cj), ja, jb, slot, bnew, cj};
+      if (slot >= 0 && better(cnd, best)) best = cnd;
+    }
+    if (my_ins | err) atomicAdd(&s_info, ((unsigned long long)my_ins << 8) | (unsigned long long)err);
+    block_reduce<kMaxWaves>(best, recalc, s_cand, s_sum);
+    Partial* P = A.parts + (step & 1) * G;
+    if (tid == 0) {
+      partial_store(&P[blockIdx.x], best, recalc);
+      st_co(&P[blockIdx.x].info, (int64_t)s_info);
+    }
+    CDFCI_TICK(tp1);
+    target += G;
+    if (!grid_barrier(&ctl->barrier, target)) flags |= kErrBarrier;
+
+    CDFCI_TICK(tp2);
+    // ---- phase C: combine (every workgroup, same order)
+    Cand w{-1.0, kEmpty, kEmpty, -1, 0.0, 0.0};
+    double rs = 0.0;
+    unsigned long long ins_part = 0;  // inserts and error bits over the workgroups
+    int fl_part = 0;
+    for (int i = tid; i < G; i += blockDim.x) {
+      double qr;
+      Cand c = partial_load(&P[i], &qr);
+      if (better(c, w)) w = c;
+      rs += qr;
+      const unsigned long long q = (unsigned long long)ld_co(&P[i].info);
+      ins_part += q >> 8;
+      fl_part |= (int)(q & 0xff);
+    }
+    if (ins_part) atomicAdd(&s_ins_sum, ins_part);
+    if (fl_part) atomicOr(&s_flags, fl_part);
+    block_reduce<kMaxWaves>(w, rs, s_cand, s_sum);
+    const unsigned long long info = s_ins_sum;
+    flags |= s_flags;
+    occupied += info;
+    inserts += info;
+    if (occupied > A.max_entries) flags |= kErrTableFull;
+    const double R = Hii * cnew + rs;
+    Cand self{fabs(4.0 * R + 4.0 * mu1 * cnew), sa, sb, sslot, R, cnew};
+    if (better(self, w)) w = self;
+    if (blockIdx.x == 0 && tid == 0) {
+      atomic_add_f64(&A.T[sslot].b, R - sbv);
+      if (A.tr_E) A.tr_E[step0 + step] = dd_val(al) / mu1;
+      if (A.tr_a) A.tr_a[step0 + step] = sa;
+      if (A.tr_b) A.tr_b[step0 + step] = sb;
+      if (A.tr_eta) A.tr_eta[step0 + step] = eta;
+    }
+    d = (step0 + step == 0) ? fabs(eta) : A.theta * d + (1.0 - A.theta) * fabs(eta);
+    pa = sa;
+    pb = sb;
+    pR = R;
+    sa = w.a;
+    sb = w.b;
+    sslot = w.slot;
+    sc = w.c;
+    sbv = w.bnew;
+    CDFCI_TICK(tp3);
+    if (flags) {
+      ++step;
+      break;
+    }
+    if (d < A.dx_tol) {
+      stopped = 1;
+      ++step;
+      break;
+    }
+  }
+#undef CDFCI_TICK
+  // statistics and state write-back
+  __shared__ int s_probe;
+  if (tid == 0) s_probe = 0;
+  __syncthreads();
+  atomicMax(&s_probe, my_probe);
+  __syncthreads();
+  if (tid == 0) atomicMax(&ctl->max_probe, s_probe);
+  if (blockIdx.x == 0 && tid == 0) {
+    if (flags) atomicOr(&ctl->error, flags);
+    ctl->inserts += inserts;
+    ctl->occupied = occupied;
+    ctl->mu_hi = mu.hi;
+    ctl->mu_lo = mu.lo;
+    ctl->al_hi = al.hi;
+    ctl->al_lo = al.lo;
+    ctl->d = d;
+    ctl->energy = dd_val(al) / dd_val(mu);
+    ctl->sel_a = sa;
+    ctl->sel_b = sb;
+    ctl->sel_slot = sslot;
+    ctl->sel_c = sc;
+    ctl->sel_b_val = sbv;
+    ctl->steps_this_call = step;
+    ctl->stopped = stopped;
+    ctl->t_phase[0] += tp0;
+    ctl->t_phase[1] += tp1;
+    ctl->t_phase[2] += tp2;
+    ctl->t_phase[3] += tp3;
+  }
+}
+
+// Adds the step count after the persistent kernel (one thread).
+__global__ void k_finish_steps(Ctl* ctl) {
+  ctl->steps += ctl->steps_this_call;
+  ctl->barrier = 0;
+}
+
+__global__ void k_reset_barrier(Ctl* ctl) {
+  ctl->barrier = 0;
+  ctl->steps_this_call = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Coulomb/exchange rows for single excitations: jk[((r*N+p)*N+k)*2] = (rp|kk),
+// jk[((r*N+p)*N+k)*2+1] = (rk|kp).
+
+__global__ void __launch_bounds__(256) k_build_jk(const double* eri, int N, double* jk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)N * N * N;
+  if (i >= n) return;
+  const int k = (int)(i % N), p = (int)((i / N) % N), r = (int)(i / ((int64_t)N * N));
+  const size_t N1 = N;
+  jk[2 * i] = eri[((r * N1 + p) * N1 + k) * N1 + k];
+  jk[2 * i + 1] = eri[((r * N1 + k) * N1 + k) * N1 + p];
+}
+
+// ---------------------------------------------------------------------------
+// Table maintenance.
+
+__global__ void __launch_bounds__(256) k_clear_table(Slot* T, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    T[i] = Slot{kEmpty, kPending, 0.0, 0.0};
+  }
+}
+
+__global__ void k_zero_ctl(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    uint64_t* w = reinterpret_cast<uint64_t*>(ctl);
+    for (size_t i = 0; i < sizeof(Ctl) / 8; ++i) w[i] = 0;
+    ctl->sel_slot = -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial vector: dets[0..n) with coefficients coef[0..n) are stored, then
+// b = H c is scattered exactly (no compression), column by column.
+
+struct InitTask {
+  uint64_t a, b;
+  double coef;
+};
+
+__global__ void k_init_insert(Slot* T, uint64_t mask, const InitTask* tasks, int n, Ctl* ctl) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int ins = 0, probes = 0, err = 0;
+  SlotVal v0;
+  int64_t s = table_upsert(T, mask, tasks[i].a, tasks[i].b, &ins, &probes, &err, &v0);
+  if (s < 0) {
+    atomicOr(&ctl->error, err ? err : kErrTableFull);
+    return;
+  }
+  atomic_add_f64(&T[s].c, tasks[i].coef);
+  if (ins) {
+    atomicAdd(&ctl->occupied, 1ull);
+    atomicAdd(&ctl->inserts, 1ull);
+  }
+}
+
+// grid: (chunks, n tasks)
+__global__ void __launch_bounds__(256) k_init_scatter(Ham H, Slot* T, uint64_t mask, const InitTask* tasks, int64_t n_col,
+                               Ctl* ctl) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  const InitTask t = tasks[blockIdx.y];
+  if (threadIdx.x == 0) {
+    make_lists_serial(t.a, t.b, H.N, L);
+    s_diag = diag_serial(H, L);
+  }
+  __syncthreads();
+  unsigned long long ins_cnt = 0;
+  int err = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_col;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ja, jb;
+    double Hj = column_entry(H, L, t.a, t.b, e, s_diag, &ja, &jb);
+    if (Hj == 0.0) continue;
+    int ins = 0, probes = 0;
+    SlotVal vj;
+    int64_t s = table_upsert(T, mask, ja, jb, &ins, &probes, &err, &vj);
+    if (s < 0) break;
+    atomic_add_f64(&T[s].b, t.coef * Hj);
+    ins_cnt += ins;
+  }
+  if (err) atomicOr(&ctl->error, err);
+  if (ins_cnt) {
+    atomicAdd(&ctl->occupied, ins_cnt);
+    atomicAdd(&ctl->inserts, ins_cnt);
+  }
+}
+
+// mu = sum c^2, alpha = sum c b over the initial support (one workgroup,
+// fixed order), then the first coordinate = argmax over all stored entries.
+__global__ void k_init_scalars(const Slot* T, uint64_t mask, const InitTask* tasks, int n, Ctl* ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  dd mu{0, 0}, al{0, 0};
+  for (int i = 0; i < n; ++i) {
+    int probes;
+    SlotVal v;
+    int64_t s = table_find(T, mask, tasks[i].a, tasks[i].b, &probes, &v);
+    if (s < 0) continue;
+    double c = v.c, b = v.b;
+    mu = dd_add(mu, two_prod(c, c));
+    al = dd_add(al, two_prod(c, b));
+  }
+  ctl->mu_hi = mu.hi;
+  ctl->mu_lo = mu.lo;
+  ctl->al_hi = al.hi;
+  ctl->al_lo = al.lo;
+  ctl->energy = dd_val(al) / dd_val(mu);
+}
+
+// argmax of |4b + 4 mu c| over every stored entry (used once after init)
+__global__ void __launch_bounds__(256) k_select_table(const Slot* T, uint64_t nslots, Ctl* ctl, Partial* parts) {
+  __shared__ Cand s_cand[kMaxWaves];
+  __shared__ double s_sum[kMaxWaves];
+  const double mu = ctl->mu_hi + ctl->mu_lo;
+  Cand best{-1.0, kEmpty, kEmpty, -1, 0.0, 0.0};
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    Slot s = T[i];
+    if (s.ka == kEmpty) continue;
+    Cand c{fabs(4.0 * s.b + 4.0 * mu * s.c), s.ka, s.kb, (int64_t)i, s.b, s.c};
+    if (better(c, best)) best = c;
+  }
+  double dummy = 0.0;
+  block_reduce<kMaxWaves>(best, dummy, s_cand, s_sum);
+  if (threadIdx.x == 0)
+    parts[blockIdx.x] = Partial{best.g, best.a, best.b, best.slot, best.bnew, best.c, 0.0, 0};
+}
+
+__global__ void k_select_final(const Partial* parts, int n, Ctl* ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Cand w{-1.0, kEmpty, kEmpty, -1, 0.0, 0.0};
+  for (int i = 0; i < n; ++i) {
+    Cand c{parts[i].g, parts[i].a, parts[i].b, parts[i].slot, parts[i].bnew, parts[i].c};
+    if (better(c, w)) w = c;
+  }
+  ctl->sel_a = w.a;
+  ctl->sel_b = w.b;
+  ctl->sel_slot = w.slot;
+  ctl->sel_c = w.c;
+  ctl->sel_b_val = w.bnew;
+}
+
+// ---------------------------------------------------------------------------
+// Subspace initial vector (lattice models): D0 plus the nonzero entries of its
+// column; H on that set; lowest eigenpair by cyclic Jacobi (one thread).
+
+constexpr int kMaxSub = 128;
+
+__global__ void k_subspace_init(Ham H, uint64_t a0, uint64_t b0, int64_t n_col, InitTask* out,
+                                int* n_out, double* work /* kMaxSub^2 * 2 */, int* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Lists L;
+  make_lists_serial(a0, b0, H.N, L);
+  double d0 = diag_serial(H, L);
+  int n = 0;
+  out[n++] = InitTask{a0, b0, 0.0};
+  for (int64_t e = 1; e < n_col; ++e) {
+    uint64_t ja, jb;
+    double v = column_entry(H, L, a0, b0, e, d0, &ja, &jb);
+    if (v == 0.0) continue;
+    if (n >= kMaxSub) {
+      *status = -2;
+      return;
+    }
+    out[n++] = InitTask{ja, jb, 0.0};
+  }
+  double* A = work;
+  double* V = work + kMaxSub * kMaxSub;
+  for (int j = 0; j < n; ++j) {
+    Lists Lj;
+    make_lists_serial(out[j].a, out[j].b, H.N, Lj);
+    double dj = diag_serial(H, Lj);
+    for (int i = 0; i < n; ++i) A[i * n + j] = sc_entry(H, out[i].a, out[i].b, out[j].a, out[j].b, Lj, dj);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  // cyclic Jacobi sweeps (Golub & Van Loan, symmetric Schur rotations)
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int m = 0;
+  for (int i = 1; i < n; ++i)
+    if (A[i * n + i] < A[m * n + m]) m = i;
+  double lam = A[m * n + m];
+  if (!(lam < 0.0)) {
+    *status = -4;
+    return;
+  }
+  double sgn = V[0 * n + m] < 0.0 ? -1.0 : 1.0;
+  double scale = sqrt(-lam) * sgn;
+  for (int i = 0; i < n; ++i) out[i].coef = scale * V[i * n + m];
+  *n_out = n;
+  *status = 0;
+}
+
+// Aufbau determinant on the device: the n lowest h_pp (ties: lower index).
+__global__ void k_aufbau_init(Ham H, InitTask* out, int* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t used = 0, a = 0, b = 0;
+  for (int k = 0; k < max(H.na, H.nb); ++k) {
+    int best = -1;
+    for (int p = 0; p < H.N; ++p) {
+      if ((used >> p) & 1) continue;
+      if (best < 0 || H.h[p * H.N + p] < H.h[best * H.N + best]) best = p;
+    }
+    used |= 1ull << best;
+    if (k < H.na) a |= 1ull << best;
+    if (k < H.nb) b |= 1ull << best;
+  }
+  Lists L;
+  make_lists_serial(a, b, H.N, L);
+  double d0 = diag_serial(H, L);
+  if (!(d0 < 0.0)) {
+    *status = -4;
+    return;
+  }
+  out[0] = InitTask{a, b, sqrt(-d0)};
+  *status = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Inspection kernels.
+
+__global__ void __launch_bounds__(256) k_column(Ham H, uint64_t a, uint64_t b, int64_t n_col, uint64_t* keys, double* vals) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  if (threadIdx.x == 0) {
+    make_lists_serial(a, b, H.N, L);
+    s_diag = diag_serial(H, L);
+  }
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_col;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ja, jb;
+    double v = column_entry(H, L, a, b, e, s_diag, &ja, &jb);
+    keys[2 * e] = ja;
+    keys[2 * e + 1] = jb;
+    vals[e] = v;
+  }
+}
+
+__global__ void k_entry(Ham H, uint64_t a1, uint64_t b1, uint64_t a2, uint64_t b2, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Lists L;
+  make_lists_serial(a2, b2, H.N, L);
+  double d = diag_serial(H, L);
+  *out = sc_entry(H, a1, b1, a2, b2, L, d);
+}
+
+// compact occupied slots (c != 0 if nonzero_c) into a list of slot ids
+__global__ void __launch_bounds__(256) k_compact(const Slot* T, uint64_t nslots, int nonzero_c, int64_t* list,
+                          unsigned long long* count, int64_t cap) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    Slot s = T[i];
+    if (s.ka == kEmpty) continue;
+    if (nonzero_c && s.c == 0.0) continue;
+    unsigned long long k = atomicAdd(count, 1ull);
+    if ((int64_t)k < cap) list[k] = (int64_t)i;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gather(const Slot* T, const int64_t* list, int64_t n, uint64_t* keys, double* c,
+                         double* b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    Slot s = T[list[i]];
+    keys[2 * i] = s.ka;
+    keys[2 * i + 1] = s.kb;
+    c[i] = s.c;
+    b[i] = s.b;
+  }
+}
+
+// c^T H c over the support: each workgroup takes support determinants in turn
+// and sums c_i H_ji c_j over the column of i; per-workgroup partial sums.
+__global__ void __launch_bounds__(256) k_apply_energy(Ham H, const Slot* T, uint64_t mask, const int64_t* list, int64_t n,
+                               int64_t n_col, double* partial_num, double* partial_den) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  __shared__ Cand s_cand[kMaxWaves];
+  __shared__ double s_sum[kMaxWaves];
+  double num = 0.0, den = 0.0;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    Slot si = T[list[i]];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      make_lists_serial(si.ka, si.kb, H.N, L);
+      s_diag = diag_serial(H, L);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) den += si.c * si.c;
+    for (int64_t e = threadIdx.x; e < n_col; e += blockDim.x) {
+      uint64_t ja, jb;
+      double v = column_entry(H, L, si.ka, si.kb, e, s_diag, &ja, &jb);
+      if (v == 0.0) continue;
+      int probes;
+      SlotVal sv;
+      int64_t s = table_find(T, mask, ja, jb, &probes, &sv);
+      if (s < 0) continue;
+      num += si.c * v * sv.c;
+    }
+  }
+  Cand dummy{0, 0, 0, 0, 0, 0};
+  block_reduce<kMaxWaves>(dummy, num, s_cand, s_sum);
+  block_reduce<kMaxWaves>(dummy, den, s_cand, s_sum);
+  if (threadIdx.x == 0) {
+    partial_num[blockIdx.x] = num;
+    partial_den[blockIdx.x] = den;
+  }
+}
+
+__global__ void k_sum_partials(const double* num, const double* den, int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  dd a{0, 0}, b{0, 0};
+  for (int i = 0; i < n; ++i) {
+    a = dd_add(a, dd{num[i], 0.0});
+    b = dd_add(b, dd{den[i], 0.0});
+  }
+  out[0] = dd_val(a);
+  out[1] = dd_val(b);
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side.
+
+struct cdfci_ctx {
+  int N, na, nb;
+  int device;
+  hipStream_t stream;
+  double* d_h = nullptr;
+  double* d_eri = nullptr;
+  double* d_jk = nullptr;
+  Slot* T = nullptr;
+  uint64_t nslots = 0, mask = 0, max_entries = 0;
+  bool own_table = false;
+  Ctl* ctl = nullptr;
+  Partial* parts = nullptr;
+  int max_parts = 0;
+  int64_t n_col = 0;
+  cdfci_opts opts;
+  int grid = 0, block = 256;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool poisoned = false;
+  // scratch for inspection/energy calls
+  int64_t* list = nullptr;
+  int64_t list_cap = 0;
+  double* dscratch = nullptr;  // 2 * 2048 partials + 2
+};
+
+namespace {
+
+Ham ham_of(const cdfci_ctx* c) { return Ham{c->N, c->na, c->nb, c->d_h, c->d_eri, c->d_jk}; }
+
+int ctl_read(cdfci_ctx* c, Ctl* host) {
+  HIP_TRY(hipMemcpyAsync(host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int check_error(cdfci_ctx* c, const Ctl& h) {
+  if (h.error & kErrTableFull) {
+    c->poisoned = true;
+    return CDFCI_ERR_TABLE_FULL;
+  }
+  if (h.error & kErrBarrier) {
+    c->poisoned = true;
+    return CDFCI_ERR_BARRIER;
+  }
+  if (h.error & kErrPublish) {
+    c->poisoned = true;
+    return CDFCI_ERR_HIP;
+  }
+  if (h.occupied > c->max_entries) {
+    c->poisoned = true;
+    return CDFCI_ERR_TABLE_FULL;
+  }
+  return 0;
+}
+
+void fill_defaults(cdfci_opts& o) {
+  if (o.table_slots == 0) o.table_slots = 1ull << 22;
+  if (o.load_factor <= 0.0) o.load_factor = 0.79;
+  if (o.dx_damping <= 0.0) o.dx_damping = 0.9;
+  if (o.block_threads <= 0) o.block_threads = 256;
+}
+
+int ensure_list(cdfci_ctx* c, int64_t n) {
+  if (c->list_cap >= n) return 0;
+  if (c->list) HIP_TRY(hipFree(c->list));
+  c->list = nullptr;
+  int64_t cap = std::max<int64_t>(n, 1024);
+  HIP_TRY(hipMalloc(&c->list, cap * sizeof(int64_t)));
+  c->list_cap = cap;
+  return 0;
+}
+
+// common setup after integrals are on the device
+int setup_and_init(cdfci_ctx* c, int init_kind, uint64_t neel_a, uint64_t neel_b) {
+  const cdfci_opts& o = c->opts;
+  c->nslots = o.table_slots;
+  c->mask = c->nslots - 1;
+  c->max_entries = (uint64_t)(o.load_factor * (double)c->nslots);
+  size_t tbytes = c->nslots * sizeof(Slot);
+  if (o.workspace) {
+    if (o.workspace_bytes < tbytes || ((uintptr_t)o.workspace & 255)) return CDFCI_ERR_WORKSPACE;
+    c->T = (Slot*)o.workspace;
+    c->own_table = false;
+  } else {
+    HIP_TRY(hipMalloc(&c->T, tbytes));
+    c->own_table = true;
+  }
+  HIP_TRY(hipMalloc(&c->ctl, sizeof(Ctl)));
+  c->max_parts = 4096;
+  HIP_TRY(hipMalloc(&c->parts, 2 * c->max_parts * sizeof(Partial)));
+  HIP_TRY(hipMalloc(&c->dscratch, (2 * 4096 + 8) * sizeof(double)));
+  HIP_TRY(hipEventCreate(&c->ev0));
+  HIP_TRY(hipEventCreate(&c->ev1));
+  c->n_col = column_count(c->N, c->na, c->nb);
+
+  // persistent grid: enough lanes for one column entry each, bounded by residency
+  int dev_cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cd1, c->block, 0));
+  int max_grid = std::max(1, per_cu) * dev_cus;
+  int want = o.grid_blocks > 0 ? o.grid_blocks
+                               : (int)std::min<int64_t>((c->n_col + c->block - 1) / c->block, dev_cus);
+  c->grid = std::max(1, std::min(want, std::min(max_grid, c->max_parts)));
+
+  hipStream_t s = c->stream;
+  k_zero_ctl<<<1, 1, 0, s>>>(c->ctl);
+  k_clear_table<<<2048, 256, 0, s>>>(c->T, c->nslots);
+  HIP_TRY(hipGetLastError());
+
+  InitTask* d_tasks = nullptr;
+  int* d_stat = nullptr;
+  int* d_n = nullptr;
+  double* d_work = nullptr;
+  HIP_TRY(hipMalloc(&d_tasks, kMaxSub * sizeof(InitTask)));
+  HIP_TRY(hipMalloc(&d_stat, 2 * sizeof(int)));
+  int ntask = 1;
+  int rc = 0;
+  Ham H = ham_of(c);
+  if (init_kind == 2) {
+    HIP_TRY(hipMalloc(&d_work, 2 * kMaxSub * kMaxSub * sizeof(double)));
+    d_n = d_stat + 1;
+    k_subspace_init<<<1, 1, 0, s>>>(H, neel_a, neel_b, c->n_col, d_tasks, d_n, d_work, d_stat);
+  } else {
+    k_aufbau_init<<<1, 1, 0, s>>>(H, d_tasks, d_stat);
+  }
+  HIP_TRY(hipGetLastError());
+  int hstat[2] = {0, 1};
+  HIP_TRY(hipMemcpyAsync(hstat, d_stat, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hstat[0] == -4) rc = CDFCI_ERR_NOT_NEGATIVE;
+  else if (hstat[0] != 0) rc = CDFCI_ERR_UNSUPPORTED;
+  if (init_kind == 2 && rc == 0) ntask = hstat[1];
+  if (rc == 0) {
+    k_init_insert<<<(ntask + 63) / 64, 64, 0, s>>>(c->T, c->mask, d_tasks, ntask, c->ctl);
+    int chunks = (int)std::min<int64_t>((c->n_col + 255) / 256, 1024);
+    k_init_scatter<<<dim3(chunks, ntask), 256, 0, s>>>(H, c->T, c->mask, d_tasks, c->n_col, c->ctl);
+    k_init_scalars<<<1, 1, 0, s>>>(c->T, c->mask, d_tasks, ntask, c->ctl);
+    int sel_blocks = (int)std::min<uint64_t>((c->nslots + 255) / 256, (uint64_t)c->max_parts);
+    k_select_table<<<sel_blocks, 256, 0, s>>>(c->T, c->nslots, c->ctl, c->parts);
+    k_select_final<<<1, 1, 0, s>>>(c->parts, sel_blocks, c->ctl);
+    HIP_TRY(hipGetLastError());
+    Ctl h;
+    int e = ctl_read(c, &h);
+    if (e) rc = e;
+    else rc = check_error(c, h);
+  }
+  (void)hipFree(d_tasks);
+  (void)hipFree(d_stat);
+  if (d_work) (void)hipFree(d_work);
+  return rc;
+}
+
+int make_ctx(int N, int na, int nb, const cdfci_opts* opts, cdfci_ctx** out) {
+  if (!out) return CDFCI_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (N < 1 || N > kMaxOrb || na < 0 || nb < 0 || na > N || nb > N) return CDFCI_ERR_UNSUPPORTED;
+  if (na + nb < 1) return CDFCI_ERR_INVALID_ARG;
+  cdfci_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  fill_defaults(o);
+  if ((o.table_slots & (o.table_slots - 1)) != 0 || o.table_slots < 64) return CDFCI_ERR_INVALID_ARG;
+  if (o.block_threads % 64 != 0 || o.block_threads > 256) return CDFCI_ERR_INVALID_ARG;
+  if (o.load_factor > 0.95) return CDFCI_ERR_INVALID_ARG;
+  cdfci_ctx* c = new cdfci_ctx();
+  c->N = N;
+  c->na = na;
+  c->nb = nb;
+  c->opts = o;
+  c->block = o.block_threads;
+  c->stream = (hipStream_t)o.stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return CDFCI_ERR_HIP;
+  }
+  *out = c;
+  return 0;
+}
+
+int upload(cdfci_ctx* c, const double* h, const double* eri) {
+  size_t N = c->N;
+  HIP_TRY(hipMalloc(&c->d_h, N * N * sizeof(double)));
+  HIP_TRY(hipMalloc(&c->d_eri, N * N * N * N * sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(c->d_h, h, N * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_eri, eri, N * N * N * N * sizeof(double), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMalloc(&c->d_jk, 2 * N * N * N * sizeof(double)));
+  const int64_t njk = (int64_t)N * N * N;
+  k_build_jk<<<(int)((njk + 255) / 256), 256, 0, c->stream>>>(c->d_eri, c->N, c->d_jk);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+std::vector<std::pair<int, int>> lattice_bonds(const int* dims, int ndim) {
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) L *= dims[i];
+  std::vector<std::pair<int, int>> bonds;
+  std::vector<int> coord(ndim);
+  for (int site = 0; site < L; ++site) {
+    int rem = site;
+    for (int ax = ndim - 1; ax >= 0; --ax) {
+      coord[ax] = rem % dims[ax];
+      rem /= dims[ax];
+    }
+    for (int ax = 0; ax < ndim; ++ax) {
+      if (dims[ax] < 2) continue;
+      std::vector<int> nb = coord;
+      nb[ax] = (nb[ax] + 1) % dims[ax];
+      int other = 0;
+      for (int k = 0; k < ndim; ++k) other = other * dims[k] + nb[k];
+      if (other == site) continue;
+      std::pair<int, int> bd(std::min(site, other), std::max(site, other));
+      if (std::find(bonds.begin(), bonds.end(), bd) == bonds.end()) bonds.push_back(bd);
+    }
+  }
+  return bonds;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdfci_workspace_size(int n_orb, int n_alpha, int n_beta, const cdfci_opts* opts, size_t* bytes) {
+  if (!bytes) return CDFCI_ERR_INVALID_ARG;
+  if (n_orb < 1 || n_orb > kMaxOrb || n_alpha > n_orb || n_beta > n_orb) return CDFCI_ERR_UNSUPPORTED;
+  cdfci_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  fill_defaults(o);
+  *bytes = o.table_slots * sizeof(Slot);
+  return 0;
+}
+
+int cdfci_init(const double* h, const double* eri, int n_orb, int n_alpha, int n_beta,
+               const cdfci_opts* opts, cdfci_ctx** out) {
+  if (!h || !eri) return CDFCI_ERR_INVALID_ARG;
+  int rc = make_ctx(n_orb, n_alpha, n_beta, opts, out);
+  if (rc) return rc;
+  cdfci_ctx* c = *out;
+  rc = upload(c, h, eri);
+  int kind = c->opts.init_kind == 2 ? 2 : 1;
+  uint64_t a0 = 0, b0 = 0;
+  if (!rc && kind == 2) {
+    // lowest-index Neel pattern for a chain: alternate sites
+    for (int p = 0, ka = 0; p < n_orb && ka < n_alpha; p += 2, ++ka) a0 |= 1ull << p;
+    for (int p = 1, kb = 0; p < n_orb && kb < n_beta; p += 2, ++kb) b0 |= 1ull << p;
+  }
+  if (!rc) rc = setup_and_init(c, kind, a0, b0);
+  if (rc) {
+    cdfci_free(c);
+    *out = nullptr;
+  }
+  return rc;
+}
+
+int cdfci_init_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                       const cdfci_opts* opts, cdfci_ctx** out) {
+  if (!dims || ndim < 1 || ndim > 3 || !out) return CDFCI_ERR_INVALID_ARG;
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (dims[i] < 1) return CDFCI_ERR_INVALID_ARG;
+    L *= dims[i];
+  }
+  if (L > kMaxOrb) return CDFCI_ERR_UNSUPPORTED;
+  int rc = make_ctx(L, n_alpha, n_beta, opts, out);
+  if (rc) return rc;
+  cdfci_ctx* c = *out;
+  std::vector<double> h((size_t)L * L, 0.0), eri((size_t)L * L * L * L, 0.0);
+  for (auto& bd : lattice_bonds(dims, ndim)) {
+    h[(size_t)bd.first * L + bd.second] = -t;
+    h[(size_t)bd.second * L + bd.first] = -t;
+  }
+  for (int i = 0; i < L; ++i) eri[(((size_t)i * L + i) * L + i) * L + i] = U;
+  rc = upload(c, h.data(), eri.data());
+  // Neel determinant: alpha on the even-coordinate-sum sublattice (then the
+  // rest), beta on the remaining sites (then the alpha sites), ascending.
+  std::vector<int> even, odd;
+  for (int site = 0; site < L; ++site) {
+    int rem = site, sum = 0;
+    for (int ax = ndim - 1; ax >= 0; --ax) {
+      sum += rem % dims[ax];
+      rem /= dims[ax];
+    }
+    (sum % 2 == 0 ? even : odd).push_back(site);
+  }
+  std::vector<int> order = even;
+  order.insert(order.end(), odd.begin(), odd.end());
+  uint64_t a0 = 0, b0 = 0;
+  for (int k = 0; k < n_alpha; ++k) a0 |= 1ull << order[k];
+  std::vector<int> rest;
+  for (int site = 0; site < L; ++site)
+    if (!((a0 >> site) & 1)) rest.push_back(site);
+  for (int site = 0; site < L; ++site)
+    if ((a0 >> site) & 1) rest.push_back(site);
+  for (int k = 0; k < n_beta; ++k) b0 |= 1ull << rest[k];
+  int kind = c->opts.init_kind == 1 ? 1 : 2;
+  if (!rc) rc = setup_and_init(c, kind, a0, b0);
+  if (rc) {
+    cdfci_free(c);
+    *out = nullptr;
+  }
+  return rc;
+}
+
+static int run_cd1(cdfci_ctx* c, int64_t nsteps, double* trE, uint64_t* tra, uint64_t* trb,
+                   double* treta, cdfci_stats* out) {
+  if (!c) return CDFCI_ERR_INVALID_ARG;
+  if (c->poisoned) return CDFCI_ERR_INVALID_ARG;
+  if (nsteps < 0) return CDFCI_ERR_INVALID_ARG;
+  Ctl before;
+  int rc = ctl_read(c, &before);
+  if (rc) return rc;
+  if (before.sel_slot < 0 || (uint64_t)before.sel_slot >= c->nslots) return CDFCI_ERR_INVALID_ARG;
+  double* dE = nullptr;
+  uint64_t *da = nullptr, *db = nullptr;
+  double* deta = nullptr;
+  bool tracing = trE || tra || trb || treta;
+  if (tracing) {
+    // trace arrays are indexed by the global step, so offset by steps so far
+    size_t n = (size_t)(before.steps + nsteps);
+    HIP_TRY(hipMalloc(&dE, n * sizeof(double)));
+    HIP_TRY(hipMalloc(&da, n * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&db, n * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&deta, n * sizeof(double)));
+  }
+  Cd1Args A;
+  A.H = ham_of(c);
+  A.T = c->T;
+  A.mask = c->mask;
+  A.max_entries = c->max_entries;
+  A.ctl = c->ctl;
+  A.parts = c->parts;
+  A.nsteps = nsteps;
+  A.n_col = c->n_col;
+  A.tau = c->opts.z_threshold;
+  A.theta = c->opts.dx_damping;
+  A.dx_tol = c->opts.dx_threshold;
+  A.tr_E = dE;
+  A.tr_a = da;
+  A.tr_b = db;
+  A.tr_eta = deta;
+  hipStream_t s = c->stream;
+  k_reset_barrier<<<1, 1, 0, s>>>(c->ctl);
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  if (nsteps > 0) {
+    void* args[] = {&A};
+    HIP_TRY(hipLaunchCooperativeKernel((const void*)k_cd1, dim3(c->grid), dim3(c->block), args, 0, s));
+  }
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  k_finish_steps<<<1, 1, 0, s>>>(c->ctl);
+  HIP_TRY(hipGetLastError());
+  Ctl h;
+  rc = ctl_read(c, &h);
+  if (rc) return rc;
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (tracing) {
+    int64_t done = h.steps - before.steps;
+    if (trE) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+    if (tra) HIP_TRY(hipMemcpy(tra, da + before.steps, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (trb) HIP_TRY(hipMemcpy(trb, db + before.steps, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (treta) HIP_TRY(hipMemcpy(treta, deta + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+    (void)hipFree(dE);
+    (void)hipFree(da);
+    (void)hipFree(db);
+    (void)hipFree(deta);
+  }
+  if (out) {
+    out->steps = h.steps - before.steps;
+    out->total_steps = h.steps;
+    out->elements = out->steps * c->n_col;
+    out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->occupied = h.occupied;
+    out->max_probe = h.max_probe;
+    out->stopped = h.stopped;
+    out->energy = h.energy;
+    out->dx = h.d;
+    out->mu = h.mu_hi + h.mu_lo;
+    out->alpha = h.al_hi + h.al_lo;
+    out->seconds = ms * 1e-3;
+  }
+  return check_error(c, h);
+}
+
+int cdfci_step(cdfci_ctx* ctx, int k, int64_t nsteps, cdfci_stats* out) {
+  if (!ctx || k < 1) return CDFCI_ERR_INVALID_ARG;
+  if (k == 1) return run_cd1(ctx, nsteps, nullptr, nullptr, nullptr, nullptr, out);
+  return CDFCI_ERR_UNSUPPORTED;
+}
+
+int cdfci_step_trace(cdfci_ctx* ctx, int64_t nsteps, double* energy, uint64_t* sel_alpha,
+                     uint64_t* sel_beta, double* eta, cdfci_stats* out) {
+  return run_cd1(ctx, nsteps, energy, sel_alpha, sel_beta, eta, out);
+}
+
+int cdfci_energy(cdfci_ctx* c, int exact, double* energy) {
+  if (!c || !energy) return CDFCI_ERR_INVALID_ARG;
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  if (!exact) {
+    *energy = (h.al_hi + h.al_lo) / (h.mu_hi + h.mu_lo);
+    return 0;
+  }
+  hipStream_t s = c->stream;
+  unsigned long long* d_cnt = (unsigned long long*)(c->dscratch + 2 * 4096 + 4);
+  HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
+  rc = ensure_list(c, (int64_t)h.occupied + 1);
+  if (rc) return rc;
+  k_compact<<<2048, 256, 0, s>>>(c->T, c->nslots, 1, c->list, d_cnt, c->list_cap);
+  unsigned long long n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, d_cnt, sizeof(n), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((int64_t)n > c->list_cap) return CDFCI_ERR_INVALID_ARG;
+  int nb = 2048;
+  k_apply_energy<<<nb, 256, 0, s>>>(ham_of(c), c->T, c->mask, c->list, (int64_t)n, c->n_col,
+                                    c->dscratch, c->dscratch + 4096);
+  k_sum_partials<<<1, 1, 0, s>>>(c->dscratch, c->dscratch + 4096, nb, c->dscratch + 2 * 4096);
+  HIP_TRY(hipGetLastError());
+  double r[2];
+  HIP_TRY(hipMemcpyAsync(r, c->dscratch + 2 * 4096, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *energy = r[0] / r[1];
+  return 0;
+}
+
+int cdfci_rdm_backward(cdfci_ctx*, double, int64_t, double*, double*, double*) {
+  return CDFCI_ERR_UNSUPPORTED;
+}
+
+int cdfci_column(cdfci_ctx* c, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
+                 int64_t* count) {
+  if (!c || !key || !count) return CDFCI_ERR_INVALID_ARG;
+  if (__builtin_popcountll(key[0]) != c->na || __builtin_popcountll(key[1]) != c->nb ||
+      (c->N < 64 && ((key[0] | key[1]) >> c->N)))
+    return CDFCI_ERR_INVALID_ARG;
+  *count = c->n_col;
+  if (cap < c->n_col || !keys || !vals) return CDFCI_ERR_INVALID_ARG;
+  uint64_t* dk;
+  double* dv;
+  HIP_TRY(hipMalloc(&dk, 2 * c->n_col * sizeof(uint64_t)));
+  HIP_TRY(hipMalloc(&dv, c->n_col * sizeof(double)));
+  int blocks = (int)std::min<int64_t>((c->n_col + 255) / 256, 4096);
+  k_column<<<blocks, 256, 0, c->stream>>>(ham_of(c), key[0], key[1], c->n_col, dk, dv);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(keys, dk, 2 * c->n_col * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(vals, dv, c->n_col * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  (void)hipFree(dk);
+  (void)hipFree(dv);
+  return 0;
+}
+
+int cdfci_entry(cdfci_ctx* c, const uint64_t k1[2], const uint64_t k2[2], double* value) {
+  if (!c || !k1 || !k2 || !value) return CDFCI_ERR_INVALID_ARG;
+  double* d;
+  HIP_TRY(hipMalloc(&d, sizeof(double)));
+  k_entry<<<1, 1, 0, c->stream>>>(ham_of(c), k1[0], k1[1], k2[0], k2[1], d);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(value, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  (void)hipFree(d);
+  return 0;
+}
+
+int cdfci_export(cdfci_ctx* c, int64_t top_n, uint64_t* keys, double* cv, double* bv, int64_t cap,
+                 int64_t* count) {
+  if (!c || !count) return CDFCI_ERR_INVALID_ARG;
+  if (top_n > 0) return CDFCI_ERR_UNSUPPORTED;
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  hipStream_t s = c->stream;
+  unsigned long long* d_cnt = (unsigned long long*)(c->dscratch + 2 * 4096 + 4);
+  HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
+  rc = ensure_list(c, (int64_t)h.occupied + 1);
+  if (rc) return rc;
+  k_compact<<<2048, 256, 0, s>>>(c->T, c->nslots, 0, c->list, d_cnt, c->list_cap);
+  unsigned long long n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, d_cnt, sizeof(n), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *count = (int64_t)n;
+  int64_t m = std::min<int64_t>(std::min<int64_t>((int64_t)n, cap), c->list_cap);
+  if (m > 0 && keys && cv && bv) {
+    uint64_t* dk;
+    double *dc, *db;
+    HIP_TRY(hipMalloc(&dk, 2 * m * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&dc, m * sizeof(double)));
+    HIP_TRY(hipMalloc(&db, m * sizeof(double)));
+    k_gather<<<1024, 256, 0, s>>>(c->T, c->list, m, dk, dc, db);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(keys, dk, 2 * m * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(cv, dc, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(bv, db, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(dk);
+    (void)hipFree(dc);
+    (void)hipFree(db);
+  }
+  return 0;
+}
+
+int cdfci_free(cdfci_ctx* c) {
+  if (!c) return 0;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->own_table && c->T) (void)hipFree(c->T);
+  if (c->d_h) (void)hipFree(c->d_h);
+  if (c->d_eri) (void)hipFree(c->d_eri);
+  if (c->d_jk) (void)hipFree(c->d_jk);
+  if (c->ctl) (void)hipFree(c->ctl);
+  if (c->parts) (void)hipFree(c->parts);
+  if (c->list) (void)hipFree(c->list);
+  if (c->dscratch) (void)hipFree(c->dscratch);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+  return 0;
+}
+
+const char* cdfci_strerror(int code) {
+  switch (code) {
+    case CDFCI_OK: return "ok";
+    case CDFCI_ERR_INVALID_ARG: return "invalid argument or context state";
+    case CDFCI_ERR_UNSUPPORTED: return "unsupported size or mode";
+    case CDFCI_ERR_TABLE_FULL: return "hash table full (occupancy limit or probe bound exceeded)";
+    case CDFCI_ERR_NOT_NEGATIVE: return "starting energy is not negative";
+    case CDFCI_ERR_HIP: return "HIP runtime error";
+    case CDFCI_ERR_BARRIER: return "device-wide barrier timed out";
+    case CDFCI_ERR_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown error";
+  }
+}
+
+const char* cdfci_last_error(void) { return g_last_error.c_str(); }
+
+int cdfci_phase_times(cdfci_ctx* c, double* seconds) {
+  if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+  for (int k = 0; k < 4; ++k) seconds[k] = (double)h.t_phase[k] / (1e3 * (double)khz);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every entry point include/cdfci.h
+declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+from paper_2605_04483_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cdfci.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cdfci_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("cdfci_init", "cdfci_step", "cdfci_energy", "cdfci_rdm_backward", "cdfci_column",
+                 "cdfci_entry", "cdfci_export", "cdfci_free", "cdfci_init_hubbard"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    bound = {n for n, _, _ in _lib.SIGNATURES}
+    assert bound == set(declared_symbols())
+
+
+def test_struct_layouts():
+    # cdfci_opts: 5 8-byte scalars, 4 ints, 3 pointer-size fields
+    assert ctypes.sizeof(_lib.cdfci_opts) == 5 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(_lib.cdfci_stats) == 5 * 8 + 2 * 4 + 5 * 8
+
+
+def test_strerror_without_gpu():
+    L = _lib.load()
+    assert L.cdfci_strerror(-3).decode().startswith("hash table full")
+    assert L.cdfci_strerror(0).decode() == "ok"
+
+
+def test_host_side_argument_errors_without_gpu():
+    """Argument checks that return before any device call."""
+    L = _lib.load()
+    ctx = ctypes.c_void_p()
+    opts = _lib.cdfci_opts()
+    # too many orbitals -> UNSUPPORTED before touching the device
+    h = (ctypes.c_double * 1)()
+    rc = L.cdfci_init(h, h, 64, 1, 1, ctypes.byref(opts), ctypes.byref(ctx))
+    assert rc == _lib.CDFCI_ERR_UNSUPPORTED
+    rc = L.cdfci_init(None, None, 4, 1, 1, ctypes.byref(opts), ctypes.byref(ctx))
+    assert rc == _lib.CDFCI_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert L.cdfci_workspace_size(24, 6, 6, ctypes.byref(opts), ctypes.byref(n)) == 0
+    assert n.value == (1 << 22) * 32

@@ -2,9 +2,14 @@
 
 Workload: synthetic ab initio Hamiltonian, 24 spatial orbitals, 6 alpha + 6
 beta electrons, 72 auxiliary vectors (seed 2024), hash table of 2^28 slots,
-single-coordinate CDFCI (Alg. 1).  One benchmark step = one cdfci_step call of
---iters coordinate-descent iterations (each: select, line search, enumerate
-the 16471-entry column, Slater-Condon, probe, scatter, recalculate b_i).
+single-coordinate CDFCI (Alg. 1) for 10^6 iterations in total (warmup + timed)
+with compression threshold tau = 5e-5 (at tau = 0 the 2^28-slot table reaches
+its 0.79 load limit after about 4.6e5 iterations).  One benchmark step = one
+cdfci_step call of --iters iterations (each: select, line search, enumerate the
+16471-entry column, Slater-Condon, probe, scatter, recalculate b_i).
+
+--copy-probe runs only a device copy of known size (for calibrating the HBM
+byte counters of a profiler run) and exits.
 
 Prints one JSON line: H elements/s (enumerated column entries per second,
 zeros included) as `value`, plus CD iterations/s, the HBM roofline of the
@@ -47,11 +52,12 @@ def cpu_baseline(h, eri, na, nb, seconds_target=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=95)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--iters", type=int, default=10000, help="CD iterations per benchmark step")
     ap.add_argument("--table-log2", type=int, default=28)
-    ap.add_argument("--tau", type=float, default=0.0)
+    ap.add_argument("--tau", type=float, default=5e-5)
+    ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -60,13 +66,21 @@ def main():
               "(sharding the hash table by key), not an executable path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2605_04483_amd as api
     import synth_inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # 1 GiB read + 1 GiB write, the reference for FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8}), flush=True)
+        return
     N, na, nb, naux = 24, 6, 6, 72
     seed = synth_inputs.CONFIG_SEEDS["abinitio_n24"]
     h, eri = synth_inputs.ab_initio(N, naux, seed)
@@ -102,7 +116,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "ab initio N=24 6a+6b naux=72 seed=2024, 2^28-slot table, "
-                               "single-coordinate CDFCI",
+                               "single-coordinate CDFCI, 1e6 iterations",
                    "iters_per_step": args.iters, "tau": args.tau,
                    "column_entries": n_col},
         "cd_iters_per_s": iters / wall,

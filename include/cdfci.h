@@ -42,6 +42,7 @@ extern "C" {
 #define CDFCI_ERR_HIP -5           /* a HIP runtime call failed */
 #define CDFCI_ERR_BARRIER -6       /* a device-wide barrier exceeded its spin limit */
 #define CDFCI_ERR_WORKSPACE -7     /* caller workspace too small */
+#define CDFCI_ERR_NUMERIC -8       /* a multicoordinate step produced a non-finite value */
 
 typedef struct cdfci_ctx cdfci_ctx; /* opaque, library-owned */
 
@@ -98,11 +99,19 @@ int cdfci_init(const double* h, const double* eri, int n_orb, int n_alpha, int n
 int cdfci_init_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
                        const cdfci_opts* opts, cdfci_ctx** out);
 
-/* Run up to nsteps iterations (Alg. 1 when k == 1, Alg. 2 when k > 1) and
- * stop early if the damped step accumulator drops below dx_threshold
- * (Sec. 4.1.3).  Enqueued on the context's stream; returns after completion.
- * out may be NULL. */
+/* Run up to nsteps iterations and stop early if the damped step accumulator
+ * drops below dx_threshold (Sec. 4.1.3).  k == 1: single-coordinate descent
+ * (Alg. 1, Sec. 3.1).  1 < k <= 1024: multicoordinate descent (Alg. 2,
+ * Sec. 3.2): the k candidates of largest |4 b_i + 4 mu c_i| from the previous
+ * step's columns, the step (gamma, eta) from the lowest eigenpair of the
+ * (k+1)-dimensional Q^T H Q, c <- gamma c + E_I eta, b <- gamma b + H_{:,I} eta.
+ * Steps with different k may be mixed on one context.  Enqueued on the
+ * context's stream; returns after completion.  out may be NULL. */
 int cdfci_step(cdfci_ctx* ctx, int k, int64_t nsteps, cdfci_stats* out);
+
+/* Like cdfci_step and also records the energy alpha/mu after every iteration
+ * into energy (host, length nsteps). */
+int cdfci_step_energies(cdfci_ctx* ctx, int k, int64_t nsteps, double* energy, cdfci_stats* out);
 
 /* Like cdfci_step (k == 1 only) and also records, per iteration, the energy,
  * the chosen determinant and the step size into host arrays of length nsteps

@@ -64,10 +64,16 @@ def mcdfci_run(h, eri, init_keys, init_c, m, tau=0.0, max_steps=100, theta=0.9, 
     d = 0.0
     energies = []
     selections = []
+    gaps = []
     for step in range(max_steps):
         g = {j: abs(4.0 * b.get(j, 0.0) + 4.0 * mu * c.get(j, 0.0)) for j in cand}
         order = sorted(cand, key=lambda j: (-g[j], _order_key(j)))
         I = order[:m]
+        # relative gap between the last chosen and the first left-out gradient
+        if len(order) > m and g[order[m - 1]] > 0.0:
+            gaps.append((g[order[m - 1]] - g[order[m]]) / g[order[m - 1]])
+        else:
+            gaps.append(1.0)
         mm = len(I)
         cI = np.array([c.get(i, 0.0) for i in I])
         bI = np.array([b.get(i, 0.0) for i in I])
@@ -127,5 +133,6 @@ def mcdfci_run(h, eri, init_keys, init_c, m, tau=0.0, max_steps=100, theta=0.9, 
     st.c, st.b, st.mu, st.alpha = c, b, mu, alpha
     st.energies = np.array(energies)
     st.selections = selections
+    st.gaps = np.array(gaps)
     st.energy = alpha / mu
     return st

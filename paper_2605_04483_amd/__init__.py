@@ -7,8 +7,8 @@ call does, and fails loudly if it has not been built.
 """
 from .api import (CDFCIError, Context, cdfci_column, cdfci_energy, cdfci_entry, cdfci_export,
                   cdfci_free, cdfci_init, cdfci_init_hubbard, cdfci_phase_times, cdfci_rdm_backward, cdfci_step,
-                  cdfci_step_trace, cdfci_strerror, cdfci_workspace_size, make_opts)
+                  cdfci_step_energies, cdfci_step_trace, cdfci_strerror, cdfci_workspace_size, make_opts)
 
 __all__ = ["CDFCIError", "Context", "cdfci_column", "cdfci_energy", "cdfci_entry", "cdfci_export",
            "cdfci_free", "cdfci_init", "cdfci_init_hubbard", "cdfci_phase_times", "cdfci_rdm_backward", "cdfci_step",
-           "cdfci_step_trace", "cdfci_strerror", "cdfci_workspace_size", "make_opts"]
+           "cdfci_step_energies", "cdfci_step_trace", "cdfci_strerror", "cdfci_workspace_size", "make_opts"]

@@ -13,6 +13,7 @@ CDFCI_ERR_NOT_NEGATIVE = -4
 CDFCI_ERR_HIP = -5
 CDFCI_ERR_BARRIER = -6
 CDFCI_ERR_WORKSPACE = -7
+CDFCI_ERR_NUMERIC = -8
 
 
 class cdfci_opts(ctypes.Structure):
@@ -70,6 +71,7 @@ SIGNATURES = [
       ctypes.c_int, _OPTP, _CTXP]),
     ("cdfci_step", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, _STP]),
     ("cdfci_step_trace", ctypes.c_int, [_P, ctypes.c_int64, _DP, _UP, _UP, _DP, _STP]),
+    ("cdfci_step_energies", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, _DP, _STP]),
     ("cdfci_energy", ctypes.c_int, [_P, ctypes.c_int, _DP]),
     ("cdfci_rdm_backward", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64, _DP, _DP, _DP]),
     ("cdfci_column", ctypes.c_int, [_P, _UP, _UP, _DP, ctypes.c_int64, _I64P]),

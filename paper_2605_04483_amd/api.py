@@ -137,6 +137,14 @@ def cdfci_step_trace(ctx, nsteps):
             "stats": st.as_dict()}
 
 
+def cdfci_step_energies(ctx, k, nsteps):
+    E = np.zeros(max(int(nsteps), 1))
+    st = cdfci_stats()
+    _check(_lib.load().cdfci_step_energies(ctx.handle, int(k), int(nsteps), _dp(E), ctypes.byref(st)),
+           "cdfci_step_energies")
+    return E[:st.steps], st.as_dict()
+
+
 def cdfci_energy(ctx, exact=0):
     e = ctypes.c_double(0.0)
     _check(_lib.load().cdfci_energy(ctx.handle, int(exact), ctypes.byref(e)), "cdfci_energy")

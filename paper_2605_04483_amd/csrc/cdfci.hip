@@ -452,6 +452,7 @@ __global__ void k_finish_steps(Ctl* ctl) {
 __global__ void k_reset_barrier(Ctl* ctl) {
   ctl->barrier = 0;
   ctl->steps_this_call = 0;
+  ctl->stopped = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -805,6 +806,8 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
   out[1] = dd_val(b);
 }
 
+#include "mcd_kernels.h"
+
 }  // namespace
 
 // ===========================================================================
@@ -832,6 +835,24 @@ struct cdfci_ctx {
   int64_t* list = nullptr;
   int64_t list_cap = 0;
   double* dscratch = nullptr;  // 2 * 2048 partials + 2
+  // multicoordinate state (allocated on the first k > 1 step)
+  int mode = 0;  // 0: single-coordinate state current, 1: multicoordinate state current
+  int mc_kcap = 0;
+  uint64_t cand_cap = 0;
+  McState* mst = nullptr;
+  unsigned* cand = nullptr;  // candidate pages (kPage slot ids each)
+  unsigned* cnt = nullptr;   // entries used per page
+  unsigned long long* gkey = nullptr;
+  unsigned* hist = nullptr;
+  unsigned* ties = nullptr;
+  int64_t* sel_slot = nullptr;
+  uint64_t* sel_a = nullptr;
+  uint64_t* sel_b = nullptr;
+  double* eta = nullptr;
+  double* recalc = nullptr;
+  double* hii = nullptr;
+  double* lan = nullptr;
+  unsigned* bitmap = nullptr;
 };
 
 namespace {
@@ -856,6 +877,10 @@ int check_error(cdfci_ctx* c, const Ctl& h) {
   if (h.error & kErrPublish) {
     c->poisoned = true;
     return CDFCI_ERR_HIP;
+  }
+  if (h.error & kErrNumeric) {
+    c->poisoned = true;
+    return CDFCI_ERR_NUMERIC;
   }
   if (h.occupied > c->max_entries) {
     c->poisoned = true;
@@ -1194,14 +1219,193 @@ static int run_cd1(cdfci_ctx* c, int64_t nsteps, double* trE, uint64_t* tra, uin
   return check_error(c, h);
 }
 
+// ---- multicoordinate descent (Alg. 2) host orchestration
+
+static constexpr int kMaxK = 1024;
+
+// (Re)allocates the multicoordinate buffers.  A reallocation discards the
+// candidate list, so *lost is set and the caller must rebuild it.
+static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
+  *lost = false;
+  // pages: one per scatter workgroup (k columns x chunks) plus the chosen set,
+  // or enough for every stored entry when the list is rebuilt from the table
+  const uint64_t chunks = (uint64_t)((c->n_col + kPage - 1) / kPage);
+  const uint64_t pages = std::max<uint64_t>((uint64_t)k * chunks + (k + kPage - 1) / kPage,
+                                            (occupied + 1 + kPage - 1) / kPage);
+  const uint64_t need_cand = pages * kPage;
+  if (k > c->mc_kcap || need_cand > c->cand_cap) {
+    // release and reallocate at the larger size
+    void* olds[] = {c->cand, c->cnt, c->gkey, c->hii, c->lan, c->sel_slot, c->sel_a, c->sel_b, c->eta,
+                    c->recalc};
+    for (void* p : olds)
+      if (p) (void)hipFree(p);
+    const int kc = std::max(k, c->mc_kcap);
+    const uint64_t cc = std::max(need_cand, c->cand_cap);
+    HIP_TRY(hipMalloc(&c->cand, cc * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->cnt, (cc / kPage) * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->gkey, cc * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&c->hii, (size_t)kc * kc * sizeof(double)));
+    HIP_TRY(hipMalloc(&c->lan, (size_t)(kLanczosMax + 1) * (kc + 1) * sizeof(double)));
+    HIP_TRY(hipMalloc(&c->sel_slot, (size_t)kc * sizeof(int64_t)));
+    HIP_TRY(hipMalloc(&c->sel_a, (size_t)kc * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&c->sel_b, (size_t)kc * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&c->eta, (size_t)kc * sizeof(double)));
+    HIP_TRY(hipMalloc(&c->recalc, (size_t)kc * sizeof(double)));
+    HIP_TRY(hipMemsetAsync(c->recalc, 0, (size_t)kc * sizeof(double), c->stream));
+    c->mc_kcap = kc;
+    c->cand_cap = cc;
+    *lost = true;
+  }
+  if (!c->mst) {
+    HIP_TRY(hipMalloc(&c->mst, sizeof(McState)));
+    McState z;
+    memset(&z, 0, sizeof(z));
+    z.scale = 1.0;
+    z.inv_scale = 1.0;
+    HIP_TRY(hipMemcpyAsync(c->mst, &z, sizeof(z), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMalloc(&c->hist, kRadixBins * sizeof(unsigned)));
+    HIP_TRY(hipMemsetAsync(c->hist, 0, kRadixBins * sizeof(unsigned), c->stream));
+    HIP_TRY(hipMalloc(&c->ties, kMaxTies * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->bitmap, (c->nslots / 32 + 1) * sizeof(unsigned)));
+  }
+  return 0;
+}
+
+// single-coordinate state -> multicoordinate state: every stored entry is a
+// candidate of the first multicoordinate selection (after init these are the
+// columns of the starting determinants, as Alg. 2 prescribes)
+static int enter_multi(cdfci_ctx* c) {
+  hipStream_t s = c->stream;
+  const uint64_t nwords = c->nslots / 32 + 1;
+  k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, nwords, c->mst);
+  k_mc_init_cands<<<2048, 256, 0, s>>>(c->T, c->nslots, c->cand, c->mst, c->cand_cap);
+  k_mc_dense_pages<<<256, 256, 0, s>>>(c->cnt, c->mst, c->cand_cap);
+  HIP_TRY(hipGetLastError());
+  c->mode = 1;
+  return 0;
+}
+
+// multicoordinate state -> single-coordinate state: fold the lazy scale into
+// the table and choose the next coordinate over every stored entry
+static int enter_single(cdfci_ctx* c) {
+  hipStream_t s = c->stream;
+  k_mc_rescale<<<2048, 256, 0, s>>>(c->T, c->nslots, c->mst, 1);
+  k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
+  int sel_blocks = (int)std::min<uint64_t>((c->nslots + 255) / 256, (uint64_t)c->max_parts);
+  k_select_table<<<sel_blocks, 256, 0, s>>>(c->T, c->nslots, c->ctl, c->parts);
+  k_select_final<<<1, 1, 0, s>>>(c->parts, sel_blocks, c->ctl);
+  HIP_TRY(hipGetLastError());
+  c->mode = 0;
+  return 0;
+}
+
+static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats* out) {
+  if (c->poisoned) return CDFCI_ERR_INVALID_ARG;
+  if (k > kMaxK || nsteps < 0) return CDFCI_ERR_INVALID_ARG;
+  Ctl before;
+  int rc = ctl_read(c, &before);
+  if (rc) return rc;
+  bool lost = false;
+  rc = mc_alloc(c, k, before.occupied, &lost);
+  if (rc) return rc;
+  if (c->mode != 1 || lost) {
+    rc = enter_multi(c);
+    if (rc) return rc;
+  }
+  double* dE = nullptr;
+  if (trE) HIP_TRY(hipMalloc(&dE, (size_t)(before.steps + nsteps + 1) * sizeof(double)));
+  hipStream_t s = c->stream;
+  const Ham H = ham_of(c);
+  const int hist_blocks = 1024;
+  const int chunks = (int)((c->n_col + kPage - 1) / kPage);
+  const uint64_t nwords = c->nslots / 32 + 1;
+  EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, k,
+             c->opts.dx_damping, c->opts.dx_threshold, dE};
+  ScatterArgs sa{H,        c->T,      c->mask,   c->sel_a, c->sel_b, c->eta,  c->mst,
+                 c->ctl,   c->recalc, c->bitmap, c->cand,  c->cnt,   c->n_col, c->opts.z_threshold,
+                 k};
+  const unsigned page0 = (unsigned)(k * chunks);
+  k_reset_barrier<<<1, 1, 0, s>>>(c->ctl);
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  for (int64_t step = 0; step < nsteps; ++step) {
+    k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+      k_mc_hist<<<hist_blocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist,
+                                            pass);
+      k_mc_scan<<<1, 256, 0, s>>>(c->hist, c->mst, c->cnt, k, pass);
+    }
+    k_mc_gather<<<hist_blocks, 256, 0, s>>>(c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties);
+    k_mc_ties<<<1, 256, 0, s>>>(c->T, c->mst, c->sel_slot, c->sel_a, c->sel_b, c->ties, k);
+    k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, nwords, c->mst);
+    k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k);
+    k_mc_eig<<<1, 1024, 0, s>>>(ea);
+    k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
+    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
+                                   c->ctl, c->max_entries, page0, k);
+    k_mc_rescale<<<256, 256, 0, s>>>(c->T, c->nslots, c->mst, 0);
+    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);
+    if (((step + 1) & 63) == 0) HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  HIP_TRY(hipGetLastError());
+  Ctl h;
+  rc = ctl_read(c, &h);
+  if (rc) return rc;
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  const int64_t done = h.steps - before.steps;
+  if (trE) {
+    if (done > 0) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+    (void)hipFree(dE);
+  }
+  if (out) {
+    out->steps = done;
+    out->total_steps = h.steps;
+    out->elements = done * (int64_t)k * c->n_col;
+    out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->occupied = h.occupied;
+    out->max_probe = h.max_probe;
+    out->stopped = h.stopped;
+    out->energy = h.energy;
+    out->dx = h.d;
+    out->mu = h.mu_hi + h.mu_lo;
+    out->alpha = h.al_hi + h.al_lo;
+    out->seconds = ms * 1e-3;
+  }
+  return check_error(c, h);
+}
+
 int cdfci_step(cdfci_ctx* ctx, int k, int64_t nsteps, cdfci_stats* out) {
   if (!ctx || k < 1) return CDFCI_ERR_INVALID_ARG;
-  if (k == 1) return run_cd1(ctx, nsteps, nullptr, nullptr, nullptr, nullptr, out);
-  return CDFCI_ERR_UNSUPPORTED;
+  if (k == 1) {
+    if (ctx->mode == 1) {
+      int rc = enter_single(ctx);
+      if (rc) return rc;
+    }
+    return run_cd1(ctx, nsteps, nullptr, nullptr, nullptr, nullptr, out);
+  }
+  return run_mc(ctx, k, nsteps, nullptr, out);
+}
+
+int cdfci_step_energies(cdfci_ctx* ctx, int k, int64_t nsteps, double* energy, cdfci_stats* out) {
+  if (!ctx || k < 1 || !energy) return CDFCI_ERR_INVALID_ARG;
+  if (k == 1) {
+    if (ctx->mode == 1) {
+      int rc = enter_single(ctx);
+      if (rc) return rc;
+    }
+    return run_cd1(ctx, nsteps, energy, nullptr, nullptr, nullptr, out);
+  }
+  return run_mc(ctx, k, nsteps, energy, out);
 }
 
 int cdfci_step_trace(cdfci_ctx* ctx, int64_t nsteps, double* energy, uint64_t* sel_alpha,
                      uint64_t* sel_beta, double* eta, cdfci_stats* out) {
+  if (!ctx) return CDFCI_ERR_INVALID_ARG;
+  if (ctx->mode == 1) {
+    int rc = enter_single(ctx);
+    if (rc) return rc;
+  }
   return run_cd1(ctx, nsteps, energy, sel_alpha, sel_beta, eta, out);
 }
 
@@ -1279,10 +1483,14 @@ int cdfci_export(cdfci_ctx* c, int64_t top_n, uint64_t* keys, double* cv, double
                  int64_t* count) {
   if (!c || !count) return CDFCI_ERR_INVALID_ARG;
   if (top_n > 0) return CDFCI_ERR_UNSUPPORTED;
+  hipStream_t s = c->stream;
+  if (c->mode == 1) {  // true values: fold the multicoordinate lazy scale in
+    k_mc_rescale<<<2048, 256, 0, s>>>(c->T, c->nslots, c->mst, 1);
+    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
+  }
   Ctl h;
   int rc = ctl_read(c, &h);
   if (rc) return rc;
-  hipStream_t s = c->stream;
   unsigned long long* d_cnt = (unsigned long long*)(c->dscratch + 2 * 4096 + 4);
   HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
   rc = ensure_list(c, (int64_t)h.occupied + 1);
@@ -1324,6 +1532,10 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->parts) (void)hipFree(c->parts);
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
+  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
+                c->eta, c->recalc, c->hii, c->lan, c->bitmap};
+  for (void* p : mc)
+    if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;

@@ -27,6 +27,7 @@ constexpr int kMaxOrb = 63;
 constexpr int kErrTableFull = 1;
 constexpr int kErrBarrier = 2;
 constexpr int kErrPublish = 4;
+constexpr int kErrNumeric = 8;
 
 struct alignas(32) Slot {
   uint64_t ka, kb;

@@ -1,0 +1,797 @@
+// Multicoordinate descent, mCDFCI (paper Sec. 3.2, Algorithm 2), device side.
+// Included into cdfci.hip inside its kernel namespace (uses Ctl, Cand, Slot).
+//
+// One step is a fixed sequence of launches with no host synchronisation:
+//   select   top-k of |4 b_j + 4 mu c_j| over the step's candidates (the union
+//            of the previous step's columns, deduplicated): MSB radix select
+//            on the bit pattern of the non-negative double |g| (six digit
+//            passes), exact ties at the threshold to the smaller key;
+//   H_II     pairwise Slater-Condon entries among the chosen determinants;
+//   reduced  A = Q^T H Q with Q = [c~, E_I] (eq. (def-z)); its lowest
+//            eigenpair by Lanczos with full reorthogonalisation started from
+//            the current point [nu; c_I]; gamma, eta; mu and alpha updates;
+//   scatter  b += H_{:,I} eta over the k columns with the compression rule,
+//            recalculation sums for b_I, touched entries marked in a slot
+//            bitmap and written to the workgroup's own candidate page;
+//   finish   b_I <- recalculated values, I appended to the candidates.
+// c and b are stored with a lazy global scale: c = s * c_hat, b = s * b_hat, so
+// the gamma rescaling of every entry costs one scalar update (s <- gamma s).
+//
+// Candidates live in pages of 256 slot ids with a count per page.  Each
+// scatter workgroup owns one page, so no global append counter is contended.
+
+struct McState {
+  unsigned long long n_pages;        // candidate pages of the coming selection
+  unsigned long long prefix, pmask;  // radix select: fixed bits and their mask
+  long long need;                    // still to take inside the current bucket
+  unsigned long long n_above;        // strictly above the bucket (selected)
+  unsigned long long n_sel, n_tie;   // gather counters
+  unsigned long long n_dense;        // entries of a dense candidate list (mode entry)
+  int all, done;                     // all candidates selected / bucket exact
+  double scale;                      // s in c = s * c_hat
+  double inv_scale;                  // 1 / s after this step's update
+  double gamma;
+  int lanczos_iters;
+  int rescale;
+  int skip;  // this step does nothing (an error is pending or the run stopped)
+  int pad;
+};
+
+constexpr int kPage = 256;
+constexpr int kRadixBits = 11;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixPasses = 6;  // digits at bits 53, 42, 31, 20, 9 (11 wide) and 0 (9 wide)
+constexpr int kMaxTies = 4096;
+constexpr int kLanczosMax = 64;
+
+__device__ __forceinline__ int radix_shift(int pass) { return pass < 5 ? 53 - 11 * pass : 0; }
+__device__ __forceinline__ unsigned long long radix_digit_mask(int pass) {
+  return pass < 5 ? 0x7FFull : 0x1FFull;
+}
+
+__device__ __forceinline__ unsigned long long g_key(const Slot& s, double mu) {
+  double g = fabs(4.0 * s.b + 4.0 * mu * s.c);
+  return (unsigned long long)__double_as_longlong(g);
+}
+
+// start of a step: skip it if an error is pending or the stopping rule fired
+__global__ void k_mc_begin(McState* st, const Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->skip = (ctl->error || ctl->stopped) ? 1 : 0;
+}
+
+// all occupied slots become candidates (entering the multicoordinate mode):
+// a dense list, turned into full pages by k_mc_dense_pages
+__global__ void __launch_bounds__(256) k_mc_init_cands(const Slot* T, uint64_t nslots,
+                                                       unsigned* cand, McState* st, uint64_t cap) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (T[i].ka == kEmpty) continue;
+    unsigned long long k = atomicAdd(&st->n_dense, 1ull);
+    if (k < cap) cand[k] = (unsigned)i;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* st, uint64_t cap) {
+  const unsigned long long n = min(st->n_dense, (unsigned long long)cap);
+  const unsigned long long pages = (n + kPage - 1) / kPage;
+  for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < pages;
+       p += (unsigned long long)gridDim.x * blockDim.x)
+    cnt[p] = (unsigned)min((unsigned long long)kPage, n - p * kPage);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->n_pages = pages;
+    st->n_dense = 0;
+  }
+}
+
+// radix-select histogram pass; pass 0 also computes the keys
+__global__ void __launch_bounds__(256) k_mc_hist(const Slot* T, const unsigned* cand,
+                                                 const unsigned* cnt, unsigned long long* gkey,
+                                                 const Ctl* ctl, const McState* st, unsigned* hist,
+                                                 int pass) {
+  __shared__ unsigned h[kRadixBins];
+  if (st->skip) return;
+  if (pass > 0 && (st->all || st->done)) return;
+  for (int i = threadIdx.x; i < kRadixBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const unsigned long long n = st->n_pages * kPage;
+  const double mu = ctl->mu_hi + ctl->mu_lo;
+  const int sh = radix_shift(pass);
+  const unsigned long long dm = radix_digit_mask(pass);
+  const unsigned long long P = st->prefix, M = st->pmask;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
+    unsigned long long key;
+    if (pass == 0) {
+      key = g_key(T[cand[i]], mu);
+      gkey[i] = key;
+    } else {
+      key = gkey[i];
+      if ((key & M) != P) continue;
+    }
+    atomicAdd(&h[(key >> sh) & dm], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRadixBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// one workgroup: choose the digit of the bucket holding the k-th largest key
+__global__ void __launch_bounds__(256) k_mc_scan(unsigned* hist, McState* st, const unsigned* cnt,
+                                                 int k, int pass) {
+  __shared__ unsigned long long s_suffix[kRadixBins];  // count of bins > d
+  __shared__ unsigned long long s_total;
+  __shared__ int s_d;
+  if (st->skip) return;
+  const int tid = threadIdx.x;
+  if (pass == 0) {
+    // total candidates = sum of the page counts
+    unsigned long long part = 0;
+    for (unsigned long long p = tid; p < st->n_pages; p += blockDim.x) part += cnt[p];
+    if (tid == 0) s_total = 0;
+    __syncthreads();
+    atomicAdd(&s_total, part);
+    __syncthreads();
+    if (tid == 0) {
+      st->prefix = 0;
+      st->pmask = 0;
+      st->n_above = 0;
+      st->done = 0;
+      st->all = (s_total <= (unsigned long long)k) ? 1 : 0;
+      st->need = k;
+    }
+    __syncthreads();
+  }
+  if (!(st->all || st->done)) {
+    const int sh = radix_shift(pass);
+    const int nb = (int)radix_digit_mask(pass) + 1;
+    // s_suffix[d] = number of keys in bins strictly above d (block-wide scan
+    // from the top; each thread owns a run of bins)
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int lo = tid * per, hi = min(nb, lo + per);
+    unsigned long long run = 0;
+    for (int d = hi - 1; d >= lo; --d) run += hist[d];
+    __shared__ unsigned long long s_run[256];
+    s_run[tid] = run;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long acc = 0;
+      for (int t = (int)blockDim.x - 1; t >= 0; --t) {
+        unsigned long long r = s_run[t];
+        s_run[t] = acc;  // keys in the threads' runs above t
+        acc += r;
+      }
+    }
+    __syncthreads();
+    unsigned long long acc = s_run[tid];
+    for (int d = hi - 1; d >= lo; --d) {
+      s_suffix[d] = acc;
+      acc += hist[d];
+    }
+    if (tid == 0) s_d = 0;
+    __syncthreads();
+    const long long need = st->need;
+    for (int d = lo; d < hi; ++d) {
+      const long long above = (long long)s_suffix[d];
+      if (above < need && above + (long long)hist[d] >= need) s_d = d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int d = s_d;
+      const long long above = (long long)s_suffix[d];
+      st->n_above += (unsigned long long)above;
+      st->need = need - above;
+      st->prefix |= (unsigned long long)d << sh;
+      st->pmask |= radix_digit_mask(pass) << sh;
+      if ((long long)hist[d] == need - above) st->done = 1;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < kRadixBins; i += blockDim.x) hist[i] = 0;
+}
+
+// selected slots -> sel_slot (order irrelevant); exact ties -> tie buffer
+__global__ void __launch_bounds__(256) k_mc_gather(const unsigned* cand, const unsigned* cnt,
+                                                   const unsigned long long* gkey, McState* st,
+                                                   int64_t* sel_slot, unsigned* ties) {
+  if (st->skip) return;
+  const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long P = st->prefix, M = st->pmask;
+  const int all = st->all, done = st->done;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
+    const unsigned long long km = gkey[i] & M;
+    const bool take = all || km > P || (done && km == P);
+    if (take) {
+      unsigned long long s = atomicAdd(&st->n_sel, 1ull);
+      sel_slot[s] = cand[i];
+    } else if (km == P) {
+      unsigned long long t = atomicAdd(&st->n_tie, 1ull);
+      if (t < kMaxTies) ties[t] = cand[i];
+    }
+  }
+}
+
+// resolve exact ties by key order, then fill the keys of the chosen set
+__global__ void __launch_bounds__(256) k_mc_ties(const Slot* T, McState* st, int64_t* sel_slot,
+                                                 uint64_t* sel_a, uint64_t* sel_b, const unsigned* ties,
+                                                 int k) {
+  __shared__ unsigned long long s_base;
+  if (st->skip) return;
+  const int tid = threadIdx.x;
+  if (!(st->all || st->done)) {
+    const long long need = st->need;
+    const int nt = (int)min(st->n_tie, (unsigned long long)kMaxTies);
+    if (tid == 0) s_base = st->n_sel;
+    __syncthreads();
+    for (int i = tid; i < nt; i += blockDim.x) {
+      const Slot si = T[ties[i]];
+      int rank = 0;
+      for (int j = 0; j < nt; ++j) {
+        const Slot sj = T[ties[j]];
+        if (key_less(sj.ka, sj.kb, si.ka, si.kb)) ++rank;
+      }
+      if (rank < need) sel_slot[s_base + rank] = ties[i];
+    }
+    __syncthreads();
+    if (tid == 0) st->n_sel = s_base + (unsigned long long)min((long long)nt, need);
+  }
+  __syncthreads();
+  const int m = (int)min(st->n_sel, (unsigned long long)k);
+  for (int i = tid; i < m; i += blockDim.x) {
+    const Slot s = T[sel_slot[i]];
+    sel_a[i] = s.ka;
+    sel_b[i] = s.kb;
+  }
+}
+
+// clear the candidate bitmap for the coming scatter
+__global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwords, McState* st) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    bitmap[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_tie = 0;
+}
+
+// workgroup sum (any power-of-two size up to 1024), fixed order
+__device__ double wg_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(v, off);
+    v = (lane & off) ? (o + v) : (v + o);
+  }
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ dd wg_sum_dd(dd v, double* scratch) {
+  double hi = wg_sum(v.hi, scratch);
+  double lo = wg_sum(v.lo, scratch);
+  return two_sum(hi, lo);
+}
+
+// H_II: block y builds column y (ket = chosen determinant y)
+__global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, const uint64_t* sel_b,
+                                                const McState* st, double* hii, int k) {
+  __shared__ Lists L;
+  __shared__ double s_red[4];
+  if (st->skip) return;
+  const int m = (int)min(st->n_sel, (unsigned long long)k);
+  const int y = blockIdx.x;
+  if (y >= m) return;
+  const uint64_t a = sel_a[y], b = sel_b[y];
+  make_lists_block(a, b, H.N, L);
+  __syncthreads();
+  double part = 0.0;
+  const int nt = diag_terms(L);
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+  const double diag = wg_sum(part, s_red);
+  for (int i = threadIdx.x; i < m; i += blockDim.x)
+    hii[(size_t)i * m + y] = sc_entry(H, sel_a[i], sel_b[i], a, b, L, diag);
+}
+
+// ---------------------------------------------------------------- reduced problem
+
+// Sturm count: eigenvalues of the tridiagonal (a, b) below x
+__device__ __forceinline__ int sturm_count(const double* a, const double* b, int n, double x) {
+  int cnt = 0;
+  double d = a[0] - x;
+  if (d == 0.0) d = -1e-300;
+  cnt += d < 0.0;
+  for (int i = 1; i < n; ++i) {
+    d = a[i] - x - b[i - 1] * b[i - 1] / d;
+    if (d == 0.0) d = -1e-300;
+    cnt += d < 0.0;
+  }
+  return cnt;
+}
+
+// Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)), called
+// by one full wave: 64-way multisection on the Sturm count (six bits per
+// round), then inverse iteration with partial pivoting by lane 0.  y and wk
+// live in shared memory; the eigenvalue is returned to every lane.
+__device__ double tri_lowest_wave(const double* a, const double* b, int n, double* y, double* wk) {
+  const int lane = threadIdx.x & 63;
+  if (n == 1) {
+    if (lane == 0) y[0] = 1.0;
+    return a[0];
+  }
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < n - 1 ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  const double scale = fmax(fabs(lo), fabs(hi));
+  for (int round = 0; round < 16 && hi - lo > 2e-16 * scale; ++round) {
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const bool below = sturm_count(a, b, n, x) >= 1;  // lowest eigenvalue < x
+    const unsigned long long bal = __ballot(below);
+    // first lane whose point lies above the eigenvalue
+    const int f = bal ? (__ffsll((unsigned long long)bal) - 1) : 64;
+    const double nhi = f < 64 ? lo + (hi - lo) * (double)(f + 1) / 65.0 : hi;
+    const double nlo = f > 0 ? lo + (hi - lo) * (double)f / 65.0 : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  const double lam = 0.5 * (lo + hi);
+  if (lane == 0) {
+    // inverse iteration on (T - lam I): Gaussian elimination with partial
+    // pivoting of a tridiagonal matrix (fill-in one extra superdiagonal)
+    double* dl = wk;
+    double* dm = wk + n;
+    double* du = wk + 2 * n;
+    double* du2 = wk + 3 * n;
+    int* piv = (int*)(wk + 4 * n);
+    for (int i = 0; i < n; ++i) {
+      dm[i] = a[i] - lam;
+      du[i] = i < n - 1 ? b[i] : 0.0;
+      dl[i] = i < n - 1 ? b[i] : 0.0;
+      du2[i] = 0.0;
+      y[i] = 1.0;
+    }
+    const double tiny = 1e-300 + 1e-15 * scale;
+    for (int i = 0; i < n - 1; ++i) {
+      if (fabs(dm[i]) >= fabs(dl[i])) {
+        piv[i] = 0;
+        if (dm[i] == 0.0) dm[i] = tiny;
+        const double f = dl[i] / dm[i];
+        dl[i] = f;
+        dm[i + 1] -= f * du[i];
+      } else {
+        piv[i] = 1;
+        const double f = dm[i] / dl[i];
+        dm[i] = dl[i];
+        dl[i] = f;
+        const double t = du[i];
+        du[i] = dm[i + 1];
+        dm[i + 1] = t - f * dm[i + 1];
+        if (i < n - 2) {
+          du2[i] = du[i + 1];
+          du[i + 1] = -f * du[i + 1];
+        }
+      }
+    }
+    if (dm[n - 1] == 0.0) dm[n - 1] = tiny;
+    for (int sweep = 0; sweep < 3; ++sweep) {
+      for (int i = 0; i < n - 1; ++i) {
+        if (piv[i] == 0) {
+          y[i + 1] -= dl[i] * y[i];
+        } else {
+          const double t = y[i];
+          y[i] = y[i + 1];
+          y[i + 1] = t - dl[i] * y[i + 1];
+        }
+      }
+      y[n - 1] /= dm[n - 1];
+      y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / dm[n - 2];
+      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / dm[i];
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+      nrm = sqrt(nrm);
+      for (int i = 0; i < n; ++i) y[i] /= nrm;
+    }
+  }
+  return lam;
+}
+
+struct EigArgs {
+  const Slot* T;
+  Slot* Tw;
+  const int64_t* sel_slot;
+  const double* hii;  // m x m, symmetric
+  McState* st;
+  Ctl* ctl;
+  double* lan;  // (kLanczosMax + 1) * (k + 1) scratch
+  double* eta_out;
+  int k;
+  double theta, dx_tol;
+  double* tr_E;  // optional per-step energy trace
+};
+
+// The reduced matrix A (order n = m + off, off = 1 when the c~ column exists):
+//   A_00 = a00, A_0i = A_i0 = a0_i, A_ij = (H_II)_ij.
+// Thread r owns entry r (and r + 1024 when n = 1025).  H_II is read column-wise
+// (it is exactly symmetric), so the loads of a wave are contiguous.
+__device__ void mc_matvec(const double* hii, int m, int off, double a00, const double* s_a0,
+                          const double* s_x, double* yg, int n) {
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double acc = 0.0;
+    if (off && r == 0) {
+      acc = a00 * s_x[0];
+      for (int j = 0; j < m; ++j) acc += s_a0[j] * s_x[1 + j];
+    } else {
+      const int i = r - off;
+      for (int j = 0; j < m; ++j) acc += hii[(size_t)j * m + i] * s_x[off + j];
+      if (off) acc += s_a0[i] * s_x[0];
+    }
+    yg[r] = acc;
+  }
+}
+
+// h[i] = V_i . w for i = 0..j in one workgroup reduction (fixed order)
+__device__ void mc_multidot(const double* V, int n, int j, const double* w, double* s_dots,
+                            double* s_h) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = 0; i <= j; ++i) {
+    double p = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) p += V[(size_t)i * n + r] * w[r];
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_xor(p, off);
+      p = (lane & off) ? (o + p) : (p + o);
+    }
+    if (lane == 0) s_dots[wv * (kLanczosMax + 1) + i] = p;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += s_dots[q * (kLanczosMax + 1) + i];
+    s_h[i] = t;
+  }
+  __syncthreads();
+}
+
+// one workgroup of 1024 threads
+__global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
+  __shared__ double s_c[1024], s_b[1024], s_a0[1024], s_x[1025];
+  __shared__ double s_red[16];
+  __shared__ double s_dots[16 * (kLanczosMax + 1)];
+  __shared__ double s_alpha[kLanczosMax + 1], s_beta[kLanczosMax + 1];
+  __shared__ double s_y[kLanczosMax + 1], s_h[kLanczosMax + 1], s_h2[kLanczosMax + 1];
+  __shared__ double s_wk[5 * (kLanczosMax + 1)];
+  __shared__ double s_bc[4];
+  Ctl* ctl = A.ctl;
+  if (A.st->skip) return;
+  const int tid = threadIdx.x;
+  const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
+  const double s = A.st->scale;
+  const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
+  const double* hii = A.hii;
+  for (int i = tid; i < m; i += blockDim.x) {
+    const Slot sl = A.T[A.sel_slot[i]];
+    s_c[i] = s * sl.c;
+    s_b[i] = s * sl.b;
+  }
+  __syncthreads();
+  // hc = H_II c_I
+  double hc_i = 0.0;
+  if (tid < m)
+    for (int j = 0; j < m; ++j) hc_i += hii[(size_t)j * m + tid] * s_c[j];
+  const double ci = tid < m ? s_c[tid] : 0.0, bi = tid < m ? s_b[tid] : 0.0;
+  const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
+  const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
+  const dd chc = wg_sum_dd(two_prod(ci, hc_i), s_red);
+  // nu^2 = mu - c_I.c_I and the numerator of A_00 = alpha - 2 c_I.b_I + c_I.H_II.c_I
+  const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
+  const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
+  const double nu2v = dd_val(nu2);
+  const int off = nu2v > 1e-24 * dd_val(mu) ? 1 : 0;
+  const double nu = off ? sqrt(nu2v) : 0.0;
+  const double a00 = off ? dd_val(num) / nu2v : 0.0;
+  if (tid < m) s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
+  const int n = m + off;
+  if (n == 0) {  // nothing stored and nothing chosen: no step is possible
+    if (tid == 0) ctl->stopped = 1;
+    return;
+  }
+  double* V = A.lan;                            // rows 0..kLanczosMax-1: Lanczos vectors
+  double* w = A.lan + (size_t)kLanczosMax * n;  // work vector
+  // start vector: the current point [nu; c_I]
+  {
+    double part = 0.0;
+    for (int r = tid; r < n; r += blockDim.x) {
+      const double v = (off && r == 0) ? nu : s_c[r - off];
+      V[r] = v;
+      part += v * v;
+    }
+    double nrm = sqrt(wg_sum(part, s_red));
+    const bool ok = nrm > 0.0;
+    for (int r = tid; r < n; r += blockDim.x) V[r] = ok ? V[r] / nrm : (r == 0 ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  int iters = 0;
+  const int jmax = min(kLanczosMax, n);
+  for (int j = 0; j < jmax; ++j) {
+    for (int r = tid; r < n; r += blockDim.x) s_x[r] = V[(size_t)j * n + r];
+    __syncthreads();
+    mc_matvec(hii, m, off, a00, s_a0, s_x, w, n);
+    __syncthreads();
+    // classical Gram-Schmidt against V_0..V_j, twice
+    mc_multidot(V, n, j, w, s_dots, s_h);
+    for (int r = tid; r < n; r += blockDim.x) {
+      double t = w[r];
+      for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
+      w[r] = t;
+    }
+    __syncthreads();
+    if (tid <= j) s_h2[tid] = s_h[tid];
+    __syncthreads();
+    mc_multidot(V, n, j, w, s_dots, s_h);
+    double part = 0.0;
+    for (int r = tid; r < n; r += blockDim.x) {
+      double t = w[r];
+      for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
+      w[r] = t;
+      part += t * t;
+    }
+    const double beta = sqrt(wg_sum(part, s_red));
+    if (tid == 0) {
+      s_alpha[j] = s_h2[j] + s_h[j];
+      s_beta[j] = beta;
+    }
+    __syncthreads();
+    iters = j + 1;
+    bool stop = (j + 1 == jmax) || !(beta > 1e-14 * fabs(s_alpha[0]) + 1e-300);
+    if (!stop && (j & 1)) {
+      // residual of the lowest Ritz pair: |beta_j y_j|; the eigenvalue error
+      // is quadratic in it
+      if (tid < 64) {
+        const double l = tri_lowest_wave(s_alpha, s_beta, j + 1, s_y, s_wk);
+        if (tid == 0) {
+          s_bc[0] = l;
+          s_bc[1] = fabs(beta * s_y[j]);
+        }
+      }
+      __syncthreads();
+      if (s_bc[1] <= 1e-10 * fabs(s_bc[0])) stop = true;
+    }
+    if (stop) break;
+    for (int r = tid; r < n; r += blockDim.x) V[(size_t)(j + 1) * n + r] = w[r] / beta;
+    __syncthreads();
+  }
+  if (tid < 64) {
+    const double l = tri_lowest_wave(s_alpha, s_beta, iters, s_y, s_wk);
+    if (tid == 0) s_bc[0] = l;
+  }
+  __syncthreads();
+  const double lam = s_bc[0];
+  // z = sqrt(-lambda) * (V^T y)
+  const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
+  for (int r = tid; r < n; r += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < iters; ++j) acc += V[(size_t)j * n + r] * s_y[j];
+    s_x[r] = zscale * acc;
+  }
+  __syncthreads();
+  // sign: z_0 >= 0 with the c~ column, else z . c_I >= 0
+  double zc_part = 0.0;
+  if (!off)
+    for (int r = tid; r < n; r += blockDim.x) zc_part += s_x[r] * s_c[r];
+  const double zc = wg_sum(zc_part, s_red);
+  const double sgn = off ? (s_x[0] < 0.0 ? -1.0 : 1.0) : (zc < 0.0 ? -1.0 : 1.0);
+  const double gamma = off ? sgn * s_x[0] / nu : 1.0;
+  double eta_i = 0.0;
+  if (tid < m) eta_i = sgn * s_x[off + tid] - gamma * s_c[tid];
+  __syncthreads();
+  if (tid < m) s_x[tid] = eta_i;
+  __syncthreads();
+  double heta_i = 0.0;
+  if (tid < m)
+    for (int j = 0; j < m; ++j) heta_i += hii[(size_t)j * m + tid] * s_x[j];
+  const dd ec = wg_sum_dd(two_prod(eta_i, ci), s_red);
+  const dd eb = wg_sum_dd(two_prod(eta_i, bi), s_red);
+  const dd ee = wg_sum_dd(two_prod(eta_i, eta_i), s_red);
+  const dd ehe = wg_sum_dd(two_prod(eta_i, heta_i), s_red);
+  // mu' = gamma^2 mu + 2 gamma eta.c_I + eta.eta ;
+  // alpha' = gamma^2 alpha + 2 gamma eta.b_I + eta.H_II.eta   (Alg. 2)
+  const dd g2 = two_prod(gamma, gamma);
+  const dd mu_n = dd_add(dd_add(dd_mul(g2, mu), dd_mul_d(ec, 2.0 * gamma)), ee);
+  const dd al_n = dd_add(dd_add(dd_mul(g2, al), dd_mul_d(eb, 2.0 * gamma)), ehe);
+  const double s_new = gamma * s;
+  if (tid < m) {
+    A.eta_out[tid] = eta_i;
+    Slot* sl = A.Tw + A.sel_slot[tid];
+    sl->c = sl->c + eta_i / s_new;  // c_hat_I += eta / s'
+  }
+  if (tid == 0) {
+    ctl->mu_hi = mu_n.hi;
+    ctl->mu_lo = mu_n.lo;
+    ctl->al_hi = al_n.hi;
+    ctl->al_lo = al_n.lo;
+    const double E = dd_val(al_n) / dd_val(mu_n);
+    ctl->energy = E;
+    const double step_norm = sqrt(fmax(0.0, dd_val(ee)));
+    ctl->d = (ctl->steps == 0) ? step_norm : A.theta * ctl->d + (1.0 - A.theta) * step_norm;
+    if (A.tr_E) A.tr_E[ctl->steps] = E;
+    ctl->steps += 1;
+    ctl->steps_this_call += 1;
+    if (ctl->d < A.dx_tol) ctl->stopped = 1;
+    A.st->scale = s_new;
+    A.st->inv_scale = 1.0 / s_new;
+    A.st->gamma = gamma;
+    A.st->lanczos_iters = iters;
+    // doubles reach 2^1023: fold the scale into the table long before that
+    A.st->rescale = fabs(log2(fabs(s_new))) > 400.0 ? 1 : 0;
+    if (!(fabs(s_new) > 1e-250) || !(E == E)) ctl->error |= kErrNumeric;
+  }
+}
+
+// b_hat += H_{:,I} eta / s' with the compression rule; recalculation sums;
+// touched entries marked once in the bitmap and written to this workgroup's
+// candidate page.  grid = (column chunks, k); one column entry per thread.
+struct ScatterArgs {
+  Ham H;
+  Slot* T;
+  uint64_t mask;
+  const uint64_t* sel_a;
+  const uint64_t* sel_b;
+  const double* eta;
+  McState* st;
+  Ctl* ctl;
+  double* recalc;
+  unsigned* bitmap;
+  unsigned* cand;
+  unsigned* cnt;
+  int64_t n_col;
+  double tau;
+  int k;
+};
+
+__global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  __shared__ double s_red[4];
+  __shared__ unsigned s_ins, s_ncand;
+  __shared__ int s_err;
+  const int y = blockIdx.y;
+  const unsigned page = (unsigned)(y * gridDim.x + blockIdx.x);
+  if (A.st->skip) return;
+  const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
+  if (y >= m) {
+    if (threadIdx.x == 0) A.cnt[page] = 0;
+    return;
+  }
+  Ctl* ctl = A.ctl;
+  const uint64_t a = A.sel_a[y], b = A.sel_b[y];
+  const double eta = A.eta[y];
+  const double coef = eta * A.st->inv_scale;
+  make_lists_block(a, b, A.H.N, L);
+  if (threadIdx.x == 0) {
+    s_ins = 0;
+    s_err = 0;
+    s_ncand = 0;
+  }
+  __syncthreads();
+  const Ham H = A.H;
+  if (blockIdx.x == 0) {  // H_DD of this column, shared by the workgroup
+    double part = 0.0;
+    const int nt = diag_terms(L);
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+    for (int offs = 32; offs > 0; offs >>= 1) part += __shfl_xor(part, offs);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += s_red[i];
+      s_diag = t;
+    }
+    __syncthreads();
+  }
+  double recalc = 0.0;
+  int err = 0;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < A.n_col) {
+    uint64_t ja = a, jb = b;
+    const double Hj = e == 0 ? s_diag : column_entry(H, L, a, b, e, 0.0, &ja, &jb);
+    if (Hj != 0.0) {
+      int probes = 0;
+      SlotVal sv;
+      int64_t slot = table_find(A.T, A.mask, ja, jb, &probes, &sv);
+      double cj = slot >= 0 ? sv.c : 0.0;
+      if (e != 0) {
+        const bool big = fabs(eta * Hj) >= A.tau;
+        if (slot < 0 && big) {
+          int ins = 0;
+          slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
+          if (ins) atomicAdd(&s_ins, 1u);
+          cj = slot >= 0 ? sv.c : 0.0;
+        }
+        if (slot >= 0 && (cj != 0.0 || big)) atomic_add_f64(&A.T[slot].b, Hj * coef);
+        if (slot >= 0) {
+          const unsigned bit = 1u << (slot & 31);
+          const unsigned old = atomicOr(&A.bitmap[slot >> 5], bit);
+          if (!(old & bit)) {
+            const unsigned pos = atomicAdd(&s_ncand, 1u);
+            A.cand[(size_t)page * kPage + pos] = (unsigned)slot;
+          }
+        }
+      }
+      recalc += Hj * cj;
+    }
+  }
+  // workgroup sum of the recalculation part, one atomic per workgroup
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int offs = 32; offs > 0; offs >>= 1) recalc += __shfl_xor(recalc, offs);
+  if (lane == 0) s_red[w] = recalc;
+  if (err) atomicOr(&s_err, err);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += s_red[i];
+    atomic_add_f64(&A.recalc[y], r);
+    A.cnt[page] = s_ncand;
+    if (s_ins) atomicAdd(&ctl->occupied, (unsigned long long)s_ins);
+    if (s_ins) atomicAdd(&ctl->inserts, (unsigned long long)s_ins);
+    if (s_err) atomicOr(&ctl->error, s_err);
+  }
+}
+
+// b_hat_I <- recalculated values; I joins the candidates (own pages after the
+// scatter pages); occupancy check
+__global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_slot, double* recalc,
+                                                    unsigned* bitmap, unsigned* cand, unsigned* cnt,
+                                                    McState* st, Ctl* ctl, uint64_t max_entries,
+                                                    unsigned page0, int k) {
+  __shared__ unsigned s_n;
+  if (st->skip) return;
+  const int m = (int)min(st->n_sel, (unsigned long long)k);
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int64_t slot = sel_slot[i];
+    T[slot].b = recalc[i];
+    recalc[i] = 0.0;
+    const unsigned bit = 1u << (slot & 31);
+    const unsigned old = atomicOr(&bitmap[slot >> 5], bit);
+    if (!(old & bit)) {
+      const unsigned pos = atomicAdd(&s_n, 1u);
+      cand[(size_t)page0 * kPage + pos] = (unsigned)slot;
+    }
+  }
+  __syncthreads();
+  const unsigned npg = (unsigned)((k + kPage - 1) / kPage);
+  for (unsigned p = threadIdx.x; p < npg; p += blockDim.x)
+    cnt[page0 + p] = s_n > p * kPage ? min((unsigned)kPage, s_n - p * kPage) : 0u;
+  if (threadIdx.x == 0) {
+    st->n_sel = 0;
+    st->n_pages = (unsigned long long)page0 + npg;
+    if (ctl->occupied > max_entries) ctl->error |= kErrTableFull;
+  }
+}
+
+// fold the lazy scale into every stored entry (only when it drifted far)
+__global__ void __launch_bounds__(256) k_mc_rescale(Slot* T, uint64_t nslots, McState* st, int force) {
+  const int go = force || st->rescale;
+  if (!go) return;
+  const double s = st->scale;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (T[i].ka == kEmpty) continue;
+    T[i].c *= s;
+    T[i].b *= s;
+  }
+}
+
+__global__ void k_mc_rescale_done(McState* st, int force) {
+  if (force || st->rescale) {
+    st->scale = 1.0;
+    st->inv_scale = 1.0;
+    st->rescale = 0;
+  }
+}

@@ -234,3 +234,41 @@ def ground_energy(h, eri, na, nb, dense_max=3000):
         return float(np.linalg.eigvalsh(H.toarray())[0])
     w = sla.eigsh(H, k=1, which="SA", tol=1e-14, return_eigenvectors=False)
     return float(w[0])
+
+
+def rdm12(N, keys_a, keys_b, c):
+    """Spin-summed 1- and 2-RDMs (chemist order) of the normalised vector c
+    over the given determinants, from the C++ operator-application oracle."""
+    L = lib()
+    if not hasattr(L, "_rdm_bound"):
+        dp = ctypes.POINTER(ctypes.c_double)
+        up = ctypes.POINTER(ctypes.c_uint64)
+        L.oracle_rdm12.restype = ctypes.c_int
+        L.oracle_rdm12.argtypes = [ctypes.c_int, ctypes.c_int64, up, up, dp, dp, dp]
+        L.oracle_support_energy.restype = ctypes.c_double
+        L.oracle_support_energy.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, up, up, dp]
+        L._rdm_bound = True
+    ka = np.ascontiguousarray(keys_a, dtype=np.uint64)
+    kb = np.ascontiguousarray(keys_b, dtype=np.uint64)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    g1 = np.zeros((N, N))
+    g2 = np.zeros((N, N, N, N))
+    rc = L.oracle_rdm12(N, len(cc), _p(ka, ctypes.c_uint64), _p(kb, ctypes.c_uint64),
+                        _p(cc, ctypes.c_double), _p(g1, ctypes.c_double), _p(g2, ctypes.c_double))
+    assert rc == 0
+    return g1, g2
+
+
+def support_energy(h, eri, keys_a, keys_b, c):
+    """c^T H c / c^T c restricted to the given determinants."""
+    rdm12(1, np.zeros(1, np.uint64), np.zeros(1, np.uint64), np.ones(1))  # binds the symbols
+    L = lib()
+    N = h.shape[0]
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    ka = np.ascontiguousarray(keys_a, dtype=np.uint64)
+    kb = np.ascontiguousarray(keys_b, dtype=np.uint64)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    return L.oracle_support_energy(N, _p(h, ctypes.c_double), _p(eri, ctypes.c_double), len(cc),
+                                   _p(ka, ctypes.c_uint64), _p(kb, ctypes.c_uint64),
+                                   _p(cc, ctypes.c_double))

@@ -207,6 +207,87 @@ struct Val {
 
 extern "C" {
 
+// Spin-summed reduced density matrices of the normalised vector c over the
+// given determinants (RDMs of Sec. 3.4, eq. (subopt)):
+//   g1[p*N+q]           = sum_s <a+_ps a_qs>
+//   g2[((p*N+q)*N+r)*N+s] = sum_st <a+_ps a+_rt a_st a_qs>
+// by applying every operator string to every determinant of the support and
+// looking the result up (annihilators must hit occupied spin-orbitals, so Q and
+// S range over the occupied ones and P, R over the empty ones plus Q, S).
+int oracle_rdm12(int N, int64_t ndet, const uint64_t* ka, const uint64_t* kb, const double* c,
+                 double* g1, double* g2) {
+  if (N < 1 || N > 64 || ndet < 1) return -1;
+  std::unordered_map<Key, double, KeyHash> sup;
+  double nrm = 0.0;
+  for (int64_t i = 0; i < ndet; ++i) nrm += c[i] * c[i];
+  nrm = sqrt(nrm);
+  for (int64_t i = 0; i < ndet; ++i) sup[Key{ka[i], kb[i]}] += c[i] / nrm;
+  const size_t N2 = (size_t)N * N, N4 = N2 * N2;
+  for (size_t i = 0; i < N2; ++i) g1[i] = 0.0;
+  for (size_t i = 0; i < N4; ++i) g2[i] = 0.0;
+  const int ns = 2 * N;
+  for (const auto& kv : sup) {
+    const Occ x{{kv.first.a, kv.first.b}};
+    const double cj = kv.second;
+    std::vector<int> oc = occ_list(x, N);
+    for (int Q : oc)
+      for (int P = 0; P < ns; ++P) {
+        if ((P >= N) != (Q >= N)) continue;
+        if (P != Q && is_set(x, P, N)) continue;
+        Occ y = x;
+        const char kd[2] = {'c', 'a'};
+        const int ix[2] = {P, Q};
+        int sg = apply_ops(y, 2, kd, ix, N);
+        if (!sg) continue;
+        auto it = sup.find(Key{y.w[0], y.w[1]});
+        if (it == sup.end()) continue;
+        g1[(P % N) * N + (Q % N)] += it->second * sg * cj;
+      }
+    for (int Q : oc)
+      for (int S : oc) {
+        if (Q == S) continue;
+        for (int P = 0; P < ns; ++P) {
+          if ((P >= N) != (Q >= N)) continue;
+          if (P != Q && P != S && is_set(x, P, N)) continue;
+          for (int R = 0; R < ns; ++R) {
+            if ((R >= N) != (S >= N)) continue;
+            if (R == P) continue;
+            if (R != Q && R != S && is_set(x, R, N)) continue;
+            Occ y = x;
+            const char kd[4] = {'c', 'c', 'a', 'a'};
+            const int ix[4] = {P, R, S, Q};
+            int sg = apply_ops(y, 4, kd, ix, N);
+            if (!sg) continue;
+            auto it = sup.find(Key{y.w[0], y.w[1]});
+            if (it == sup.end()) continue;
+            g2[(((size_t)(P % N) * N + (Q % N)) * N + (R % N)) * N + (S % N)] += it->second * sg * cj;
+          }
+        }
+      }
+  }
+  return 0;
+}
+
+// c^T H c / c^T c over the given support (integrals may be perturbed by the
+// caller): each support column from get_column, entries looked up in the support
+double oracle_support_energy(int N, const double* h, const double* eri, int64_t ndet,
+                             const uint64_t* ka, const uint64_t* kb, const double* c) {
+  Ham H{N, h, eri};
+  std::unordered_map<Key, double, KeyHash> sup;
+  for (int64_t i = 0; i < ndet; ++i) sup[Key{ka[i], kb[i]}] += c[i];
+  std::vector<Elem> col;
+  long double num = 0.0L, den = 0.0L;
+  for (const auto& kv : sup) {
+    column(H, kv.first, col);
+    for (const Elem& e : col) {
+      auto it = sup.find(e.k);
+      if (it != sup.end()) num += (long double)it->second * e.v * kv.second;
+    }
+    den += (long double)kv.second * kv.second;
+  }
+  return (double)(num / den);
+}
+
 double oracle_line_search(double v1, double v2, double v3) { return line_search(v1, v2, v3); }
 
 double oracle_entry(int N, const double* h, const double* eri, uint64_t bra_a, uint64_t bra_b,

@@ -92,3 +92,27 @@ def test_orbital_gradient_by_finite_difference(system):
     # at the exact FCI ground state of the full orbital space the energy is
     # invariant under rotations of the orbitals, so kappa vanishes
     assert np.max(np.abs(kap)) < 1e-9
+
+
+def test_cpp_rdm_matches_brute_force(system):
+    """The C++ operator-application RDMs equal the Python brute force, for the
+    ground state and for a random sparse vector."""
+    from oracle import cd as ocd
+
+    N, na, nb, h, eri, E0, v0, B, g1, g2 = system
+    ka = np.array([k[0] for k in B], np.uint64)
+    kb = np.array([k[1] for k in B], np.uint64)
+    G1, G2 = ocd.rdm12(N, ka, kb, v0)
+    np.testing.assert_allclose(G1, g1, atol=1e-13)
+    np.testing.assert_allclose(G2, g2, atol=1e-13)
+    rng = np.random.default_rng(11)
+    c = rng.normal(size=len(B)) * (rng.random(len(B)) < 0.4)
+    keep = c != 0.0
+    P1, P2 = fci.rdm12([B[i] for i in range(len(B)) if keep[i]], c[keep], N)
+    Q1, Q2 = ocd.rdm12(N, ka[keep], kb[keep], c[keep])
+    np.testing.assert_allclose(Q1, P1, atol=1e-13)
+    np.testing.assert_allclose(Q2, P2, atol=1e-13)
+    # the support energy equals the Rayleigh quotient of the dense matrix
+    H, _ = fci.dense_H(h, eri, N, na, nb)
+    cv = np.where(keep, c, 0.0)
+    assert abs(ocd.support_energy(h, eri, ka[keep], kb[keep], c[keep]) - cv @ H @ cv / (cv @ cv)) < 1e-12

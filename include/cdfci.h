@@ -124,17 +124,27 @@ int cdfci_step_trace(cdfci_ctx* ctx, int64_t nsteps, double* energy, uint64_t* s
  * c^T H c / c^T c by applying H to the stored c on the device. */
 int cdfci_energy(cdfci_ctx* ctx, int exact, double* energy);
 
-/* Reverse pass of E = c^T H c / c^T c with c held fixed (pattern (a)):
- * the truncated, normalised wavefunction is the top_n stored determinants by
- * |c| (top_n <= 0: all).  Outputs, host, any may be NULL:
+/* Reverse pass of E = c^T H c / c^T c with c held fixed, the energy of the
+ * variational objective of Sec. 3.4 eq. (subopt) at U = I, whose 1- and 2-RDMs
+ * feed the orbital optimisation (Alg. 4).  The wavefunction is the top_n
+ * stored determinants by |c| (equal |c| ordered by the smaller key; top_n <= 0
+ * or above the count: every entry with c != 0), normalised.  Outputs, host,
+ * any may be NULL:
+ *   energy[0]    = sum h gamma + 1/2 sum (pq|rs) Gamma, energy[1] = the same
+ *                  quotient evaluated directly from Hamiltonian entries;
  *   dh[p*N+q]    = grad_E * gamma_pq,  gamma_pq = sum_s <a+_ps a_qs>;
- *   deri[pqrs]   = grad_E * Gamma_pqrs / 2,
+ *   deri[pqrs]   = grad_E * Gamma_pqrs / 2 (N^4 doubles),
  *                  Gamma_pqrs = sum_st <a+_ps a+_rt a_st a_qs> (chemist order);
  *   kappa[p*N+q] = grad_E * 2 (F_pq - F_qp), F_pq = sum_r h_pr gamma_rq
- *                  + sum_rst (pr|st) Gamma_qrst, the gradient of E(U = exp(K))
- *                  in K_pq (p > q) for rotated orbitals (Sec. 3.4, eq. (subopt)). */
-int cdfci_rdm_backward(cdfci_ctx* ctx, double grad_E, int64_t top_n, double* dh, double* deri,
-                       double* kappa);
+ *                  + sum_rst (pr|st) Gamma_qrst: the derivative of E(h', eri')
+ *                  with h' = U^T h U, U = exp(K), K = -K^T, in K_pq (p > q).
+ * gamma and Gamma are the derivatives of E in each tensor element (the
+ * symmetric images of one integral each get their own share).  c is not
+ * changed.  CDFCI_ERR_INVALID_ARG if no stored c is nonzero;
+ * CDFCI_ERR_UNSUPPORTED if more than 4096 entries share the |c| at the top_n
+ * boundary.  Device memory used: two N^4 arrays plus a table of the support. */
+int cdfci_rdm_backward(cdfci_ctx* ctx, double grad_E, int64_t top_n, double* energy, double* dh,
+                       double* deri, double* kappa);
 
 /* get_column (Sec. 4.1.1): every (D', H_{D',D}) for D' = D and all single and
  * double excitations of D, in the library's enumeration order with the
@@ -148,8 +158,10 @@ int cdfci_column(cdfci_ctx* ctx, const uint64_t key[2], uint64_t* keys, double* 
 int cdfci_entry(cdfci_ctx* ctx, const uint64_t k1[2], const uint64_t k2[2], double* value);
 
 /* Copy the stored determinants out: keys 2*cap uint64 (alpha, beta), c and b
- * values (true scale).  top_n > 0 keeps the top_n by |c|; top_n <= 0 keeps all
- * entries.  *count = entries available; at most cap are written. */
+ * values (true scale).  top_n > 0 keeps the top_n by |c| among the entries
+ * with c != 0, chosen as cdfci_rdm_backward chooses its support (in no
+ * particular order); top_n <= 0 keeps every stored entry.  *count = entries
+ * available; at most cap are written. */
 int cdfci_export(cdfci_ctx* ctx, int64_t top_n, uint64_t* keys, double* c, double* b, int64_t cap,
                  int64_t* count);
 

@@ -152,14 +152,16 @@ def cdfci_energy(ctx, exact=0):
 
 
 def cdfci_rdm_backward(ctx, grad_E=1.0, top_n=0, want_eri=True):
+    """Returns (energy[2], dh, deri or None, kappa); see include/cdfci.h."""
     N = ctx.N
+    energy = np.zeros(2)
     dh = np.zeros((N, N))
     deri = np.zeros((N, N, N, N)) if want_eri else None
     kap = np.zeros((N, N))
-    _check(_lib.load().cdfci_rdm_backward(ctx.handle, float(grad_E), int(top_n), _dp(dh),
+    _check(_lib.load().cdfci_rdm_backward(ctx.handle, float(grad_E), int(top_n), _dp(energy), _dp(dh),
                                           _dp(deri) if deri is not None else None, _dp(kap)),
            "cdfci_rdm_backward")
-    return dh, deri, kap
+    return energy, dh, deri, kap
 
 
 def cdfci_column(ctx, key):

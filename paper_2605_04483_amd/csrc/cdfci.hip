@@ -807,6 +807,7 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
 }
 
 #include "mcd_kernels.h"
+#include "rdm_kernels.h"
 
 }  // namespace
 
@@ -1051,6 +1052,79 @@ std::vector<std::pair<int, int>> lattice_bonds(const int* dims, int ndim) {
     }
   }
   return bonds;
+}
+
+// device buffers owned by one library call, released when it returns
+// (hipFree waits for the work that uses them)
+struct CallBufs {
+  std::vector<void*> ptrs;
+  ~CallBufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t alloc(T** out, uint64_t n) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<uint64_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(p);
+    *out = (T*)p;
+    return e;
+  }
+};
+
+// Slot ids of the top_n stored determinants by |c| (equal |c| ordered by the
+// smaller key), or of every entry with c != 0 when top_n <= 0 or exceeds that
+// count, into *sel (device, owned by bufs); the count into *n_out.  Uses the
+// radix select of the multicoordinate step keyed on |c|.
+int select_support(cdfci_ctx* c, int64_t top_n, CallBufs& bufs, int64_t** sel, int64_t* n_out) {
+  hipStream_t s = c->stream;
+  if (c->mode == 1) {  // true values: fold the multicoordinate lazy scale in
+    k_mc_rescale<<<2048, 256, 0, s>>>(c->T, c->nslots, c->mst, 1);
+    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
+  }
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  const uint64_t pages = (h.occupied + kPage) / kPage;
+  const uint64_t cap = pages * kPage;
+  McState* st;
+  unsigned *cand, *cnt, *hist, *ties;
+  unsigned long long* gkey;
+  HIP_TRY(bufs.alloc(&st, 1));
+  HIP_TRY(bufs.alloc(&cand, cap));
+  HIP_TRY(bufs.alloc(&cnt, pages));
+  HIP_TRY(bufs.alloc(&gkey, cap));
+  HIP_TRY(bufs.alloc(&hist, kRadixBins));
+  HIP_TRY(bufs.alloc(&ties, kMaxTies));
+  HIP_TRY(hipMemsetAsync(st, 0, sizeof(McState), s));
+  HIP_TRY(hipMemsetAsync(hist, 0, kRadixBins * sizeof(unsigned), s));
+  k_rdm_nonzero<<<2048, 256, 0, s>>>(c->T, c->nslots, cand, st, cap);
+  HIP_TRY(hipGetLastError());
+  unsigned long long nnz = 0;
+  HIP_TRY(hipMemcpyAsync(&nnz, &st->n_dense, sizeof(nnz), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (nnz == 0 || nnz > cap) return CDFCI_ERR_INVALID_ARG;
+  const int64_t n = (top_n > 0 && (uint64_t)top_n < nnz) ? top_n : (int64_t)nnz;
+  if (n > (int64_t)0x7fffffff) return CDFCI_ERR_UNSUPPORTED;
+  k_mc_dense_pages<<<256, 256, 0, s>>>(cnt, st, cap);
+  uint64_t *sa, *sb;
+  HIP_TRY(bufs.alloc(sel, n));
+  HIP_TRY(bufs.alloc(&sa, n));
+  HIP_TRY(bufs.alloc(&sb, n));
+  const int hb = 1024;
+  for (int pass = 0; pass < kRadixPasses; ++pass) {
+    k_mc_hist<<<hb, 256, 0, s>>>(c->T, cand, cnt, gkey, c->ctl, st, hist, pass, 1);
+    k_mc_scan<<<1, 256, 0, s>>>(hist, st, cnt, (int)n, pass);
+  }
+  k_mc_gather<<<hb, 256, 0, s>>>(cand, cnt, gkey, st, *sel, ties);
+  k_mc_ties<<<1, 256, 0, s>>>(c->T, st, *sel, sa, sb, ties, (int)n);
+  HIP_TRY(hipGetLastError());
+  unsigned long long got = 0;
+  HIP_TRY(hipMemcpyAsync(&got, &st->n_sel, sizeof(got), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // more than kMaxTies entries of exactly the threshold |c| are not ranked
+  if ((int64_t)got != n) return CDFCI_ERR_UNSUPPORTED;
+  *n_out = n;
+  return 0;
 }
 
 }  // namespace
@@ -1331,7 +1405,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
     for (int pass = 0; pass < kRadixPasses; ++pass) {
       k_mc_hist<<<hist_blocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist,
-                                            pass);
+                                            pass, 0);
       k_mc_scan<<<1, 256, 0, s>>>(c->hist, c->mst, c->cnt, k, pass);
     }
     k_mc_gather<<<hist_blocks, 256, 0, s>>>(c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties);
@@ -1440,8 +1514,78 @@ int cdfci_energy(cdfci_ctx* c, int exact, double* energy) {
   return 0;
 }
 
-int cdfci_rdm_backward(cdfci_ctx*, double, int64_t, double*, double*, double*) {
-  return CDFCI_ERR_UNSUPPORTED;
+int cdfci_rdm_backward(cdfci_ctx* c, double grad_E, int64_t top_n, double* energy, double* dh,
+                       double* deri, double* kappa) {
+  if (!c) return CDFCI_ERR_INVALID_ARG;
+  CallBufs bufs;
+  int64_t* sel = nullptr;
+  int64_t n = 0;
+  int rc = select_support(c, top_n, bufs, &sel, &n);
+  if (rc) return rc;
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const size_t N2 = (size_t)N * N, N4 = N2 * N2;
+  const Ham H = ham_of(c);
+  // normalisation and the support table (load <= 1/2)
+  double* part;
+  HIP_TRY(bufs.alloc(&part, 2 * 1024 + 8));
+  k_rdm_norm<<<1024, 256, 0, s>>>(c->T, sel, n, part);
+  k_sum_partials<<<1, 1, 0, s>>>(part, part, 1024, part + 2048);
+  uint64_t ss = 1024;
+  while (ss < 2 * (uint64_t)n) ss <<= 1;
+  Slot* S;
+  uint64_t *sa, *sb;
+  double *sc, *Y1, *Z, *g1, *g2, *F2, *dkap, *ddh;
+  int* err;
+  HIP_TRY(bufs.alloc(&S, ss));
+  HIP_TRY(bufs.alloc(&sa, n));
+  HIP_TRY(bufs.alloc(&sb, n));
+  HIP_TRY(bufs.alloc(&sc, n));
+  HIP_TRY(bufs.alloc(&err, 1));
+  HIP_TRY(bufs.alloc(&Y1, N2));
+  HIP_TRY(bufs.alloc(&Z, N4));
+  HIP_TRY(bufs.alloc(&g1, N2));
+  HIP_TRY(bufs.alloc(&g2, N4));
+  HIP_TRY(bufs.alloc(&F2, N2));
+  HIP_TRY(bufs.alloc(&dkap, N2));
+  HIP_TRY(bufs.alloc(&ddh, N2));
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(Y1, 0, N2 * sizeof(double), s));
+  HIP_TRY(hipMemsetAsync(Z, 0, N4 * sizeof(double), s));
+  HIP_TRY(hipMemsetAsync(F2, 0, N2 * sizeof(double), s));
+  double* e_acc = part + 2048 + 2;  // direct c^T H c of the normalised support
+  HIP_TRY(hipMemsetAsync(e_acc, 0, sizeof(double), s));
+  k_clear_table<<<1024, 256, 0, s>>>(S, ss);
+  k_rdm_build<<<1024, 256, 0, s>>>(c->T, sel, n, part + 2048, S, ss - 1, sa, sb, sc, err);
+  // pair and diagonal contributions
+  k_rdm_pairs<<<(int)std::min<int64_t>(n, 16384), 256, 0, s>>>(H, S, ss - 1, sa, sb, sc, n, c->n_col, Y1,
+                                                                Z, e_acc);
+  k_rdm_symmetrize<<<2048, 256, 0, s>>>(Y1, Z, N, g1, g2);
+  const size_t shm = (size_t)(N + 2 * N * N) * sizeof(double);
+  k_rdm_diag<<<(int)std::min<int64_t>(n, 512), 256, shm, s>>>(H, sa, sb, sc, n, g1, g2, e_acc);
+  // kappa: F2 on the FP64 matrix cores, then F, kappa and dh
+  const int tiles = (N + 15) / 16;
+  const int slices = (int)(((int64_t)N * N * N + kKappaSlice - 1) / kKappaSlice);
+  k_kappa_mfma<<<dim3(tiles * tiles, slices), 64, 0, s>>>(c->d_eri, g2, N, F2);
+  k_kappa_finish<<<(int)((N2 + 255) / 256), 256, 0, s>>>(c->d_h, g1, F2, N, grad_E, dkap, ddh);
+  // energy from the RDMs; g2 becomes deri
+  k_rdm_outputs<<<1024, 256, 0, s>>>(c->d_h, c->d_eri, g1, g2, N, grad_E, part + 1024);
+  k_sum_partials<<<1, 1, 0, s>>>(part + 1024, part + 1024, 1024, part + 2048 + 4);
+  HIP_TRY(hipGetLastError());
+  int herr = 0;
+  double he[8];
+  HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(he, part + 2048, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (dh) HIP_TRY(hipMemcpyAsync(dh, ddh, N2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (kappa) HIP_TRY(hipMemcpyAsync(kappa, dkap, N2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (deri) HIP_TRY(hipMemcpyAsync(deri, g2, N4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return CDFCI_ERR_TABLE_FULL;
+  if (energy) {
+    energy[0] = he[4];
+    energy[1] = he[2];
+  }
+  return 0;
 }
 
 int cdfci_column(cdfci_ctx* c, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
@@ -1482,8 +1626,30 @@ int cdfci_entry(cdfci_ctx* c, const uint64_t k1[2], const uint64_t k2[2], double
 int cdfci_export(cdfci_ctx* c, int64_t top_n, uint64_t* keys, double* cv, double* bv, int64_t cap,
                  int64_t* count) {
   if (!c || !count) return CDFCI_ERR_INVALID_ARG;
-  if (top_n > 0) return CDFCI_ERR_UNSUPPORTED;
   hipStream_t s = c->stream;
+  if (top_n > 0) {
+    CallBufs bufs;
+    int64_t* sel = nullptr;
+    int64_t n = 0;
+    int rc = select_support(c, top_n, bufs, &sel, &n);
+    if (rc) return rc;
+    *count = n;
+    const int64_t m = std::min(n, cap);
+    if (m > 0 && keys && cv && bv) {
+      uint64_t* dk;
+      double *dc, *db;
+      HIP_TRY(bufs.alloc(&dk, 2 * m));
+      HIP_TRY(bufs.alloc(&dc, m));
+      HIP_TRY(bufs.alloc(&db, m));
+      k_gather<<<1024, 256, 0, s>>>(c->T, sel, m, dk, dc, db);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(keys, dk, 2 * m * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(cv, dc, m * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(bv, db, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return 0;
+  }
   if (c->mode == 1) {  // true values: fold the multicoordinate lazy scale in
     k_mc_rescale<<<2048, 256, 0, s>>>(c->T, c->nslots, c->mst, 1);
     k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
@@ -1552,6 +1718,7 @@ const char* cdfci_strerror(int code) {
     case CDFCI_ERR_HIP: return "HIP runtime error";
     case CDFCI_ERR_BARRIER: return "device-wide barrier timed out";
     case CDFCI_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case CDFCI_ERR_NUMERIC: return "non-finite value in a multicoordinate step";
     default: return "unknown error";
   }
 }

@@ -424,83 +424,118 @@ __device__ inline double single_value(const Ham& H, int p, int r, const int8_t* 
   return v;
 }
 
-// Entry e of get_column(D) in the library's enumeration order:
-//   0                      diagonal
-//   alpha singles          na*va   (occupied index major)
-//   beta singles           nb*vb
-//   alpha-alpha doubles    C(na,2)*C(va,2)   (occupied pair major)
-//   beta-beta doubles      C(nb,2)*C(vb,2)
-//   alpha-beta doubles     na*va*nb*vb       (alpha single major)
-// Writes the excited key and returns H_{D',D}.  `diag` supplies H_DD for e = 0.
-__device__ inline double column_entry(const Ham& H, const Lists& L, uint64_t a, uint64_t b,
-                                      int64_t e, double diag, uint64_t* oa_out, uint64_t* ob_out) {
-  if (e == 0) {
-    *oa_out = a;
-    *ob_out = b;
-    return diag;
-  }
+// Excitation of entry e of get_column(D), in the library's enumeration order:
+//   0                      diagonal                       type 0
+//   alpha singles          na*va   (occupied index major)  type 1: p -> r
+//   beta singles           nb*vb                           type 2: p -> r
+//   alpha-alpha doubles    C(na,2)*C(va,2) (occupied pair major) type 3: p<q -> r<s
+//   beta-beta doubles      C(nb,2)*C(vb,2)                 type 4: p<q -> r<s
+//   alpha-beta doubles     na*va*nb*vb (alpha single major) type 5: p->r alpha, q->s beta
+// The fermionic phase `neg` is that of a+_r a_p (singles) or a+_r a+_s a_q a_p
+// (doubles) on D; the excited key is written to (oa, ob).  Column sizes stay
+// below 2^31 for at most 63 orbitals, so the decoding uses 32-bit arithmetic.
+struct Excitation {
+  int type, p, q, r, s, neg;
+};
+
+__device__ inline Excitation decode_excitation(const Lists& L, uint64_t a, uint64_t b, uint32_t e,
+                                               uint64_t* oa, uint64_t* ob) {
+  Excitation x{0, 0, 0, 0, 0, 0};
+  *oa = a;
+  *ob = b;
+  if (e == 0) return x;
   e -= 1;
-  const int64_t sa = (int64_t)L.na * L.nva;
+  const uint32_t sa = (uint32_t)(L.na * L.nva);
   if (e < sa) {
-    int i = (int)(e / L.nva), x = (int)(e % L.nva);
-    int p = L.oa[i], r = L.va[x];
-    *oa_out = a ^ (1ull << p) ^ (1ull << r);
-    *ob_out = b;
-    double v = single_value(H, p, r, L.oa, L.na, L.ob, L.nb);
-    return parity_between(a, p, r) ? -v : v;
+    x.type = 1;
+    x.p = L.oa[e / L.nva];
+    x.r = L.va[e % L.nva];
+    *oa = a ^ (1ull << x.p) ^ (1ull << x.r);
+    x.neg = parity_between(a, x.p, x.r);
+    return x;
   }
   e -= sa;
-  const int64_t sb = (int64_t)L.nb * L.nvb;
+  const uint32_t sb = (uint32_t)(L.nb * L.nvb);
   if (e < sb) {
-    int i = (int)(e / L.nvb), x = (int)(e % L.nvb);
-    int p = L.ob[i], r = L.vb[x];
-    *oa_out = a;
-    *ob_out = b ^ (1ull << p) ^ (1ull << r);
-    double v = single_value(H, p, r, L.ob, L.nb, L.oa, L.na);
-    return parity_between(b, p, r) ? -v : v;
+    x.type = 2;
+    x.p = L.ob[e / L.nvb];
+    x.r = L.vb[e % L.nvb];
+    *ob = b ^ (1ull << x.p) ^ (1ull << x.r);
+    x.neg = parity_between(b, x.p, x.r);
+    return x;
   }
   e -= sb;
-  const int64_t qa = (int64_t)L.nva * (L.nva - 1) / 2;
-  const int64_t daa = (int64_t)L.na * (L.na - 1) / 2 * qa;
+  const uint32_t qa = (uint32_t)(L.nva * (L.nva - 1) / 2);
+  const uint32_t daa = (uint32_t)(L.na * (L.na - 1) / 2) * qa;
   if (e < daa) {
-    int po = (int)(e / qa), pv = (int)(e % qa);
-    int i, j, x, y;
-    pair_decode(po, i, j);
-    pair_decode(pv, x, y);
-    int p = L.oa[i], q = L.oa[j], r = L.va[x], s = L.va[y];
-    uint64_t a1 = a ^ (1ull << p) ^ (1ull << r);
-    int sg = parity_between(a, p, r) ^ parity_between(a1, q, s);
-    *oa_out = a1 ^ (1ull << q) ^ (1ull << s);
-    *ob_out = b;
-    double v = ERI(H, r, p, s, q) - ERI(H, r, q, s, p);
-    return sg ? -v : v;
+    int i, j, u, v;
+    pair_decode((int)(e / qa), i, j);
+    pair_decode((int)(e % qa), u, v);
+    x.type = 3;
+    x.p = L.oa[i];
+    x.q = L.oa[j];
+    x.r = L.va[u];
+    x.s = L.va[v];
+    const uint64_t a1 = a ^ (1ull << x.p) ^ (1ull << x.r);
+    x.neg = parity_between(a, x.p, x.r) ^ parity_between(a1, x.q, x.s);
+    *oa = a1 ^ (1ull << x.q) ^ (1ull << x.s);
+    return x;
   }
   e -= daa;
-  const int64_t qb = (int64_t)L.nvb * (L.nvb - 1) / 2;
-  const int64_t dbb = (int64_t)L.nb * (L.nb - 1) / 2 * qb;
+  const uint32_t qb = (uint32_t)(L.nvb * (L.nvb - 1) / 2);
+  const uint32_t dbb = (uint32_t)(L.nb * (L.nb - 1) / 2) * qb;
   if (e < dbb) {
-    int po = (int)(e / qb), pv = (int)(e % qb);
-    int i, j, x, y;
-    pair_decode(po, i, j);
-    pair_decode(pv, x, y);
-    int p = L.ob[i], q = L.ob[j], r = L.vb[x], s = L.vb[y];
-    uint64_t b1 = b ^ (1ull << p) ^ (1ull << r);
-    int sg = parity_between(b, p, r) ^ parity_between(b1, q, s);
-    *oa_out = a;
-    *ob_out = b1 ^ (1ull << q) ^ (1ull << s);
-    double v = ERI(H, r, p, s, q) - ERI(H, r, q, s, p);
-    return sg ? -v : v;
+    int i, j, u, v;
+    pair_decode((int)(e / qb), i, j);
+    pair_decode((int)(e % qb), u, v);
+    x.type = 4;
+    x.p = L.ob[i];
+    x.q = L.ob[j];
+    x.r = L.vb[u];
+    x.s = L.vb[v];
+    const uint64_t b1 = b ^ (1ull << x.p) ^ (1ull << x.r);
+    x.neg = parity_between(b, x.p, x.r) ^ parity_between(b1, x.q, x.s);
+    *ob = b1 ^ (1ull << x.q) ^ (1ull << x.s);
+    return x;
   }
   e -= dbb;
-  // alpha-beta: alpha single index major, beta single minor
-  const int64_t sbb = (int64_t)L.nb * L.nvb;
-  int64_t ia = e / sbb, ib = e % sbb;
-  int p = L.oa[ia / L.nva], r = L.va[ia % L.nva];
-  int q = L.ob[ib / L.nvb], s = L.vb[ib % L.nvb];
-  *oa_out = a ^ (1ull << p) ^ (1ull << r);
-  *ob_out = b ^ (1ull << q) ^ (1ull << s);
-  double v = ERI(H, r, p, s, q);
-  return (parity_between(a, p, r) ^ parity_between(b, q, s)) ? -v : v;
+  const uint32_t sbb = (uint32_t)(L.nb * L.nvb);
+  const uint32_t ia = e / sbb, ib = e % sbb;
+  x.type = 5;
+  x.p = L.oa[ia / L.nva];
+  x.r = L.va[ia % L.nva];
+  x.q = L.ob[ib / L.nvb];
+  x.s = L.vb[ib % L.nvb];
+  *oa = a ^ (1ull << x.p) ^ (1ull << x.r);
+  *ob = b ^ (1ull << x.q) ^ (1ull << x.s);
+  x.neg = parity_between(a, x.p, x.r) ^ parity_between(b, x.q, x.s);
+  return x;
+}
+
+// Entry e of get_column(D): writes the excited key and returns H_{D',D}
+// (eq. (entry)); `diag` supplies H_DD for e = 0.
+__device__ inline double column_entry(const Ham& H, const Lists& L, uint64_t a, uint64_t b,
+                                      int64_t e, double diag, uint64_t* oa_out, uint64_t* ob_out) {
+  const Excitation x = decode_excitation(L, a, b, (uint32_t)e, oa_out, ob_out);
+  double v;
+  switch (x.type) {
+    case 0:
+      return diag;
+    case 1:
+      v = single_value(H, x.p, x.r, L.oa, L.na, L.ob, L.nb);
+      break;
+    case 2:
+      v = single_value(H, x.p, x.r, L.ob, L.nb, L.oa, L.na);
+      break;
+    case 3:
+    case 4:
+      v = ERI(H, x.r, x.p, x.s, x.q) - ERI(H, x.r, x.q, x.s, x.p);
+      break;
+    default:
+      v = ERI(H, x.r, x.p, x.s, x.q);
+      break;
+  }
+  return x.neg ? -v : v;
 }
 
 // get_entry: H_{bra,ket} by classifying the difference of the two keys.

@@ -54,6 +54,11 @@ __device__ __forceinline__ unsigned long long g_key(const Slot& s, double mu) {
   return (unsigned long long)__double_as_longlong(g);
 }
 
+// |c| as an ordered key (selection of the largest coefficients)
+__device__ __forceinline__ unsigned long long c_key(const Slot& s) {
+  return (unsigned long long)__double_as_longlong(fabs(s.c));
+}
+
 // start of a step: skip it if an error is pending or the stopping rule fired
 __global__ void k_mc_begin(McState* st, const Ctl* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) st->skip = (ctl->error || ctl->stopped) ? 1 : 0;
@@ -83,11 +88,12 @@ __global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* 
   }
 }
 
-// radix-select histogram pass; pass 0 also computes the keys
+// radix-select histogram pass; pass 0 also computes the keys (|g| for the
+// multicoordinate selection, |c| when by_c is set)
 __global__ void __launch_bounds__(256) k_mc_hist(const Slot* T, const unsigned* cand,
                                                  const unsigned* cnt, unsigned long long* gkey,
                                                  const Ctl* ctl, const McState* st, unsigned* hist,
-                                                 int pass) {
+                                                 int pass, int by_c) {
   __shared__ unsigned h[kRadixBins];
   if (st->skip) return;
   if (pass > 0 && (st->all || st->done)) return;
@@ -103,7 +109,7 @@ __global__ void __launch_bounds__(256) k_mc_hist(const Slot* T, const unsigned* 
     if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
     unsigned long long key;
     if (pass == 0) {
-      key = g_key(T[cand[i]], mu);
+      key = by_c ? c_key(T[cand[i]]) : g_key(T[cand[i]], mu);
       gkey[i] = key;
     } else {
       key = gkey[i];

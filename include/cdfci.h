@@ -172,6 +172,77 @@ int cdfci_export(cdfci_ctx* ctx, int64_t top_n, uint64_t* keys, double* c, doubl
 int cdfci_phase_times(cdfci_ctx* ctx, double* seconds);
 
 int cdfci_free(cdfci_ctx* ctx);
+
+/* ---- Batches of periodic Hubbard lattices (Sec. 2.2, Alg. 1) ----------------
+ * Many independent instances of uneven size advance together in one
+ * persistent kernel: one wavefront holds one instance at a time (a Hubbard
+ * column has at most 1 + 2 * bonds entries) and waves take instances from a
+ * queue; the host replays a captured HIP graph of such launches until every
+ * instance has stopped or used its step budget.  Each instance is an ordinary
+ * context created as by cdfci_init_hubbard (Neel determinant plus subspace
+ * start), so it can be inspected with cdfci_energy, cdfci_export and the like
+ * through cdfci_batch_context. */
+typedef struct {
+  int dims[3];   /* sites per direction (row-major site index); entries past ndim ignored */
+  int ndim;      /* 1..3; at most 63 sites and 64 distinct bonds */
+  int n_alpha, n_beta;
+  int reserved;
+  double t, U;   /* hopping -t on each distinct nearest-neighbour pair, on-site U */
+} cdfci_hubbard_spec;
+
+typedef struct cdfci_batch cdfci_batch; /* opaque, library-owned */
+
+typedef struct {
+  uint64_t table_slots;      /* per instance (power of two); 0 = the smallest power of two
+                                >= FCI dimension / load_factor, at least 2^10, at most
+                                max_table_slots */
+  uint64_t max_table_slots;  /* 0 = 2^22 */
+  double load_factor;        /* 0 = 0.79 */
+  double z_threshold;        /* tau, as in cdfci_opts */
+  double dx_damping;         /* 0 = 0.9 */
+  double dx_threshold;       /* per-instance stopping rule; 0 = never */
+  int64_t chunk_steps;       /* steps an instance runs per visit of a wave; 0 = 1024 */
+  int launches_per_graph;    /* persistent launches captured in the replayed graph; 0 = 4 */
+  int waves;                 /* wavefronts per launch; 0 = one per instance (at most 8192) */
+  void* stream;              /* hipStream_t; NULL = a stream of the batch's own */
+} cdfci_batch_opts;
+
+typedef struct {
+  int64_t steps;           /* iterations this call, summed over instances */
+  int64_t elements;        /* column entries enumerated this call (nonzero hops + diagonal) */
+  int32_t running;         /* instances that used their whole budget */
+  int32_t stopped;         /* instances stopped by dx_threshold (now or before) */
+  int32_t failed;          /* instances with an error (table full) */
+  int32_t graph_replays;
+  double seconds;          /* device time of the call */
+} cdfci_batch_stats;
+
+/* Create count instances (count >= 1).  Errors of one instance's creation
+ * abort the whole call (nothing is kept). */
+int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const cdfci_batch_opts* opts,
+                             cdfci_batch** out);
+
+/* Advance every instance by up to max_steps iterations (fewer if it stops or
+ * fails); returns after completion.  out may be NULL. */
+int cdfci_step_batch(cdfci_batch* batch, int64_t max_steps, cdfci_batch_stats* out);
+
+/* Per instance (host arrays of length count, any may be NULL): energy
+ * alpha/mu, iterations since init, status 1 = stopped by dx_threshold,
+ * 0 = still running, negative = CDFCI_ERR_* of that instance. */
+int cdfci_batch_results(cdfci_batch* batch, double* energy, int64_t* steps, int* status);
+
+/* Advance only `instance` by up to nsteps iterations, recording per iteration
+ * the energy and the chosen determinant (host arrays of length nsteps, any may
+ * be NULL).  For parity tests. */
+int cdfci_batch_trace(cdfci_batch* batch, int instance, int64_t nsteps, double* energy,
+                      uint64_t* sel_alpha, uint64_t* sel_beta);
+
+/* Borrow the context of one instance (owned by the batch: do not free it, do
+ * not step it while the batch runs). */
+int cdfci_batch_context(cdfci_batch* batch, int instance, cdfci_ctx** ctx);
+
+int cdfci_free_batch(cdfci_batch* batch);
+
 const char* cdfci_strerror(int code);
 const char* cdfci_last_error(void);
 

@@ -5,10 +5,14 @@ this package is its Python binding: `api` mirrors include/cdfci.h entry point
 by entry point.  Importing the package does not load the library; the first
 call does, and fails loudly if it has not been built.
 """
-from .api import (CDFCIError, Context, cdfci_column, cdfci_energy, cdfci_entry, cdfci_export,
-                  cdfci_free, cdfci_init, cdfci_init_hubbard, cdfci_phase_times, cdfci_rdm_backward, cdfci_step,
-                  cdfci_step_energies, cdfci_step_trace, cdfci_strerror, cdfci_workspace_size, make_opts)
+from .api import (Batch, CDFCIError, Context, cdfci_batch_context, cdfci_batch_results, cdfci_batch_trace,
+                  cdfci_column, cdfci_energy, cdfci_entry, cdfci_export, cdfci_free, cdfci_free_batch,
+                  cdfci_init, cdfci_init_hubbard, cdfci_init_hubbard_batch, cdfci_phase_times,
+                  cdfci_rdm_backward, cdfci_step, cdfci_step_batch, cdfci_step_energies, cdfci_step_trace,
+                  cdfci_strerror, cdfci_workspace_size, make_opts)
 
-__all__ = ["CDFCIError", "Context", "cdfci_column", "cdfci_energy", "cdfci_entry", "cdfci_export",
-           "cdfci_free", "cdfci_init", "cdfci_init_hubbard", "cdfci_phase_times", "cdfci_rdm_backward", "cdfci_step",
-           "cdfci_step_energies", "cdfci_step_trace", "cdfci_strerror", "cdfci_workspace_size", "make_opts"]
+__all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch_results", "cdfci_batch_trace",
+           "cdfci_column", "cdfci_energy", "cdfci_entry", "cdfci_export", "cdfci_free", "cdfci_free_batch",
+           "cdfci_init", "cdfci_init_hubbard", "cdfci_init_hubbard_batch", "cdfci_phase_times",
+           "cdfci_rdm_backward", "cdfci_step", "cdfci_step_batch", "cdfci_step_energies", "cdfci_step_trace",
+           "cdfci_strerror", "cdfci_workspace_size", "make_opts"]

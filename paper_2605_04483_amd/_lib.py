@@ -53,6 +53,48 @@ class cdfci_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cdfci_hubbard_spec(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int * 3),
+        ("ndim", ctypes.c_int),
+        ("n_alpha", ctypes.c_int),
+        ("n_beta", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+        ("t", ctypes.c_double),
+        ("U", ctypes.c_double),
+    ]
+
+
+class cdfci_batch_opts(ctypes.Structure):
+    _fields_ = [
+        ("table_slots", ctypes.c_uint64),
+        ("max_table_slots", ctypes.c_uint64),
+        ("load_factor", ctypes.c_double),
+        ("z_threshold", ctypes.c_double),
+        ("dx_damping", ctypes.c_double),
+        ("dx_threshold", ctypes.c_double),
+        ("chunk_steps", ctypes.c_int64),
+        ("launches_per_graph", ctypes.c_int),
+        ("waves", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class cdfci_batch_stats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64),
+        ("elements", ctypes.c_int64),
+        ("running", ctypes.c_int32),
+        ("stopped", ctypes.c_int32),
+        ("failed", ctypes.c_int32),
+        ("graph_replays", ctypes.c_int32),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # (name, restype, argtypes) for every exported symbol of include/cdfci.h
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -79,6 +121,13 @@ SIGNATURES = [
     ("cdfci_export", ctypes.c_int, [_P, ctypes.c_int64, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_phase_times", ctypes.c_int, [_P, _DP]),
     ("cdfci_free", ctypes.c_int, [_P]),
+    ("cdfci_init_hubbard_batch", ctypes.c_int,
+     [ctypes.POINTER(cdfci_hubbard_spec), ctypes.c_int, ctypes.POINTER(cdfci_batch_opts), _CTXP]),
+    ("cdfci_step_batch", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(cdfci_batch_stats)]),
+    ("cdfci_batch_results", ctypes.c_int, [_P, _DP, _I64P, ctypes.POINTER(ctypes.c_int)]),
+    ("cdfci_batch_trace", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, _DP, _UP, _UP]),
+    ("cdfci_batch_context", ctypes.c_int, [_P, ctypes.c_int, _CTXP]),
+    ("cdfci_free_batch", ctypes.c_int, [_P]),
     ("cdfci_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cdfci_last_error", ctypes.c_char_p, []),
 ]

@@ -6,7 +6,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import cdfci_opts, cdfci_stats
+from ._lib import cdfci_batch_opts, cdfci_batch_stats, cdfci_hubbard_spec, cdfci_opts, cdfci_stats
 
 
 class CDFCIError(RuntimeError):
@@ -213,3 +213,102 @@ def cdfci_free(ctx):
 
 def cdfci_strerror(code):
     return _lib.load().cdfci_strerror(int(code)).decode()
+
+
+# ---------------------------------------------------------------- Hubbard batches
+
+class _BorrowedContext(Context):
+    """An instance context owned by a batch (never freed from Python)."""
+
+    def close(self):
+        self.handle = None
+
+
+class Batch:
+    """Owns a cdfci_batch."""
+
+    def __init__(self, handle, specs):
+        self.handle = handle
+        self.specs = specs
+        self.count = len(specs)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle:
+            _lib.load().cdfci_free_batch(self.handle)
+            self.handle = None
+
+
+def cdfci_init_hubbard_batch(specs, table_slots=0, max_table_slots=0, load_factor=0.0, z_threshold=0.0,
+                             dx_damping=0.0, dx_threshold=0.0, chunk_steps=0, launches_per_graph=0,
+                             waves=0):
+    """specs: sequence of dicts {dims, t, U, n_alpha, n_beta}."""
+    L = _lib.load()
+    arr = (cdfci_hubbard_spec * len(specs))()
+    for i, sp in enumerate(specs):
+        dims = tuple(int(x) for x in sp["dims"])
+        assert 1 <= len(dims) <= 3
+        arr[i].dims[:] = list(dims) + [1] * (3 - len(dims))
+        arr[i].ndim = len(dims)
+        arr[i].n_alpha = int(sp["n_alpha"])
+        arr[i].n_beta = int(sp["n_beta"])
+        arr[i].t = float(sp["t"])
+        arr[i].U = float(sp["U"])
+    o = cdfci_batch_opts()
+    o.table_slots = int(table_slots)
+    o.max_table_slots = int(max_table_slots)
+    o.load_factor = float(load_factor)
+    o.z_threshold = float(z_threshold)
+    o.dx_damping = float(dx_damping)
+    o.dx_threshold = float(dx_threshold)
+    o.chunk_steps = int(chunk_steps)
+    o.launches_per_graph = int(launches_per_graph)
+    o.waves = int(waves)
+    h = ctypes.c_void_p()
+    _check(L.cdfci_init_hubbard_batch(arr, len(specs), ctypes.byref(o), ctypes.byref(h)),
+           "cdfci_init_hubbard_batch")
+    return Batch(h, list(specs))
+
+
+def cdfci_step_batch(batch, max_steps):
+    st = cdfci_batch_stats()
+    _check(_lib.load().cdfci_step_batch(batch.handle, int(max_steps), ctypes.byref(st)), "cdfci_step_batch")
+    return st.as_dict()
+
+
+def cdfci_batch_results(batch):
+    n = batch.count
+    E = np.zeros(n)
+    steps = np.zeros(n, np.int64)
+    status = np.zeros(n, np.int32)
+    _check(_lib.load().cdfci_batch_results(batch.handle, _dp(E), steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           status.ctypes.data_as(ctypes.POINTER(ctypes.c_int))),
+           "cdfci_batch_results")
+    return E, steps, status
+
+
+def cdfci_batch_trace(batch, instance, nsteps):
+    E = np.zeros(max(int(nsteps), 1))
+    a = np.zeros(max(int(nsteps), 1), np.uint64)
+    b = np.zeros(max(int(nsteps), 1), np.uint64)
+    before = cdfci_batch_results(batch)[1][instance]
+    _check(_lib.load().cdfci_batch_trace(batch.handle, int(instance), int(nsteps), _dp(E), _up(a), _up(b)),
+           "cdfci_batch_trace")
+    done = int(cdfci_batch_results(batch)[1][instance] - before)
+    return {"energy": E[:done], "sel_alpha": a[:done], "sel_beta": b[:done]}
+
+
+def cdfci_batch_context(batch, instance):
+    h = ctypes.c_void_p()
+    _check(_lib.load().cdfci_batch_context(batch.handle, int(instance), ctypes.byref(h)), "cdfci_batch_context")
+    sp = batch.specs[instance]
+    return _BorrowedContext(h, None, int(np.prod(sp["dims"])), int(sp["n_alpha"]), int(sp["n_beta"]))
+
+
+def cdfci_free_batch(batch):
+    batch.close()

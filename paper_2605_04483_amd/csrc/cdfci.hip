@@ -808,6 +808,31 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
 
 #include "mcd_kernels.h"
 #include "rdm_kernels.h"
+#include "hub_kernels.h"
+
+// per-instance step budget of the coming batch call (traced: only instance
+// `only` advances)
+__global__ void k_hub_limits(HubInst* inst, int n, int64_t nsteps, int only) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t s = inst[i].ctl->steps;
+  inst[i].step_limit = (only < 0 || only == i) ? s + nsteps : s;
+}
+
+struct HubResult {
+  double energy;
+  int64_t steps;
+  unsigned long long elements, occupied;
+  int stopped, error;
+};
+
+__global__ void k_hub_results(const HubInst* inst, int n, HubResult* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Ctl* c = inst[i].ctl;
+  out[i] = HubResult{(c->al_hi + c->al_lo) / (c->mu_hi + c->mu_lo), c->steps, *inst[i].elements,
+                     c->occupied, c->stopped, c->error};
+}
 
 }  // namespace
 
@@ -854,6 +879,23 @@ struct cdfci_ctx {
   double* hii = nullptr;
   double* lan = nullptr;
   unsigned* bitmap = nullptr;
+};
+
+struct cdfci_batch {
+  int count = 0;
+  std::vector<cdfci_ctx*> ctx;
+  std::vector<HubInst> h_inst;
+  HubInst* d_inst = nullptr;
+  unsigned* d_queue = nullptr;
+  unsigned long long* d_elems = nullptr;
+  HubResult* d_res = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  cdfci_batch_opts opts;
+  int waves = 0;
 };
 
 namespace {
@@ -1705,6 +1747,296 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of Hubbard lattices
+
+int cdfci_free_batch(cdfci_batch* B) {
+  if (!B) return 0;
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (cdfci_ctx* c : B->ctx) cdfci_free(c);
+  void* bufs[] = {B->d_inst, B->d_queue, B->d_elems, B->d_res};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (B->ev0) (void)hipEventDestroy(B->ev0);
+  if (B->ev1) (void)hipEventDestroy(B->ev1);
+  if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+  return 0;
+}
+
+static int batch_create(const cdfci_hubbard_spec* specs, int count, cdfci_batch* B) {
+  const cdfci_batch_opts& o = B->opts;
+  if (o.stream) {
+    B->stream = (hipStream_t)o.stream;
+  } else {
+    HIP_TRY(hipStreamCreate(&B->stream));
+    B->own_stream = true;
+  }
+  HIP_TRY(hipMalloc(&B->d_elems, count * sizeof(unsigned long long)));
+  HIP_TRY(hipMemsetAsync(B->d_elems, 0, count * sizeof(unsigned long long), B->stream));
+  for (int i = 0; i < count; ++i) {
+    const cdfci_hubbard_spec& sp = specs[i];
+    int L = 1;
+    for (int k = 0; k < sp.ndim; ++k) L *= sp.dims[k];
+    const std::vector<std::pair<int, int>> bonds = lattice_bonds(sp.dims, sp.ndim);
+    uint64_t slots = o.table_slots;
+    if (!slots) {
+      // FCI dimension C(L, na) C(L, nb) as a double (only its size matters)
+      double dim = 1.0;
+      for (int k = 0; k < sp.n_alpha; ++k) dim = dim * (L - k) / (k + 1);
+      for (int k = 0; k < sp.n_beta; ++k) dim = dim * (L - k) / (k + 1);
+      slots = 1024;
+      while ((double)slots * o.load_factor < dim && slots < o.max_table_slots) slots <<= 1;
+    }
+    cdfci_opts co;
+    memset(&co, 0, sizeof(co));
+    co.table_slots = slots;
+    co.load_factor = o.load_factor;
+    co.z_threshold = o.z_threshold;
+    co.dx_damping = o.dx_damping;
+    co.dx_threshold = o.dx_threshold;
+    co.stream = B->stream;
+    cdfci_ctx* c = nullptr;
+    int rc = cdfci_init_hubbard(sp.dims, sp.ndim, sp.t, sp.U, sp.n_alpha, sp.n_beta, &co, &c);
+    if (rc) return rc;
+    B->ctx.push_back(c);
+    HubInst hi;
+    memset(&hi, 0, sizeof(hi));
+    hi.T = c->T;
+    hi.mask = c->mask;
+    hi.max_entries = c->max_entries;
+    hi.ctl = c->ctl;
+    hi.step_limit = 0;
+    hi.elements = B->d_elems + i;
+    hi.t = sp.t;
+    hi.U = sp.U;
+    hi.nbonds = (int)bonds.size();
+    for (size_t k = 0; k < bonds.size(); ++k) {
+      hi.bi[k] = (uint8_t)bonds[k].first;
+      hi.bj[k] = (uint8_t)bonds[k].second;
+    }
+    B->h_inst.push_back(hi);
+  }
+  HIP_TRY(hipMalloc(&B->d_inst, count * sizeof(HubInst)));
+  HIP_TRY(hipMemcpyAsync(B->d_inst, B->h_inst.data(), count * sizeof(HubInst), hipMemcpyHostToDevice,
+                         B->stream));
+  HIP_TRY(hipMalloc(&B->d_queue, 2 * sizeof(unsigned)));
+  HIP_TRY(hipMalloc(&B->d_res, count * sizeof(HubResult)));
+  HIP_TRY(hipEventCreate(&B->ev0));
+  HIP_TRY(hipEventCreate(&B->ev1));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  return 0;
+}
+
+int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const cdfci_batch_opts* opts,
+                             cdfci_batch** out) {
+  if (!out) return CDFCI_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!specs || count < 1) return CDFCI_ERR_INVALID_ARG;
+  cdfci_batch_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (o.max_table_slots == 0) o.max_table_slots = 1ull << 22;
+  if (o.load_factor <= 0.0) o.load_factor = 0.79;
+  if (o.dx_damping <= 0.0) o.dx_damping = 0.9;
+  if (o.chunk_steps <= 0) o.chunk_steps = 1024;
+  if (o.launches_per_graph <= 0) o.launches_per_graph = 4;
+  if (o.waves <= 0) o.waves = std::min(count, 8192);
+  if ((o.table_slots & (o.table_slots - 1)) != 0 || (o.max_table_slots & (o.max_table_slots - 1)) != 0 ||
+      o.load_factor > 0.95 || o.launches_per_graph > 64)
+    return CDFCI_ERR_INVALID_ARG;
+  // every spec is checked before any device work
+  for (int i = 0; i < count; ++i) {
+    const cdfci_hubbard_spec& sp = specs[i];
+    if (sp.ndim < 1 || sp.ndim > 3) return CDFCI_ERR_INVALID_ARG;
+    int L = 1;
+    for (int k = 0; k < sp.ndim; ++k) {
+      if (sp.dims[k] < 1 || sp.dims[k] > kMaxOrb) return CDFCI_ERR_INVALID_ARG;
+      L *= sp.dims[k];
+      if (L > kMaxOrb) return CDFCI_ERR_UNSUPPORTED;
+    }
+    if (sp.n_alpha < 0 || sp.n_beta < 0 || sp.n_alpha > L || sp.n_beta > L) return CDFCI_ERR_UNSUPPORTED;
+    if (sp.n_alpha + sp.n_beta < 1) return CDFCI_ERR_INVALID_ARG;
+    if ((int)lattice_bonds(sp.dims, sp.ndim).size() > kHubMaxBonds) return CDFCI_ERR_UNSUPPORTED;
+  }
+  cdfci_batch* B = new cdfci_batch();
+  B->count = count;
+  B->opts = o;
+  B->waves = o.waves;
+  const int rc = batch_create(specs, count, B);
+  if (rc) {
+    cdfci_free_batch(B);
+    return rc;
+  }
+  *out = B;
+  return 0;
+}
+
+static int batch_gather(cdfci_batch* B, std::vector<HubResult>& r) {
+  r.resize(B->count);
+  k_hub_results<<<(B->count + 255) / 256, 256, 0, B->stream>>>(B->d_inst, B->count, B->d_res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(r.data(), B->d_res, B->count * sizeof(HubResult), hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  return 0;
+}
+
+static HubArgs batch_args(const cdfci_batch* B) {
+  HubArgs a;
+  a.inst = B->d_inst;
+  a.n_inst = B->count;
+  a.queue = B->d_queue;
+  a.chunk = B->opts.chunk_steps;
+  a.tau = B->opts.z_threshold;
+  a.theta = B->opts.dx_damping;
+  a.dx_tol = B->opts.dx_threshold;
+  a.trace_inst = -1;
+  a.tr_E = nullptr;
+  a.tr_a = nullptr;
+  a.tr_b = nullptr;
+  return a;
+}
+
+int cdfci_step_batch(cdfci_batch* B, int64_t max_steps, cdfci_batch_stats* out) {
+  if (!B || max_steps < 0) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = B->stream;
+  // instances stepped through their own context with k > 1 hold a lazy
+  // scale: fold it and reselect as a k = 1 step would
+  for (cdfci_ctx* c : B->ctx)
+    if (c->mode == 1) {
+      const int e = enter_single(c);
+      if (e) return e;
+    }
+  std::vector<HubResult> r0, r1;
+  int rc = batch_gather(B, r0);
+  if (rc) return rc;
+  k_hub_limits<<<(B->count + 255) / 256, 256, 0, s>>>(B->d_inst, B->count, max_steps, -1);
+  HIP_TRY(hipGetLastError());
+  const int R = B->opts.launches_per_graph;
+  if (!B->exec) {
+    const HubArgs a = batch_args(B);
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < R; ++i) {
+      k_hub_reset<<<1, 1, 0, s>>>(B->d_queue);
+      k_hub_batch<<<B->waves, 64, 0, s>>>(a);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) {
+      g_last_error = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+      return CDFCI_ERR_HIP;
+    }
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+  }
+  // every visit of a running instance advances it by min(chunk, budget left)
+  // steps, so the budget is spent within this many replays
+  const int64_t visits = (max_steps + B->opts.chunk_steps - 1) / B->opts.chunk_steps;
+  const int64_t max_replays = (visits + R - 1) / R + 1;
+  int replays = 0;
+  HIP_TRY(hipEventRecord(B->ev0, s));
+  for (int64_t it = 0; it < max_replays && max_steps > 0; ++it) {
+    HIP_TRY(hipGraphLaunch(B->exec, s));
+    ++replays;
+    unsigned active = 0;
+    HIP_TRY(hipMemcpyAsync(&active, B->d_queue + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (active == 0) break;
+  }
+  HIP_TRY(hipEventRecord(B->ev1, s));
+  rc = batch_gather(B, r1);
+  if (rc) return rc;
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, B->ev0, B->ev1));
+  int failed = 0;
+  for (int i = 0; i < B->count; ++i) failed += r1[i].error != 0;
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    for (int i = 0; i < B->count; ++i) {
+      out->steps += r1[i].steps - r0[i].steps;
+      out->elements += (int64_t)(r1[i].elements - r0[i].elements);
+      if (r1[i].error) continue;
+      if (r1[i].stopped) ++out->stopped;
+      else ++out->running;
+    }
+    out->failed = failed;
+    out->graph_replays = replays;
+    out->seconds = ms * 1e-3;
+  }
+  return 0;
+}
+
+int cdfci_batch_results(cdfci_batch* B, double* energy, int64_t* steps, int* status) {
+  if (!B) return CDFCI_ERR_INVALID_ARG;
+  std::vector<HubResult> r;
+  int rc = batch_gather(B, r);
+  if (rc) return rc;
+  for (int i = 0; i < B->count; ++i) {
+    if (energy) energy[i] = r[i].energy;
+    if (steps) steps[i] = r[i].steps;
+    if (status) {
+      int st = r[i].stopped ? 1 : 0;
+      if (r[i].error & kErrTableFull) st = CDFCI_ERR_TABLE_FULL;
+      else if (r[i].error) st = CDFCI_ERR_NUMERIC;
+      status[i] = st;
+    }
+  }
+  return 0;
+}
+
+int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, uint64_t* sel_alpha,
+                      uint64_t* sel_beta) {
+  if (!B || inst < 0 || inst >= B->count || nsteps < 0) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = B->stream;
+  std::vector<HubResult> r0, r1;
+  int rc = batch_gather(B, r0);
+  if (rc) return rc;
+  const int64_t step0 = r0[inst].steps;
+  if (B->ctx[inst]->mode == 1) {
+    rc = enter_single(B->ctx[inst]);
+    if (rc) return rc;
+  }
+  CallBufs bufs;
+  double* dE;
+  uint64_t *da, *db;
+  HIP_TRY(bufs.alloc(&dE, step0 + nsteps));
+  HIP_TRY(bufs.alloc(&da, step0 + nsteps));
+  HIP_TRY(bufs.alloc(&db, step0 + nsteps));
+  k_hub_limits<<<(B->count + 255) / 256, 256, 0, s>>>(B->d_inst, B->count, nsteps, inst);
+  HubArgs a = batch_args(B);
+  a.trace_inst = inst;
+  a.tr_E = dE;
+  a.tr_a = da;
+  a.tr_b = db;
+  const int64_t visits = (nsteps + B->opts.chunk_steps - 1) / B->opts.chunk_steps;
+  for (int64_t it = 0; it < visits + 1 && nsteps > 0; ++it) {
+    k_hub_reset<<<1, 1, 0, s>>>(B->d_queue);
+    k_hub_batch<<<B->waves, 64, 0, s>>>(a);
+    HIP_TRY(hipGetLastError());
+    unsigned active = 0;
+    HIP_TRY(hipMemcpyAsync(&active, B->d_queue + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (active == 0) break;
+  }
+  rc = batch_gather(B, r1);
+  if (rc) return rc;
+  const int64_t done = r1[inst].steps - step0;
+  if (done > 0) {
+    if (energy) HIP_TRY(hipMemcpy(energy, dE + step0, done * sizeof(double), hipMemcpyDeviceToHost));
+    if (sel_alpha) HIP_TRY(hipMemcpy(sel_alpha, da + step0, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (sel_beta) HIP_TRY(hipMemcpy(sel_beta, db + step0, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  }
+  return 0;
+}
+
+int cdfci_batch_context(cdfci_batch* B, int inst, cdfci_ctx** ctx) {
+  if (!B || !ctx || inst < 0 || inst >= B->count) return CDFCI_ERR_INVALID_ARG;
+  *ctx = B->ctx[inst];
   return 0;
 }
 

@@ -34,6 +34,9 @@ def test_struct_layouts():
     # cdfci_opts: 5 8-byte scalars, 4 ints, 3 pointer-size fields
     assert ctypes.sizeof(_lib.cdfci_opts) == 5 * 8 + 4 * 4 + 3 * 8
     assert ctypes.sizeof(_lib.cdfci_stats) == 5 * 8 + 2 * 4 + 5 * 8
+    assert ctypes.sizeof(_lib.cdfci_hubbard_spec) == 7 * 4 + 4 + 2 * 8
+    assert ctypes.sizeof(_lib.cdfci_batch_opts) == 7 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_lib.cdfci_batch_stats) == 2 * 8 + 4 * 4 + 8
 
 
 def test_strerror_without_gpu():
@@ -56,3 +59,24 @@ def test_host_side_argument_errors_without_gpu():
     n = ctypes.c_size_t()
     assert L.cdfci_workspace_size(24, 6, 6, ctypes.byref(opts), ctypes.byref(n)) == 0
     assert n.value == (1 << 22) * 32
+
+
+def test_batch_argument_errors_without_gpu():
+    """Every Hubbard spec is checked before the batch touches the device."""
+    L = _lib.load()
+    out = ctypes.c_void_p()
+    opts = _lib.cdfci_batch_opts()
+    sp = (_lib.cdfci_hubbard_spec * 2)()
+    for s, dims in zip(sp, ((2, 4, 1), (8, 8, 1))):
+        s.dims[:] = list(dims)
+        s.ndim = 2
+        s.n_alpha, s.n_beta, s.t, s.U = 4, 4, 1.0, 4.0
+    assert L.cdfci_init_hubbard_batch(sp, 2, ctypes.byref(opts), ctypes.byref(out)) == _lib.CDFCI_ERR_UNSUPPORTED
+    assert L.cdfci_init_hubbard_batch(sp, 0, ctypes.byref(opts), ctypes.byref(out)) == _lib.CDFCI_ERR_INVALID_ARG
+    sp[1].dims[:] = [2, 4, 1]
+    sp[1].ndim = 0
+    assert L.cdfci_init_hubbard_batch(sp, 2, ctypes.byref(opts), ctypes.byref(out)) == _lib.CDFCI_ERR_INVALID_ARG
+    sp[1].ndim = 2
+    sp[1].n_alpha = 9
+    assert L.cdfci_init_hubbard_batch(sp, 2, ctypes.byref(opts), ctypes.byref(out)) == _lib.CDFCI_ERR_UNSUPPORTED
+    assert not out.value

@@ -1,0 +1,132 @@
+"""GPU checks of the batched Hubbard path (many lattices in one persistent
+kernel under a replayed HIP graph), called through the C ABI.  Bars: every
+instance's energy within 1e-8 Ha of the oracle's dense / Lanczos ground
+state; the stored b equal to H c from the oracle's sparse H (1e-10); the
+maintained energy equal to the device's exact c^T H c / c^T c; step budgets
+honoured exactly."""
+import numpy as np
+import pytest
+
+from oracle import cd as ocd
+from oracle import fci
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2605_04483_amd as api
+
+    return api
+
+
+def _spec(dims, U, t=1.0):
+    L = int(np.prod(dims))
+    return {"dims": tuple(dims), "t": t, "U": U, "n_alpha": (L + 1) // 2, "n_beta": L // 2}
+
+
+def _ground(sp):
+    h, eri = fci.hubbard_integrals(sp["dims"], sp["t"], sp["U"])
+    return ocd.ground_energy(h, eri, sp["n_alpha"], sp["n_beta"])
+
+
+def test_batch_converges_to_oracle(api):
+    """Uneven lattices (4 to 9 sites, FCI dimensions 36 to 15,876) in one
+    batch, each to its own stopping rule."""
+    specs = [_spec((2, 2), 2.0), _spec((2, 3), 5.0), _spec((6,), 3.0), _spec((2, 4), 4.0),
+             _spec((8,), 7.5), _spec((3, 3), 9.0), _spec((5,), 6.0), _spec((1, 7), 2.5)]
+    B = api.cdfci_init_hubbard_batch(specs, dx_threshold=1e-11, chunk_steps=4096)
+    total = 0
+    for _ in range(8):  # budget 8 x 500k steps per instance, progress printed per call
+        st = api.cdfci_step_batch(B, 500_000)
+        total += st["steps"]
+        print(f"batch: {st}", flush=True)
+        if st["running"] == 0:
+            break
+    E, steps, status = api.cdfci_batch_results(B)
+    assert st["failed"] == 0
+    assert st["stopped"] == len(specs), (st, steps)
+    assert total == int(steps.sum())
+    for i, sp in enumerate(specs):
+        E0 = _ground(sp)
+        assert status[i] == 1
+        assert abs(E[i] - E0) < 1e-8, (sp, E[i], E0)
+        ctx = api.cdfci_batch_context(B, i)
+        assert abs(api.cdfci_energy(ctx, exact=1) - E0) < 1e-8, sp
+    B.close()
+
+
+def test_batch_state_is_consistent(api):
+    """After a fixed budget the stored b_j equal sum_i H_ji c_i over the
+    oracle's sparse H, the maintained energy equals the exact quotient, and
+    a second call continues exactly where the first one stopped."""
+    specs = [_spec((2, 4), 4.0), _spec((3, 3), 8.0), _spec((2, 3), 3.0)]
+    B = api.cdfci_init_hubbard_batch(specs, chunk_steps=700)
+    api.cdfci_step_batch(B, 5000)
+    st = api.cdfci_step_batch(B, 3000)
+    E, steps, status = api.cdfci_batch_results(B)
+    assert list(steps) == [8000, 8000, 8000]
+    assert st["steps"] == 3 * 3000 and st["running"] == 3
+    assert st["elements"] > st["steps"]
+    for i, sp in enumerate(specs):
+        ctx = api.cdfci_batch_context(B, i)
+        assert abs(api.cdfci_energy(ctx, exact=1) - E[i]) < 1e-11 * abs(E[i])
+        h, eri = fci.hubbard_integrals(sp["dims"], sp["t"], sp["U"])
+        H, basis = ocd.sparse_H(h, eri, sp["n_alpha"], sp["n_beta"])
+        index = {k: j for j, k in enumerate(basis)}
+        ka, kb, c, b = api.cdfci_export(ctx)
+        cv = np.zeros(len(basis))
+        for x, y, v in zip(ka, kb, c):
+            cv[index[(int(x), int(y))]] = v
+        Hc = H @ cv
+        err = max(abs(bv - Hc[index[(int(x), int(y))]]) for x, y, bv in zip(ka, kb, b))
+        assert err < 1e-10, (sp, err)
+    B.close()
+
+
+def test_batch_trace_matches_oracle_prefix(api):
+    """Step-by-step against the serial oracle from the same Neel + subspace
+    start, up to the first selection the oracle decides by a gap below 1e-9
+    (lattice symmetries give exact ties early)."""
+    sp = _spec((2, 3), 5.0)
+    h, eri = fci.hubbard_integrals(sp["dims"], sp["t"], sp["U"])
+    keys, c0 = ocd.init_subspace(h, eri, ocd.neel(sp["dims"], sp["n_alpha"], sp["n_beta"]))
+    orc = ocd.cd_run(h, eri, keys, c0, max_steps=2000)
+    B = api.cdfci_init_hubbard_batch([_spec((2, 2), 2.0), sp])
+    tr = api.cdfci_batch_trace(B, 1, 2000)
+    assert len(tr["energy"]) == 2000
+    E, steps, _ = api.cdfci_batch_results(B)
+    assert list(steps) == [0, 2000]
+    n = 0
+    for s in range(2000):
+        g = (int(tr["sel_alpha"][s]), int(tr["sel_beta"][s]))
+        o = (int(orc.sel_a[s]), int(orc.sel_b[s]))
+        if g != o:
+            assert orc.gap[s] < 1e-9, (s, g, o)
+            break
+        assert abs(tr["energy"][s] - orc.E[s]) <= 1e-10 * abs(orc.E[s]), s
+        n += 1
+    assert tr["energy"][-1] < tr["energy"][0]
+    assert abs(E[1] - tr["energy"][-1]) == 0.0
+    B.close()
+
+
+def test_batch_table_full_is_per_instance(api):
+    """An instance whose table fills stops with TABLE_FULL; the others finish."""
+    specs = [_spec((2, 2), 2.0), _spec((3, 3), 8.0), _spec((2, 3), 3.0)]
+    B = api.cdfci_init_hubbard_batch(specs, max_table_slots=1024, dx_threshold=1e-11)
+    for _ in range(8):
+        st = api.cdfci_step_batch(B, 250_000)
+        print(f"batch: {st}", flush=True)
+        if st["running"] == 0:
+            break
+    E, steps, status = api.cdfci_batch_results(B)
+    assert status[1] == -3
+    assert st["failed"] == 1
+    for i in (0, 2):
+        assert status[i] == 1
+        assert abs(E[i] - _ground(specs[i])) < 1e-8
+    B.close()

@@ -304,16 +304,29 @@ __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, co
 
 // ---------------------------------------------------------------- reduced problem
 
-// Sturm count: eigenvalues of the tridiagonal (a, b) below x
+// Sturm count: eigenvalues of the tridiagonal (a, b) below x, as the number
+// of sign changes of the leading principal minors p_i of T - x I, formed by
+// the three-term recurrence p_i = (a_i - x) p_(i-1) - b_(i-1)^2 p_(i-2) with
+// no division (the minors are rescaled by powers of two to stay in range;
+// an exact zero minor counts as a tiny value of the opposite sign, as the
+// ratio form d_i = p_i / p_(i-1) -> -0 does).
 __device__ __forceinline__ int sturm_count(const double* a, const double* b, int n, double x) {
   int cnt = 0;
-  double d = a[0] - x;
-  if (d == 0.0) d = -1e-300;
-  cnt += d < 0.0;
+  double p0 = 1.0, p1 = a[0] - x;
+  if (p1 == 0.0) p1 = -1e-300;
+  cnt += p1 < 0.0;
   for (int i = 1; i < n; ++i) {
-    d = a[i] - x - b[i - 1] * b[i - 1] / d;
-    if (d == 0.0) d = -1e-300;
-    cnt += d < 0.0;
+    double p2 = (a[i] - x) * p1 - (b[i - 1] * b[i - 1]) * p0;
+    if (p2 == 0.0) p2 = p1 < 0.0 ? 1e-300 : -1e-300;
+    cnt += (p2 < 0.0) != (p1 < 0.0);
+    p0 = p1;
+    p1 = p2;
+    const double m = fabs(p1);
+    if (m > 0x1p+400 || m < 0x1p-400) {
+      const int e = ilogb(m);
+      p0 = ldexp(p0, -e);
+      p1 = ldexp(p1, -e);
+    }
   }
   return cnt;
 }
@@ -321,8 +334,10 @@ __device__ __forceinline__ int sturm_count(const double* a, const double* b, int
 // Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)), called
 // by one full wave: 64-way multisection on the Sturm count (six bits per
 // round), then inverse iteration with partial pivoting by lane 0.  y and wk
-// live in shared memory; the eigenvalue is returned to every lane.
-__device__ double tri_lowest_wave(const double* a, const double* b, int n, double* y, double* wk) {
+// live in shared memory; the eigenvalue is returned to every lane.  With
+// want_y == 0 only the eigenvalue is formed.
+__device__ double tri_lowest_wave(const double* a, const double* b, int n, double* y, double* wk,
+                                  int want_y = 1) {
   const int lane = threadIdx.x & 63;
   if (n == 1) {
     if (lane == 0) y[0] = 1.0;
@@ -346,6 +361,7 @@ __device__ double tri_lowest_wave(const double* a, const double* b, int n, doubl
     lo = nlo;
     hi = nhi;
   }
+  if (!want_y) return 0.5 * (lo + hi);
   const double lam = 0.5 * (lo + hi);
   if (lane == 0) {
     // inverse iteration on (T - lam I): Gaussian elimination with partial
@@ -385,6 +401,7 @@ __device__ double tri_lowest_wave(const double* a, const double* b, int n, doubl
       }
     }
     if (dm[n - 1] == 0.0) dm[n - 1] = tiny;
+    for (int i = 0; i < n; ++i) dm[i] = 1.0 / dm[i];  // solves multiply by the reciprocals
     for (int sweep = 0; sweep < 3; ++sweep) {
       for (int i = 0; i < n - 1; ++i) {
         if (piv[i] == 0) {
@@ -395,13 +412,13 @@ __device__ double tri_lowest_wave(const double* a, const double* b, int n, doubl
           y[i + 1] = t - dl[i] * y[i + 1];
         }
       }
-      y[n - 1] /= dm[n - 1];
-      y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / dm[n - 2];
-      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / dm[i];
+      y[n - 1] *= dm[n - 1];
+      y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) * dm[n - 2];
+      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) * dm[i];
       double nrm = 0.0;
       for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
-      nrm = sqrt(nrm);
-      for (int i = 0; i < n; ++i) y[i] /= nrm;
+      const double inv = 1.0 / sqrt(nrm);
+      for (int i = 0; i < n; ++i) y[i] *= inv;
     }
   }
   return lam;
@@ -423,51 +440,85 @@ struct EigArgs {
 
 // The reduced matrix A (order n = m + off, off = 1 when the c~ column exists):
 //   A_00 = a00, A_0i = A_i0 = a0_i, A_ij = (H_II)_ij.
-// Thread r owns entry r (and r + 1024 when n = 1025).  H_II is read column-wise
-// (it is exactly symmetric), so the loads of a wave are contiguous.
-__device__ void mc_matvec(const double* hii, int m, int off, double a00, const double* s_a0,
-                          const double* s_x, double* yg, int n) {
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+// y = A x.  H_II (exactly symmetric) is read column-wise so a wave's loads are
+// contiguous.  The waves split the work into 64-row blocks times column
+// slices; each lane keeps four independent partial sums so loads overlap, and
+// the slices are combined in shared memory (s_part, 16 * 1025 doubles would
+// not fit, so slices are combined one row block at a time).
+__device__ void mc_matvec(const double* __restrict__ hii, int m, int off, double a00,
+                          const double* s_a0, const double* s_x, double* s_y, int n, double* s_part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nrb = (m + 63) >> 6;                     // row blocks of H_II
+  const int ns = nrb >= nw ? 1 : nw / nrb;           // column slices per row block
+  const int span = (m + ns - 1) / ns;
+  for (int rb0 = 0; rb0 < nrb; rb0 += nw / ns) {
+    // wave wv works on row block rb0 + wv / ns, slice wv % ns
+    const int rb = rb0 + wv / ns, sl = wv % ns;
+    const int i = rb * 64 + lane;
     double acc = 0.0;
-    if (off && r == 0) {
-      acc = a00 * s_x[0];
-      for (int j = 0; j < m; ++j) acc += s_a0[j] * s_x[1 + j];
-    } else {
-      const int i = r - off;
-      for (int j = 0; j < m; ++j) acc += hii[(size_t)j * m + i] * s_x[off + j];
-      if (off) acc += s_a0[i] * s_x[0];
+    if (rb < nrb && wv / ns < nw / ns && i < m) {
+      const int j0 = sl * span, j1 = min(m, j0 + span);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = j0;
+      for (; j + 3 < j1; j += 4) {
+        a0 += hii[(size_t)j * m + i] * s_x[off + j];
+        a1 += hii[(size_t)(j + 1) * m + i] * s_x[off + j + 1];
+        a2 += hii[(size_t)(j + 2) * m + i] * s_x[off + j + 2];
+        a3 += hii[(size_t)(j + 3) * m + i] * s_x[off + j + 3];
+      }
+      for (; j < j1; ++j) a0 += hii[(size_t)j * m + i] * s_x[off + j];
+      acc = (a0 + a1) + (a2 + a3);
     }
-    yg[r] = acc;
+    if (wv / ns < nw / ns) s_part[(wv % ns) * 64 + (wv / ns) * 64 * ns + lane] = acc;
+    __syncthreads();
+    // combine: thread t of the first (nw / ns) * 64 threads owns one row
+    const int t = threadIdx.x;
+    if (t < (nw / ns) * 64) {
+      const int rbl = t >> 6, ln = t & 63;
+      const int ii = (rb0 + rbl) * 64 + ln;
+      if (rb0 + rbl < nrb && ii < m) {
+        double sum = 0.0;
+        for (int q = 0; q < ns; ++q) sum += s_part[q * 64 + rbl * 64 * ns + ln];
+        if (off) sum += s_a0[ii] * s_x[0];
+        s_y[off + ii] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  if (off && threadIdx.x < 64) {
+    // row 0: a00 x_0 + a0 . x_I
+    double p = 0.0;
+    for (int j = lane; j < m; j += 64) p += s_a0[j] * s_x[1 + j];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double q = __shfl_xor(p, o);
+      p = (lane & o) ? (q + p) : (p + q);
+    }
+    if (lane == 0) s_y[0] = a00 * s_x[0] + p;
   }
 }
 
-// h[i] = V_i . w for i = 0..j in one workgroup reduction (fixed order)
-__device__ void mc_multidot(const double* V, int n, int j, const double* w, double* s_dots,
-                            double* s_h) {
+// h[i] = V_i . w for i = 0..j: wave q forms the dot products i = q, q + 16,
+// ... over the whole vector (fixed order), so up to 16 run side by side.
+// w is read from shared memory.
+__device__ void mc_multidot(const double* V, int n, int j, const double* s_w, double* s_h) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = 0; i <= j; ++i) {
+  for (int i = wv; i <= j; i += nw) {
     double p = 0.0;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) p += V[(size_t)i * n + r] * w[r];
+    for (int r = lane; r < n; r += 64) p += V[(size_t)i * n + r] * s_w[r];
     for (int off = 32; off > 0; off >>= 1) {
       double o = __shfl_xor(p, off);
       p = (lane & off) ? (o + p) : (p + o);
     }
-    if (lane == 0) s_dots[wv * (kLanczosMax + 1) + i] = p;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-    double t = 0.0;
-    for (int q = 0; q < nw; ++q) t += s_dots[q * (kLanczosMax + 1) + i];
-    s_h[i] = t;
+    if (lane == 0) s_h[i] = p;
   }
   __syncthreads();
 }
 
 // one workgroup of 1024 threads
 __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
-  __shared__ double s_c[1024], s_b[1024], s_a0[1024], s_x[1025];
+  __shared__ double s_c[1024], s_b[1024], s_a0[1024], s_x[1025], s_w[1025];
+  __shared__ double s_part[1024];
   __shared__ double s_red[16];
-  __shared__ double s_dots[16 * (kLanczosMax + 1)];
   __shared__ double s_alpha[kLanczosMax + 1], s_beta[kLanczosMax + 1];
   __shared__ double s_y[kLanczosMax + 1], s_h[kLanczosMax + 1], s_h2[kLanczosMax + 1];
   __shared__ double s_wk[5 * (kLanczosMax + 1)];
@@ -486,9 +537,9 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   }
   __syncthreads();
   // hc = H_II c_I
-  double hc_i = 0.0;
-  if (tid < m)
-    for (int j = 0; j < m; ++j) hc_i += hii[(size_t)j * m + tid] * s_c[j];
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_c, s_w, m, s_part);
+  __syncthreads();
+  const double hc_i = tid < m ? s_w[tid] : 0.0;
   const double ci = tid < m ? s_c[tid] : 0.0, bi = tid < m ? s_b[tid] : 0.0;
   const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
   const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
@@ -506,8 +557,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
     if (tid == 0) ctl->stopped = 1;
     return;
   }
-  double* V = A.lan;                            // rows 0..kLanczosMax-1: Lanczos vectors
-  double* w = A.lan + (size_t)kLanczosMax * n;  // work vector
+  double* V = A.lan;  // rows 0..kLanczosMax-1: Lanczos vectors
   // start vector: the current point [nu; c_I]
   {
     double part = 0.0;
@@ -526,24 +576,26 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   for (int j = 0; j < jmax; ++j) {
     for (int r = tid; r < n; r += blockDim.x) s_x[r] = V[(size_t)j * n + r];
     __syncthreads();
-    mc_matvec(hii, m, off, a00, s_a0, s_x, w, n);
+    mc_matvec(hii, m, off, a00, s_a0, s_x, s_w, n, s_part);
     __syncthreads();
     // classical Gram-Schmidt against V_0..V_j, twice
-    mc_multidot(V, n, j, w, s_dots, s_h);
+    mc_multidot(V, n, j, s_w, s_h);
     for (int r = tid; r < n; r += blockDim.x) {
-      double t = w[r];
+      double t = s_w[r];
+#pragma unroll 8
       for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
-      w[r] = t;
+      s_w[r] = t;
     }
     __syncthreads();
     if (tid <= j) s_h2[tid] = s_h[tid];
     __syncthreads();
-    mc_multidot(V, n, j, w, s_dots, s_h);
+    mc_multidot(V, n, j, s_w, s_h);
     double part = 0.0;
     for (int r = tid; r < n; r += blockDim.x) {
-      double t = w[r];
+      double t = s_w[r];
+#pragma unroll 8
       for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
-      w[r] = t;
+      s_w[r] = t;
       part += t * t;
     }
     const double beta = sqrt(wg_sum(part, s_red));
@@ -554,7 +606,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
     __syncthreads();
     iters = j + 1;
     bool stop = (j + 1 == jmax) || !(beta > 1e-14 * fabs(s_alpha[0]) + 1e-300);
-    if (!stop && (j & 1)) {
+    if (!stop && j >= 5 && (j & 3) == 1) {
       // residual of the lowest Ritz pair: |beta_j y_j|; the eigenvalue error
       // is quadratic in it
       if (tid < 64) {
@@ -568,7 +620,8 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
       if (s_bc[1] <= 1e-10 * fabs(s_bc[0])) stop = true;
     }
     if (stop) break;
-    for (int r = tid; r < n; r += blockDim.x) V[(size_t)(j + 1) * n + r] = w[r] / beta;
+    const double inv_beta = 1.0 / beta;
+    for (int r = tid; r < n; r += blockDim.x) V[(size_t)(j + 1) * n + r] = s_w[r] * inv_beta;
     __syncthreads();
   }
   if (tid < 64) {
@@ -597,9 +650,9 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   __syncthreads();
   if (tid < m) s_x[tid] = eta_i;
   __syncthreads();
-  double heta_i = 0.0;
-  if (tid < m)
-    for (int j = 0; j < m; ++j) heta_i += hii[(size_t)j * m + tid] * s_x[j];
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, m, s_part);
+  __syncthreads();
+  const double heta_i = tid < m ? s_w[tid] : 0.0;
   const dd ec = wg_sum_dd(two_prod(eta_i, ci), s_red);
   const dd eb = wg_sum_dd(two_prod(eta_i, bi), s_red);
   const dd ee = wg_sum_dd(two_prod(eta_i, eta_i), s_red);
@@ -659,6 +712,36 @@ struct ScatterArgs {
   int k;
 };
 
+// Lookup for the scatter: the key pair in one 16-byte cached load, c only on
+// a match.  Within the scatter launch c never changes and keys only appear
+// (with c = 0), so a stale "empty" costs nothing: a large update then goes
+// through the claiming insert, which sees the current slot, and a small one
+// leaves b alone exactly as for an absent key.  A key seen while its beta word
+// is still being published is looked up again with coherent loads.
+__device__ __forceinline__ int64_t scatter_find(const Slot* __restrict__ T, uint64_t mask, uint64_t a,
+                                                uint64_t b, double* c) {
+  uint64_t idx = hash_key(a, b) & mask;
+  for (int n = 0; n < kMaxProbe; ++n) {
+    const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&T[idx]);
+    if (kk.x == kEmpty) return -1;
+    if (kk.x == a) {
+      if (kk.y == b) {
+        *c = T[idx].c;
+        return (int64_t)idx;
+      }
+      if (kk.y == kPending) {
+        int probes = 0;
+        SlotVal sv;
+        const int64_t s = table_find(T, mask, a, b, &probes, &sv);
+        if (s >= 0) *c = sv.c;
+        return s;
+      }
+    }
+    idx = (idx + 1) & mask;
+  }
+  return -1;
+}
+
 __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
   __shared__ Lists L;
   __shared__ double s_diag;
@@ -708,8 +791,8 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
     if (Hj != 0.0) {
       int probes = 0;
       SlotVal sv;
-      int64_t slot = table_find(A.T, A.mask, ja, jb, &probes, &sv);
-      double cj = slot >= 0 ? sv.c : 0.0;
+      double cj = 0.0;
+      int64_t slot = scatter_find(A.T, A.mask, ja, jb, &cj);
       if (e != 0) {
         const bool big = fabs(eta * Hj) >= A.tau;
         if (slot < 0 && big) {

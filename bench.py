@@ -1,24 +1,35 @@
 """Benchmark of the coordinate-descent FCI hot path on one MI355X.
 
-Workload: synthetic ab initio Hamiltonian, 24 spatial orbitals, 6 alpha + 6
-beta electrons, 72 auxiliary vectors (seed 2024), hash table of 2^28 slots,
-single-coordinate CDFCI (Alg. 1) for 10^6 iterations in total (warmup + timed)
-with compression threshold tau = 5e-5 (at tau = 0 the 2^28-slot table reaches
-its 0.79 load limit after about 4.6e5 iterations).  One benchmark step = one
-cdfci_step call of --iters iterations (each: select, line search, enumerate the
-16471-entry column, Slater-Condon, probe, scatter, recalculate b_i).
+Headline workload (`value`): synthetic ab initio Hamiltonian, 24 spatial
+orbitals, 6 alpha + 6 beta electrons, 72 auxiliary vectors (seed 2024), hash
+table of 2^28 slots, single-coordinate CDFCI (Alg. 1) for 10^6 iterations in
+total (warmup + timed) with compression threshold tau = 5e-5 (at tau = 0 the
+2^28-slot table reaches its 0.79 load limit after about 4.6e5 iterations).
+One benchmark step = one cdfci_step call of --iters iterations (each: select,
+line search, enumerate the 16471-entry column, Slater-Condon, probe, scatter,
+recalculate b_i).  `value` = enumerated column entries per second.
+
+Further blocks on the same JSON line (skipped with --no-extra):
+  batched_vs_plain  the same N = 24 system from a fresh start with the
+                    multicoordinate step (k picked by the autotuner), timed to
+                    the energy the plain run reached;
+  mcd_n36           N = 36, 8+8, naux 108, 2^30 slots, tau 5e-5: elements/s and
+                    ms per step for k = 64, 256, 1024 and for k = 1;
+  hubbard_batch     256 periodic lattices from {2x4, 3x4, 4x4, 2x8, 3x5}, half
+                    filling, U ~ [2, 10], in one persistent kernel under a
+                    replayed graph (autotuned), against the single-instance
+                    path on a sample of the same instances;
+  rdm               RDM reverse pass on the top 10^6 determinants of the
+                    headline run's final state.
 
 --copy-probe runs only a device copy of known size (for calibrating the HBM
 byte counters of a profiler run) and exits.
-
-Prints one JSON line: H elements/s (enumerated column entries per second,
-zeros included) as `value`, plus CD iterations/s, the HBM roofline of the
-persistent kernel (40 algorithmic bytes per element: a 32-byte slot read and
-an 8-byte b write) and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +38,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_ELEMENT = 40
+COUNTERS = os.path.join(ROOT, "profiles", "k_cd1_abinitio_n24_hbm_counters.md")
+KERNEL_SOURCES = ["paper_2605_04483_amd/csrc/cdfci.hip", "paper_2605_04483_amd/csrc/device.h"]
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic_per_element():
+    """HBM bytes per column entry of k_cd1 from the committed counter runs,
+    or None when the kernel sources changed since they were taken."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_element:\s*([0-9.]+)", text)
+    s = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not s or s.group(1) != sources_sha256():
+        return None
+    return float(m.group(1))
 
 
 def cpu_baseline(h, eri, na, nb, seconds_target=15.0):
@@ -49,6 +84,121 @@ def cpu_baseline(h, eri, na, nb, seconds_target=15.0):
                       f"{dt:.1f} s), iters/s = {r.steps / dt:.1f}"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_vs_plain(api, h, eri, na, nb, args, E_plain, t_plain, n_col):
+    """Multicoordinate descent from a fresh start until it reaches E_plain."""
+    t0 = time.perf_counter()
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << args.table_log2, z_threshold=args.tau)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    best_k, rates = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.05, rounds=2)
+    E = api.cdfci_energy(ctx)
+    steps = 0
+    elements = 0
+    while E > E_plain and time.perf_counter() - t0 < args.mc_limit:
+        st = api.cdfci_step(ctx, best_k, 20)
+        steps += st["steps"]
+        elements += st["elements"]
+        E = st["energy"]
+        if st["stopped"]:
+            break
+    t_mc = time.perf_counter() - t0
+    ctx.close()
+    return {"plain_seconds": t_plain, "plain_energy": E_plain,
+            "batched_seconds": t_mc, "batched_energy": E, "reached": bool(E <= E_plain),
+            "speedup": t_plain / t_mc if E <= E_plain else None,
+            "k": best_k, "tune_rates_Ha_per_s": rates, "batched_steps_after_tuning": steps,
+            "batched_elements_per_s_after_tuning": elements / max(t_mc, 1e-9),
+            "init_seconds": t_init,
+            "note": "both from their own fresh init; tuning trials count toward the batched time"}
+
+
+def mcd_n36(api, synth_inputs, args):
+    N, na, nb = 36, 8, 8
+    h, eri = synth_inputs.ab_initio(N, 108, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
+    out = {"workload": "ab initio N=36 8a+8b naux=108 seed=3636, 2^30-slot table, tau=5e-5",
+           "column_entries": 71793}
+    import torch
+
+    for k in (64, 256, 1024):
+        ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
+        api.cdfci_step(ctx, k, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = api.cdfci_step(ctx, k, args.n36_steps)
+        wall = time.perf_counter() - t0
+        out[f"k{k}"] = {"ms_per_step": 1e3 * wall / max(1, st["steps"]),
+                        "elements_per_s": st["elements"] / wall,
+                        "coordinate_updates_per_s": st["steps"] * k / wall,
+                        "energy": st["energy"]}
+        ctx.close()
+        log(f"n36 k={k}: {out[f'k{k}']}")
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
+    api.cdfci_step(ctx, 1, 2000)
+    t0 = time.perf_counter()
+    st = api.cdfci_step(ctx, 1, 20000)
+    wall = time.perf_counter() - t0
+    out["k1"] = {"iters_per_s": st["steps"] / wall, "elements_per_s": st["elements"] / wall}
+    ctx.close()
+    return out
+
+
+def hubbard_batch(api, synth_inputs, args):
+    specs = synth_inputs.hubbard_batch_specs(256, synth_inputs.CONFIG_SEEDS["hubbard_batch"])
+    t0 = time.perf_counter()
+    B = api.cdfci_init_hubbard_batch(specs, max_table_slots=1 << 22, dx_threshold=1e-10)
+    t_init = time.perf_counter() - t0
+    chunk, launches = api.cdfci_tune_batch(B, chunks=(512, 2048), launches=(2, 8), steps_per_trial=4000)
+    t0 = time.perf_counter()
+    st = api.cdfci_step_batch(B, args.batch_steps)
+    wall = time.perf_counter() - t0
+    E, steps, status = api.cdfci_batch_results(B)
+    B.close()
+    # the single-instance path on a sample of the same instances, one after another
+    plain_steps, plain_wall = 0, 0.0
+    seen = set()
+    for sp in specs:
+        if sp["dims"] in seen:
+            continue
+        seen.add(sp["dims"])
+        ctx = api.cdfci_init_hubbard(sp["dims"], sp["t"], sp["U"], sp["n_alpha"], sp["n_beta"],
+                                     table_slots=1 << 22)
+        t1 = time.perf_counter()
+        s1 = api.cdfci_step(ctx, 1, 20000)
+        plain_wall += time.perf_counter() - t1
+        plain_steps += s1["steps"]
+        ctx.close()
+    plain_rate = plain_steps / plain_wall
+    shapes = {}
+    for sp in specs:
+        shapes[str(sp["dims"])] = shapes.get(str(sp["dims"]), 0) + 1
+    return {"instances": len(specs), "shapes": shapes, "init_seconds": t_init,
+            "chunk_steps": chunk, "launches_per_graph": launches,
+            "budget_per_instance": args.batch_steps,
+            "iters_per_s": st["steps"] / wall, "elements_per_s": st["elements"] / wall,
+            "wall_seconds": wall, "graph_replays": st["graph_replays"],
+            "stopped": int((status == 1).sum()), "failed": int((status < 0).sum()),
+            "plain_single_instance_iters_per_s": plain_rate,
+            "batched_over_plain": (st["steps"] / wall) / plain_rate,
+            "plain_sample": f"{len(seen)} instances (one per shape), 20000 iterations each, run one after another"}
+
+
+def rdm_block(api, ctx, n_col):
+    top_n = 1_000_000
+    ka, _, _, _ = api.cdfci_export(ctx, top_n=top_n)
+    n_sup = len(ka)
+    t0 = time.perf_counter()
+    energy, dh, deri, kap = api.cdfci_rdm_backward(ctx, 1.0, top_n)
+    wall = time.perf_counter() - t0
+    return {"top_n": top_n, "support": n_sup, "seconds": wall,
+            "pair_visits_per_s": n_sup * n_col / wall, "energy_rdm": energy[0],
+            "energy_direct": energy[1], "note": "wall time of cdfci_rdm_backward incl. host copies of "
+                                                "gamma, Gamma (24^4) and kappa"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +210,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--mc-limit", type=float, default=60.0)
+    ap.add_argument("--n36-steps", type=int, default=8)
+    ap.add_argument("--batch-steps", type=int, default=100000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU layout is a design "
@@ -87,9 +241,12 @@ def main():
     n_col = 16471
     ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << args.table_log2, z_threshold=args.tau,
                          grid_blocks=args.grid)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
     for _ in range(args.warmup):
         api.cdfci_step(ctx, 1, args.iters)
     torch.cuda.synchronize()
+    warm_wall = time.perf_counter() - tw
     kernel_s = 0.0
     iters = 0
     t0 = time.perf_counter()
@@ -99,9 +256,11 @@ def main():
         iters += st["steps"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"plain: {iters} iterations in {wall:.2f} s, E = {st['energy']:.10f}")
     elements = iters * n_col
     value = elements / wall
     achieved = BYTES_PER_ELEMENT * elements / kernel_s / 1e9
+    per_el = measured_traffic_per_element()
     out = {
         "metric": "H elements/s + CD iters/s to 1e-5 Ha, batched vs plain, 1 MI355X",
         "value": value,
@@ -124,12 +283,32 @@ def main():
         "occupied": st["occupied"],
         "total_iterations": st["total_steps"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cd1", "avg_launch_ms": 1e3 * kernel_s / args.steps},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (per_el * args.iters * n_col) if per_el is not None else None,
+                     "kernel": "k_cd1", "avg_launch_ms": 1e3 * kernel_s / args.steps,
+                     "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * args.iters * n_col},
     }
+    if not args.no_extra:
+        try:
+            out["rdm"] = rdm_block(api, ctx, n_col)
+            log(f"rdm: {out['rdm']}")
+        except Exception as e:  # reported, not fatal
+            out["rdm"] = {"error": str(e)}
+    ctx.close()
+    if not args.no_extra:
+        for name, fn in (("batched_vs_plain",
+                          lambda: batched_vs_plain(api, h, eri, na, nb, args, st["energy"], warm_wall + wall,
+                                                   n_col)),
+                         ("mcd_n36", lambda: mcd_n36(api, synth_inputs, args)),
+                         ("hubbard_batch", lambda: hubbard_batch(api, synth_inputs, args))):
+            try:
+                out[name] = fn()
+                log(f"{name}: done")
+            except Exception as e:
+                out[name] = {"error": str(e)}
+                log(f"{name}: error {e}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(h, eri, na, nb)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -243,6 +243,25 @@ int cdfci_batch_context(cdfci_batch* batch, int instance, cdfci_ctx** ctx);
 
 int cdfci_free_batch(cdfci_batch* batch);
 
+/* ---- Autotuning -------------------------------------------------------------
+ * Both tuners measure real work on the live state and keep it: the trial steps
+ * are ordinary steps (they move the state toward the minimiser). */
+
+/* Pick the number of coordinates per step among ks[0..nk) (each 1..1024) by
+ * the energy decrease per device-second.  Trials of about seconds_per_trial
+ * each run in `rounds` rounds, forward then backward through ks, so that the
+ * slowing convergence weighs on every candidate alike.  *best_k gets the
+ * winner; rates (nk doubles, may be NULL) the mean decrease in Ha/s. */
+int cdfci_tune_k(cdfci_ctx* ctx, const int* ks, int nk, double seconds_per_trial, int rounds, int* best_k,
+                 double* rates);
+
+/* Pick a batch's chunk_steps and launches_per_graph among the candidate lists
+ * by aggregate iterations per device-second over steps_per_trial iterations
+ * per instance each; the winners become the batch's settings.  best_chunk and
+ * best_launches may be NULL. */
+int cdfci_tune_batch(cdfci_batch* batch, const int64_t* chunks, int nc, const int* launches, int nl,
+                     int64_t steps_per_trial, int64_t* best_chunk, int* best_launches);
+
 const char* cdfci_strerror(int code);
 const char* cdfci_last_error(void);
 

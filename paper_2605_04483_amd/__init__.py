@@ -9,10 +9,10 @@ from .api import (Batch, CDFCIError, Context, cdfci_batch_context, cdfci_batch_r
                   cdfci_column, cdfci_energy, cdfci_entry, cdfci_export, cdfci_free, cdfci_free_batch,
                   cdfci_init, cdfci_init_hubbard, cdfci_init_hubbard_batch, cdfci_phase_times,
                   cdfci_rdm_backward, cdfci_step, cdfci_step_batch, cdfci_step_energies, cdfci_step_trace,
-                  cdfci_strerror, cdfci_workspace_size, make_opts)
+                  cdfci_strerror, cdfci_tune_batch, cdfci_tune_k, cdfci_workspace_size, make_opts)
 
 __all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch_results", "cdfci_batch_trace",
            "cdfci_column", "cdfci_energy", "cdfci_entry", "cdfci_export", "cdfci_free", "cdfci_free_batch",
            "cdfci_init", "cdfci_init_hubbard", "cdfci_init_hubbard_batch", "cdfci_phase_times",
            "cdfci_rdm_backward", "cdfci_step", "cdfci_step_batch", "cdfci_step_energies", "cdfci_step_trace",
-           "cdfci_strerror", "cdfci_workspace_size", "make_opts"]
+           "cdfci_strerror", "cdfci_tune_batch", "cdfci_tune_k", "cdfci_workspace_size", "make_opts"]

@@ -128,6 +128,12 @@ SIGNATURES = [
     ("cdfci_batch_trace", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, _DP, _UP, _UP]),
     ("cdfci_batch_context", ctypes.c_int, [_P, ctypes.c_int, _CTXP]),
     ("cdfci_free_batch", ctypes.c_int, [_P]),
+    ("cdfci_tune_k", ctypes.c_int,
+     [_P, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_int,
+      ctypes.POINTER(ctypes.c_int), _DP]),
+    ("cdfci_tune_batch", ctypes.c_int,
+     [_P, _I64P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64, _I64P,
+      ctypes.POINTER(ctypes.c_int)]),
     ("cdfci_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cdfci_last_error", ctypes.c_char_p, []),
 ]

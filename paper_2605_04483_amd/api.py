@@ -312,3 +312,26 @@ def cdfci_batch_context(batch, instance):
 
 def cdfci_free_batch(batch):
     batch.close()
+
+
+# ---------------------------------------------------------------- autotuning
+
+def cdfci_tune_k(ctx, ks=(64, 256, 1024), seconds_per_trial=0.05, rounds=2):
+    """Returns (best_k, {k: Ha/s})."""
+    arr = (ctypes.c_int * len(ks))(*[int(k) for k in ks])
+    rates = np.zeros(len(ks))
+    best = ctypes.c_int(0)
+    _check(_lib.load().cdfci_tune_k(ctx.handle, arr, len(ks), float(seconds_per_trial), int(rounds),
+                                    ctypes.byref(best), _dp(rates)), "cdfci_tune_k")
+    return best.value, dict(zip((int(k) for k in ks), rates.tolist()))
+
+
+def cdfci_tune_batch(batch, chunks=(256, 1024, 4096), launches=(1, 4, 16), steps_per_trial=20000):
+    """Returns (best_chunk, best_launches)."""
+    ca = (ctypes.c_int64 * len(chunks))(*[int(c) for c in chunks])
+    la = (ctypes.c_int * len(launches))(*[int(x) for x in launches])
+    bc = ctypes.c_int64(0)
+    bl = ctypes.c_int(0)
+    _check(_lib.load().cdfci_tune_batch(batch.handle, ca, len(chunks), la, len(launches), int(steps_per_trial),
+                                        ctypes.byref(bc), ctypes.byref(bl)), "cdfci_tune_batch")
+    return bc.value, bl.value

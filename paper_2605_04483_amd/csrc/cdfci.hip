@@ -605,74 +605,136 @@ __global__ void k_select_final(const Partial* parts, int n, Ctl* ctl) {
 
 constexpr int kMaxSub = 128;
 
-__global__ void k_subspace_init(Ham H, uint64_t a0, uint64_t b0, int64_t n_col, InitTask* out,
-                                int* n_out, double* work /* kMaxSub^2 * 2 */, int* status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Lists L;
-  make_lists_serial(a0, b0, H.N, L);
-  double d0 = diag_serial(H, L);
-  int n = 0;
-  out[n++] = InitTask{a0, b0, 0.0};
-  for (int64_t e = 1; e < n_col; ++e) {
-    uint64_t ja, jb;
-    double v = column_entry(H, L, a0, b0, e, d0, &ja, &jb);
-    if (v == 0.0) continue;
-    if (n >= kMaxSub) {
-      *status = -2;
-      return;
-    }
-    out[n++] = InitTask{ja, jb, 0.0};
+// One workgroup of 256 threads.  Tasks: D0, then the nonzero entries of its
+// column in enumeration order (an order-preserving compaction); A on them;
+// cyclic Jacobi in the parallel (round-robin) ordering: each round rotates
+// n/2 disjoint index pairs at once, which is the same transform as applying
+// those rotations one after another (disjoint planes commute, and each
+// rotation's 2 x 2 block depends on its own rows and columns only).
+__global__ void __launch_bounds__(256) k_subspace_init(Ham H, uint64_t a0, uint64_t b0, int64_t n_col,
+                                                       InitTask* out, int* n_out,
+                                                       double* work /* kMaxSub^2 * 2 */, int* status) {
+  __shared__ Lists L;
+  __shared__ double s_red[4];
+  __shared__ int s_n, s_wave[4];
+  __shared__ double s_c[kMaxSub / 2], s_s[kMaxSub / 2];
+  __shared__ int s_p[kMaxSub / 2], s_q[kMaxSub / 2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  make_lists_block(a0, b0, H.N, L);
+  __syncthreads();
+  double part = 0.0;
+  const int nt = diag_terms(L);
+  for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+  const double d0 = wg_sum(part, s_red);
+  if (tid == 0) {
+    out[0] = InitTask{a0, b0, 0.0};
+    s_n = 1;
+  }
+  __syncthreads();
+  for (int64_t base = 1; base < n_col; base += blockDim.x) {
+    const int64_t e = base + tid;
+    uint64_t ja = 0, jb = 0;
+    double v = 0.0;
+    if (e < n_col) v = column_entry(H, L, a0, b0, e, d0, &ja, &jb);
+    const bool nz = e < n_col && v != 0.0;
+    const unsigned long long bal = __ballot(nz);
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wv] = __popcll(bal);
+    __syncthreads();
+    int pos = s_n + below;
+    for (int q = 0; q < wv; ++q) pos += s_wave[q];
+    if (nz && pos < kMaxSub) out[pos] = InitTask{ja, jb, 0.0};
+    __syncthreads();
+    if (tid == 0) s_n += s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+  }
+  const int n = s_n;
+  if (n > kMaxSub) {
+    if (tid == 0) *status = -2;
+    return;
   }
   double* A = work;
   double* V = work + kMaxSub * kMaxSub;
-  for (int j = 0; j < n; ++j) {
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
     Lists Lj;
     make_lists_serial(out[j].a, out[j].b, H.N, Lj);
-    double dj = diag_serial(H, Lj);
-    for (int i = 0; i < n; ++i) A[i * n + j] = sc_entry(H, out[i].a, out[i].b, out[j].a, out[j].b, Lj, dj);
+    const double dj = (i == j) ? diag_serial(H, Lj) : 0.0;
+    A[i * n + j] = sc_entry(H, out[i].a, out[i].b, out[j].a, out[j].b, Lj, dj);
+    V[i * n + j] = (i == j) ? 1.0 : 0.0;
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
-  // cyclic Jacobi sweeps (Golub & Van Loan, symmetric Schur rotations)
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
-    if (off < 1e-30) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double apq = A[p * n + q];
-        if (apq == 0.0) continue;
-        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
+  __syncthreads();
+  const int m2 = n + (n & 1);  // even number of positions; position n (if any) is idle
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    double o = 0.0;
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+      const int i = idx / n, j = idx % n;
+      if (i < j) o += A[idx] * A[idx];
+    }
+    o = wg_sum(o, s_red);
+    if (o < 1e-30) break;
+    for (int r = 0; r < m2 - 1; ++r) {
+      if (tid < m2 / 2) {
+        // round-robin pairing: position 0 fixed, the others rotate
+        const int k = tid;
+        const int x = k == 0 ? 0 : 1 + (k - 1 + r) % (m2 - 1);
+        const int y = 1 + (m2 - 2 - k + r) % (m2 - 1);
+        int p = x < y ? x : y, q = x < y ? y : x;
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          if (apq != 0.0) {
+            const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+          }
+        } else {
+          p = q = -1;
         }
-        for (int k = 0; k < n; ++k) {
-          double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          double vkp = V[k * n + p], vkq = V[k * n + q];
-          V[k * n + p] = c * vkp - s * vkq;
-          V[k * n + q] = s * vkp + c * vkq;
-        }
+        s_p[k] = p;
+        s_q[k] = q;
+        s_c[k] = c;
+        s_s[k] = sn;
       }
+      __syncthreads();
+      const int np = m2 / 2;
+      // A <- J^T A: rows p, q of every pair
+      for (int idx = tid; idx < np * n; idx += blockDim.x) {
+        const int k = idx / n, col = idx % n, p = s_p[k], q = s_q[k];
+        if (p < 0 || s_s[k] == 0.0) continue;
+        const double c = s_c[k], sn = s_s[k];
+        const double apk = A[p * n + col], aqk = A[q * n + col];
+        A[p * n + col] = c * apk - sn * aqk;
+        A[q * n + col] = sn * apk + c * aqk;
+      }
+      __syncthreads();
+      // A <- A J and V <- V J: columns p, q of every pair
+      for (int idx = tid; idx < np * n; idx += blockDim.x) {
+        const int k = idx / n, row = idx % n, p = s_p[k], q = s_q[k];
+        if (p < 0 || s_s[k] == 0.0) continue;
+        const double c = s_c[k], sn = s_s[k];
+        const double akp = A[row * n + p], akq = A[row * n + q];
+        A[row * n + p] = c * akp - sn * akq;
+        A[row * n + q] = sn * akp + c * akq;
+        const double vkp = V[row * n + p], vkq = V[row * n + q];
+        V[row * n + p] = c * vkp - sn * vkq;
+        V[row * n + q] = sn * vkp + c * vkq;
+      }
+      __syncthreads();
+    }
   }
+  if (tid != 0) return;
   int m = 0;
   for (int i = 1; i < n; ++i)
     if (A[i * n + i] < A[m * n + m]) m = i;
-  double lam = A[m * n + m];
+  const double lam = A[m * n + m];
   if (!(lam < 0.0)) {
     *status = -4;
     return;
   }
-  double sgn = V[0 * n + m] < 0.0 ? -1.0 : 1.0;
-  double scale = sqrt(-lam) * sgn;
+  const double sgn = V[0 * n + m] < 0.0 ? -1.0 : 1.0;
+  const double scale = sqrt(-lam) * sgn;
   for (int i = 0; i < n; ++i) out[i].coef = scale * V[i * n + m];
   *n_out = n;
   *status = 0;
@@ -999,7 +1061,7 @@ int setup_and_init(cdfci_ctx* c, int init_kind, uint64_t neel_a, uint64_t neel_b
   if (init_kind == 2) {
     HIP_TRY(hipMalloc(&d_work, 2 * kMaxSub * kMaxSub * sizeof(double)));
     d_n = d_stat + 1;
-    k_subspace_init<<<1, 1, 0, s>>>(H, neel_a, neel_b, c->n_col, d_tasks, d_n, d_work, d_stat);
+    k_subspace_init<<<1, 256, 0, s>>>(H, neel_a, neel_b, c->n_col, d_tasks, d_n, d_work, d_stat);
   } else {
     k_aufbau_init<<<1, 1, 0, s>>>(H, d_tasks, d_stat);
   }
@@ -1343,11 +1405,12 @@ static constexpr int kMaxK = 1024;
 // candidate list, so *lost is set and the caller must rebuild it.
 static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
   *lost = false;
-  // pages: one per scatter workgroup (k columns x chunks) plus the chosen set,
-  // or enough for every stored entry when the list is rebuilt from the table
+  // pages: one per scatter workgroup (k columns x chunks) plus the chosen set;
+  // when the list is (re)built from the table (entering the multicoordinate
+  // state) also enough for every stored entry.  Growth keeps 1/4 headroom.
   const uint64_t chunks = (uint64_t)((c->n_col + kPage - 1) / kPage);
-  const uint64_t pages = std::max<uint64_t>((uint64_t)k * chunks + (k + kPage - 1) / kPage,
-                                            (occupied + 1 + kPage - 1) / kPage);
+  uint64_t pages = (uint64_t)k * chunks + (k + kPage - 1) / kPage;
+  if (c->mode != 1) pages = std::max<uint64_t>(pages, (occupied + 1 + kPage - 1) / kPage);
   const uint64_t need_cand = pages * kPage;
   if (k > c->mc_kcap || need_cand > c->cand_cap) {
     // release and reallocate at the larger size
@@ -1356,7 +1419,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     for (void* p : olds)
       if (p) (void)hipFree(p);
     const int kc = std::max(k, c->mc_kcap);
-    const uint64_t cc = std::max(need_cand, c->cand_cap);
+    const uint64_t cc = std::max(need_cand + need_cand / 4, c->cand_cap);
     HIP_TRY(hipMalloc(&c->cand, cc * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->cnt, (cc / kPage) * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->gkey, cc * sizeof(unsigned long long)));
@@ -2037,6 +2100,93 @@ int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, 
 int cdfci_batch_context(cdfci_batch* B, int inst, cdfci_ctx** ctx) {
   if (!B || !ctx || inst < 0 || inst >= B->count) return CDFCI_ERR_INVALID_ARG;
   *ctx = B->ctx[inst];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning
+
+int cdfci_tune_k(cdfci_ctx* c, const int* ks, int nk, double seconds_per_trial, int rounds, int* best_k,
+                 double* rates) {
+  if (!c || !ks || nk < 1 || !best_k || rounds < 1 || !(seconds_per_trial > 0.0)) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nk; ++i)
+    if (ks[i] < 1 || ks[i] > kMaxK) return CDFCI_ERR_INVALID_ARG;
+  std::vector<double> sum(nk, 0.0), secs(nk, 0.0);
+  // an uncounted first trial: right after a start the energy falls far faster
+  // than later, which would favour whichever candidate ran first
+  for (int r = -1; r < rounds; ++r) {
+    for (int q = 0; q < nk; ++q) {
+      const int i = (r & 1) ? nk - 1 - q : q;
+      const int k = ks[i];
+      double E0 = 0.0, E1 = 0.0, t = 0.0;
+      int rc = cdfci_energy(c, 0, &E0);
+      if (rc) return rc;
+      int64_t n = 1;
+      for (int guard = 0; guard < 64 && t < seconds_per_trial; ++guard) {
+        cdfci_stats st;
+        rc = cdfci_step(c, k, n, &st);
+        if (rc) return rc;
+        t += st.seconds;
+        if (st.stopped || st.steps < n) break;
+        const double per = st.seconds / (double)std::max<int64_t>(1, st.steps);
+        const double left = seconds_per_trial - t;
+        n = std::max<int64_t>(1, std::min<int64_t>((int64_t)(left / std::max(per, 1e-7)), 4 * n));
+      }
+      rc = cdfci_energy(c, 0, &E1);
+      if (rc) return rc;
+      if (r < 0) break;
+      sum[i] += E0 - E1;
+      secs[i] += t;
+    }
+  }
+  int best = 0;
+  for (int i = 0; i < nk; ++i) {
+    const double rate = secs[i] > 0.0 ? sum[i] / secs[i] : 0.0;
+    if (rates) rates[i] = rate;
+    const double rb = secs[best] > 0.0 ? sum[best] / secs[best] : 0.0;
+    if (rate > rb) best = i;
+  }
+  *best_k = ks[best];
+  return 0;
+}
+
+int cdfci_tune_batch(cdfci_batch* B, const int64_t* chunks, int nc, const int* launches, int nl,
+                     int64_t steps_per_trial, int64_t* best_chunk, int* best_launches) {
+  if (!B || !chunks || nc < 1 || !launches || nl < 1 || steps_per_trial < 1) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nc; ++i)
+    if (chunks[i] < 1) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nl; ++i)
+    if (launches[i] < 1 || launches[i] > 64) return CDFCI_ERR_INVALID_ARG;
+  double best_rate = -1.0;
+  int64_t bc = B->opts.chunk_steps;
+  int bl = B->opts.launches_per_graph;
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nl; ++j) {
+      // a new setting needs a new graph
+      if (B->exec) (void)hipGraphExecDestroy(B->exec);
+      if (B->graph) (void)hipGraphDestroy(B->graph);
+      B->exec = nullptr;
+      B->graph = nullptr;
+      B->opts.chunk_steps = chunks[i];
+      B->opts.launches_per_graph = launches[j];
+      cdfci_batch_stats st;
+      const int rc = cdfci_step_batch(B, steps_per_trial, &st);
+      if (rc) return rc;
+      const double rate = st.seconds > 0.0 ? (double)st.steps / st.seconds : 0.0;
+      if (rate > best_rate) {
+        best_rate = rate;
+        bc = chunks[i];
+        bl = launches[j];
+      }
+    }
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  B->opts.chunk_steps = bc;
+  B->opts.launches_per_graph = bl;
+  if (best_chunk) *best_chunk = bc;
+  if (best_launches) *best_launches = bl;
   return 0;
 }
 

@@ -239,6 +239,28 @@ __device__ __forceinline__ dd dd_mul(dd x, dd y) {
 }
 __device__ __forceinline__ double dd_val(dd x) { return x.hi + x.lo; }
 
+// workgroup sum (any power-of-two size up to 1024), fixed order
+__device__ inline double wg_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(v, off);
+    v = (lane & off) ? (o + v) : (v + o);
+  }
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ inline dd wg_sum_dd(dd v, double* scratch) {
+  double hi = wg_sum(v.hi, scratch);
+  double lo = wg_sum(v.lo, scratch);
+  return two_sum(hi, lo);
+}
+
 // ---------------------------------------------------------------- line search
 
 __device__ __forceinline__ double quartic(double e, double v1, double v2, double v3) {

@@ -260,28 +260,6 @@ __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwo
   if (blockIdx.x == 0 && threadIdx.x == 0) st->n_tie = 0;
 }
 
-// workgroup sum (any power-of-two size up to 1024), fixed order
-__device__ double wg_sum(double v, double* scratch) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(v, off);
-    v = (lane & off) ? (o + v) : (v + o);
-  }
-  __syncthreads();
-  if (lane == 0) scratch[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < nw; ++i) s += scratch[i];
-  __syncthreads();
-  return s;
-}
-
-__device__ dd wg_sum_dd(dd v, double* scratch) {
-  double hi = wg_sum(v.hi, scratch);
-  double lo = wg_sum(v.lo, scratch);
-  return two_sum(hi, lo);
-}
-
 // H_II: block y builds column y (ket = chosen determinant y)
 __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, const uint64_t* sel_b,
                                                 const McState* st, double* hii, int k) {

@@ -123,7 +123,7 @@ def mcd_n36(api, synth_inputs, args):
            "column_entries": 71793}
     import torch
 
-    for k in (64, 256, 1024):
+    for k in ((args.n36_k,) if args.n36_k else (64, 256, 1024)):
         ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
         api.cdfci_step(ctx, k, 2)
         torch.cuda.synchronize()
@@ -136,6 +136,8 @@ def mcd_n36(api, synth_inputs, args):
                         "energy": st["energy"]}
         ctx.close()
         log(f"n36 k={k}: {out[f'k{k}']}")
+    if args.n36_k:
+        return out
     ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
     api.cdfci_step(ctx, 1, 2000)
     t0 = time.perf_counter()
@@ -214,6 +216,9 @@ def main():
     ap.add_argument("--mc-limit", type=float, default=60.0)
     ap.add_argument("--n36-steps", type=int, default=8)
     ap.add_argument("--batch-steps", type=int, default=100000)
+    ap.add_argument("--only", choices=("n36", "hubbard", "rdm"), default=None,
+                    help="diagnostic: run one extra block alone (for profiler runs) and print it")
+    ap.add_argument("--n36-k", type=int, default=0, help="with --only n36: a single k")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU layout is a design "
@@ -234,6 +239,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8}), flush=True)
+        return
+    if args.only == "n36":
+        print(json.dumps({"mcd_n36": mcd_n36(api, synth_inputs, args)}), flush=True)
+        return
+    if args.only == "hubbard":
+        print(json.dumps({"hubbard_batch": hubbard_batch(api, synth_inputs, args)}), flush=True)
         return
     N, na, nb, naux = 24, 6, 6, 72
     seed = synth_inputs.CONFIG_SEEDS["abinitio_n24"]
@@ -288,6 +299,10 @@ def main():
                      "kernel": "k_cd1", "avg_launch_ms": 1e3 * kernel_s / args.steps,
                      "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * args.iters * n_col},
     }
+    if args.only == "rdm":
+        print(json.dumps({"rdm": rdm_block(api, ctx, n_col)}), flush=True)
+        ctx.close()
+        return
     if not args.no_extra:
         try:
             out["rdm"] = rdm_block(api, ctx, n_col)

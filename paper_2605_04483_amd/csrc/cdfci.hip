@@ -459,6 +459,22 @@ __global__ void k_reset_barrier(Ctl* ctl) {
 // Coulomb/exchange rows for single excitations: jk[((r*N+p)*N+k)*2] = (rp|kk),
 // jk[((r*N+p)*N+k)*2+1] = (rk|kp).
 
+// packed (pq|rs): thread t of row pq (grid y) writes the value for rs = t <= pq
+__global__ void __launch_bounds__(256) k_build_eri8(const double* eri, int N, double* eri8) {
+  const int npair = N * (N + 1) / 2;
+  const int pq = blockIdx.y;
+  if (pq >= npair) return;
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 <= pq) ++p;
+  const int q = pq - p * (p + 1) / 2;
+  for (int rs = blockIdx.x * blockDim.x + threadIdx.x; rs <= pq; rs += gridDim.x * blockDim.x) {
+    int r = 0;
+    while ((r + 1) * (r + 2) / 2 <= rs) ++r;
+    const int s = rs - r * (r + 1) / 2;
+    eri8[(int64_t)pq * (pq + 1) / 2 + rs] = eri[(((size_t)p * N + q) * N + r) * N + s];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_build_jk(const double* eri, int N, double* jk) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)N * N * N;
@@ -907,6 +923,7 @@ struct cdfci_ctx {
   hipStream_t stream;
   double* d_h = nullptr;
   double* d_eri = nullptr;
+  double* d_eri8 = nullptr;
   double* d_jk = nullptr;
   Slot* T = nullptr;
   uint64_t nslots = 0, mask = 0, max_entries = 0;
@@ -962,7 +979,7 @@ struct cdfci_batch {
 
 namespace {
 
-Ham ham_of(const cdfci_ctx* c) { return Ham{c->N, c->na, c->nb, c->d_h, c->d_eri, c->d_jk}; }
+Ham ham_of(const cdfci_ctx* c) { return Ham{c->N, c->na, c->nb, c->d_h, c->d_eri8, c->d_jk}; }
 
 int ctl_read(cdfci_ctx* c, Ctl* host) {
   HIP_TRY(hipMemcpyAsync(host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
@@ -1129,6 +1146,9 @@ int upload(cdfci_ctx* c, const double* h, const double* eri) {
   HIP_TRY(hipMalloc(&c->d_jk, 2 * N * N * N * sizeof(double)));
   const int64_t njk = (int64_t)N * N * N;
   k_build_jk<<<(int)((njk + 255) / 256), 256, 0, c->stream>>>(c->d_eri, c->N, c->d_jk);
+  const int npair = (int)(N * (N + 1) / 2);
+  HIP_TRY(hipMalloc(&c->d_eri8, (size_t)npair * (npair + 1) / 2 * sizeof(double)));
+  k_build_eri8<<<dim3((npair + 255) / 256, npair), 256, 0, c->stream>>>(c->d_eri, c->N, c->d_eri8);
   HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -1798,6 +1818,7 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->own_table && c->T) (void)hipFree(c->T);
   if (c->d_h) (void)hipFree(c->d_h);
   if (c->d_eri) (void)hipFree(c->d_eri);
+  if (c->d_eri8) (void)hipFree(c->d_eri8);
   if (c->d_jk) (void)hipFree(c->d_jk);
   if (c->ctl) (void)hipFree(c->ctl);
   if (c->parts) (void)hipFree(c->parts);

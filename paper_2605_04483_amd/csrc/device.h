@@ -34,7 +34,8 @@ struct alignas(32) Slot {
   double c, b;
 };
 
-// Hamiltonian view.  eri is the full N^4 chemist tensor (pq|rs).
+// Hamiltonian view.  eri is the packed 8-fold-symmetric chemist tensor (see
+// ERI below); the full N^4 tensor is kept separately where it is contracted.
 struct Ham {
   int N, na, nb;
   const double* __restrict__ h;
@@ -140,6 +141,9 @@ __device__ inline int64_t table_find(const Slot* __restrict__ T, uint64_t mask, 
         do {
           v.kb = ld_co(&T[idx].kb);
         } while (v.kb == kPending && ++spin < (1 << 20));
+        // c and b are meaningful once the beta word is published
+        v.c = ld_co(&T[idx].c);
+        v.b = ld_co(&T[idx].b);
       }
       if (v.kb == b) {
         *probes = n + 1;
@@ -322,9 +326,19 @@ __device__ inline double line_search(double v1, double v2, double v3) {
 
 // ---------------------------------------------------------------- Slater-Condon
 
+// (pq|rs) from the packed tensor: one value per orbit of the 8-fold symmetry
+// (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq) = ..., at the canonical position of
+// the ordered pairs pq >= rs with p >= q, r >= s.  N(N+1)/2 (N(N+1)/2 + 1) / 2
+// values: 1.78 MB at 36 orbitals, small enough to stay in one XCD's L2.
+__device__ __forceinline__ int pair_index(int p, int q) {
+  return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p;
+}
+__device__ __forceinline__ int64_t eri8_index(int p, int q, int r, int s) {
+  const int64_t pq = pair_index(p, q), rs = pair_index(r, s);
+  return pq >= rs ? pq * (pq + 1) / 2 + rs : rs * (rs + 1) / 2 + pq;
+}
 __device__ __forceinline__ double ERI(const Ham& H, int p, int q, int r, int s) {
-  const int N = H.N;
-  return H.eri[((size_t)(p * N + q) * N + r) * N + s];
+  return H.eri[eri8_index(p, q, r, s)];
 }
 
 // Occupied / virtual orbital lists of the column's determinant.

@@ -82,10 +82,9 @@ __global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* 
   for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < pages;
        p += (unsigned long long)gridDim.x * blockDim.x)
     cnt[p] = (unsigned)min((unsigned long long)kPage, n - p * kPage);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->n_pages = pages;
-    st->n_dense = 0;
-  }
+  // every workgroup reads n_dense above, so it is reset by k_mc_clear (which
+  // runs before the next list is built), not here
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_pages = pages;
 }
 
 // radix-select histogram pass; pass 0 also computes the keys (|g| for the
@@ -257,7 +256,10 @@ __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwo
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
        i += (uint64_t)gridDim.x * blockDim.x)
     bitmap[i] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_tie = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->n_tie = 0;
+    st->n_dense = 0;
+  }
 }
 
 // H_II: block y builds column y (ket = chosen determinant y)

@@ -14,7 +14,8 @@ Further blocks on the same JSON line (skipped with --no-extra):
                     multicoordinate step (k picked by the autotuner), timed to
                     the energy the plain run reached;
   mcd_n36           N = 36, 8+8, naux 108, 2^30 slots, tau 5e-5: elements/s and
-                    ms per step for k = 64, 256, 1024 and for k = 1;
+                    ms per step for k = 64, 256, 1024; k = 1 for a fixed wall time,
+                    then the autotuned multicoordinate step timed to that energy;
   hubbard_batch     256 periodic lattices from {2x4, 3x4, 4x4, 2x8, 3x5}, half
                     filling, U ~ [2, 10], in one persistent kernel under a
                     replayed graph (autotuned), against the single-instance
@@ -138,13 +139,39 @@ def mcd_n36(api, synth_inputs, args):
         log(f"n36 k={k}: {out[f'k{k}']}")
     if args.n36_k:
         return out
+    # plain single-coordinate descent for a fixed wall time, then the
+    # multicoordinate step (k autotuned) from its own fresh start, timed to the
+    # energy the plain run reached
     ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
-    api.cdfci_step(ctx, 1, 2000)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = api.cdfci_step(ctx, 1, 20000)
-    wall = time.perf_counter() - t0
-    out["k1"] = {"iters_per_s": st["steps"] / wall, "elements_per_s": st["elements"] / wall}
+    iters = 0
+    while time.perf_counter() - t0 < args.n36_plain_seconds:
+        st = api.cdfci_step(ctx, 1, 20000)
+        iters += st["steps"]
+    t_plain = time.perf_counter() - t0
+    E_plain = st["energy"]
+    out["k1"] = {"iters_per_s": iters / t_plain, "elements_per_s": iters * 71793 / t_plain,
+                 "seconds": t_plain, "energy": E_plain}
     ctx.close()
+    log(f"n36 plain: {out['k1']}")
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best_k, rates = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.05, rounds=2)
+    E = api.cdfci_energy(ctx)
+    while E > E_plain and time.perf_counter() - t0 < 3 * t_plain:
+        st = api.cdfci_step(ctx, best_k, 10)
+        E = st["energy"]
+        if st["stopped"]:
+            break
+    t_mc = time.perf_counter() - t0
+    ctx.close()
+    out["batched_vs_plain"] = {"plain_seconds": t_plain, "plain_energy": E_plain, "batched_seconds": t_mc,
+                               "batched_energy": E, "reached": bool(E <= E_plain), "k": best_k,
+                               "speedup": t_plain / t_mc if E <= E_plain else None,
+                               "tune_rates_Ha_per_s": rates}
+    log(f"n36 batched vs plain: {out['batched_vs_plain']}")
     return out
 
 
@@ -215,6 +242,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--mc-limit", type=float, default=60.0)
     ap.add_argument("--n36-steps", type=int, default=8)
+    ap.add_argument("--n36-plain-seconds", type=float, default=20.0)
     ap.add_argument("--batch-steps", type=int, default=100000)
     ap.add_argument("--only", choices=("n36", "hubbard", "rdm"), default=None,
                     help="diagnostic: run one extra block alone (for profiler runs) and print it")

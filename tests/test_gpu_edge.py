@@ -1,0 +1,90 @@
+"""GPU edge cases through the C ABI, against the CPU oracle: the largest
+orbital count the 64-bit keys allow (63), one spin channel empty, a single
+electron, a completely filled spin shell, and requests larger than the space
+(k above the number of determinants, top_n above the support).  Bars as in the
+other GPU files: key sets bit-exact, entries 1e-12, energies 1e-8 Ha at
+convergence."""
+import numpy as np
+import pytest
+
+import synth_inputs
+from oracle import cd as ocd
+from oracle import fci
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2605_04483_amd as api
+
+    return api
+
+
+def _col_dict(ka, kb, v):
+    return {(int(a), int(b)): float(x) for a, b, x in zip(ka, kb, v)}
+
+
+def _column_parity(api, ctx, h, eri, dets):
+    N = h.shape[0]
+    for a, b in dets:
+        gka, gkb, gv = api.cdfci_column(ctx, (a, b))
+        oka, okb, ov = ocd.column(h, eri, a, b)
+        g = _col_dict(gka, gkb, gv)
+        o = _col_dict(oka, okb, ov)
+        assert len(gv) == len(ov)
+        assert set(g) == set(o)
+        assert max(abs(g[k] - o[k]) for k in o) <= 1e-12
+        assert (gka[0], gkb[0]) == (a, b)
+        assert all(int(x) >> N == 0 and int(y) >> N == 0 for x, y in g)
+
+
+def test_63_orbitals(api):
+    """Keys use bit 62; the packed integral tensor has 2016 * 2017 / 2 entries."""
+    N, na, nb = 63, 2, 2
+    h, eri = synth_inputs.ab_initio(N, 64, 63)
+    # 18,789-entry columns at tau = 0: 100 + 16 * 5 columns stay below 2^23 * 0.79 entries
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 23)
+    a_s, b_s = synth_inputs.random_dets(N, na, nb, 3, 64)
+    dets = list(zip(a_s.tolist(), b_s.tolist())) + [((1 << 61) | (1 << 62), (1 << 62) | 1)]
+    _column_parity(api, ctx, h, eri, dets)
+    st = api.cdfci_step(ctx, 1, 100)
+    assert abs(api.cdfci_energy(ctx, exact=1) - st["energy"]) < 1e-10 * abs(st["energy"])
+    st = api.cdfci_step(ctx, 16, 5)
+    assert abs(api.cdfci_energy(ctx, exact=1) - st["energy"]) < 1e-10 * abs(st["energy"])
+    ctx.close()
+
+
+@pytest.mark.parametrize("N,na,nb", [(10, 4, 0), (6, 1, 0), (6, 6, 3), (7, 0, 3)])
+def test_degenerate_electron_counts_converge(api, N, na, nb):
+    h, eri = synth_inputs.ab_initio(N, 3 * N, 100 + N + na)
+    E0 = ocd.ground_energy(h, eri, na, nb)
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 14, dx_threshold=1e-12)
+    a_s, b_s = synth_inputs.random_dets(N, na, nb, 2, 7)
+    _column_parity(api, ctx, h, eri, list(zip(a_s.tolist(), b_s.tolist())))
+    api.cdfci_step(ctx, 1, 100000)
+    assert abs(api.cdfci_energy(ctx, exact=1) - E0) < 1e-8, (N, na, nb)
+    ctx.close()
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 14, dx_threshold=1e-12)
+    E, st = api.cdfci_step_energies(ctx, 8, 20000)
+    assert abs(st["energy"] - E0) < 1e-8
+    ctx.close()
+
+
+def test_requests_larger_than_the_space(api):
+    """k = 1024 on a 36-determinant space and top_n far above the support."""
+    N, na, nb = 4, 2, 2
+    h, eri = synth_inputs.ab_initio(N, 12, 17)
+    E0 = ocd.ground_energy(h, eri, na, nb)
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 10)
+    E, st = api.cdfci_step_energies(ctx, 1024, 4)
+    assert abs(st["energy"] - E0) < 1e-10
+    energy, dh, deri, kap = api.cdfci_rdm_backward(ctx, 1.0, 10 ** 9)
+    assert abs(energy[0] - E0) < 1e-10 and abs(energy[1] - E0) < 1e-10
+    assert abs(np.trace(dh) - (na + nb)) < 1e-12
+    ka, kb, c, b = api.cdfci_export(ctx, top_n=10 ** 9)
+    assert len(ka) == np.count_nonzero(api.cdfci_export(ctx)[2])
+    ctx.close()

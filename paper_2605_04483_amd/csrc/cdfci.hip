@@ -1537,7 +1537,10 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     k_mc_ties<<<1, 256, 0, s>>>(c->T, c->mst, c->sel_slot, c->sel_a, c->sel_b, c->ties, k);
     k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, nwords, c->mst);
     k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k);
-    k_mc_eig<<<1, 1024, 0, s>>>(ea);
+    if (k <= kEigSmall)
+      k_mc_eig_small<<<1, 64 * kEigWaves, 0, s>>>(ea);
+    else
+      k_mc_eig<<<1, 1024, 0, s>>>(ea);
     k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
     k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);

@@ -8,8 +8,9 @@
 //            passes), exact ties at the threshold to the smaller key;
 //   H_II     pairwise Slater-Condon entries among the chosen determinants;
 //   reduced  A = Q^T H Q with Q = [c~, E_I] (eq. (def-z)); its lowest
-//            eigenpair by Lanczos with full reorthogonalisation started from
-//            the current point [nu; c_I]; gamma, eta; mu and alpha updates;
+//            eigenpair (k <= 64: Householder tridiagonalisation in shared
+//            memory; larger k: Lanczos with full reorthogonalisation started
+//            from the current point [nu; c_I]); gamma, eta; mu and alpha;
 //   scatter  b += H_{:,I} eta over the k columns with the compression rule,
 //            recalculation sums for b_I, touched entries marked in a slot
 //            bitmap and written to the workgroup's own candidate page;
@@ -43,6 +44,13 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 6;  // digits at bits 53, 42, 31, 20, 9 (11 wide) and 0 (9 wide)
 constexpr int kMaxTies = 4096;
 constexpr int kLanczosMax = 64;
+// nu^2 = ||c - E_I c_I||^2 is formed as mu - c_I.c_I.  mu is carried from
+// step to step while the stored c is rounded at every update, so the two
+// drift apart by a few ulps of mu per step; below this fraction of mu nu^2
+// cannot be told from that drift and the c~ column is dropped (nu = 0,
+// gamma = 1).  A genuine nu^2 this small changes the step's energy by about
+// the same relative amount.
+constexpr double kNu2Floor = 0x1p-36;
 
 __device__ __forceinline__ int radix_shift(int pass) { return pass < 5 ? 53 - 11 * pass : 0; }
 __device__ __forceinline__ unsigned long long radix_digit_mask(int pass) {
@@ -290,20 +298,35 @@ __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, co
 // no division (the minors are rescaled by powers of two to stay in range;
 // an exact zero minor counts as a tiny value of the opposite sign, as the
 // ratio form d_i = p_i / p_(i-1) -> -0 does).
-__device__ __forceinline__ int sturm_count(const double* a, const double* b, int n, double x) {
+__device__ __forceinline__ int sturm_count(const double* __restrict__ a, const double* __restrict__ b,
+                                           int n, double x) {
   int cnt = 0;
   double p0 = 1.0, p1 = a[0] - x;
   if (p1 == 0.0) p1 = -1e-300;
   cnt += p1 < 0.0;
-  for (int i = 1; i < n; ++i) {
-    double p2 = (a[i] - x) * p1 - (b[i - 1] * b[i - 1]) * p0;
-    if (p2 == 0.0) p2 = p1 < 0.0 ? 1e-300 : -1e-300;
-    cnt += (p2 < 0.0) != (p1 < 0.0);
-    p0 = p1;
-    p1 = p2;
-    const double m = fabs(p1);
-    if (m > 0x1p+400 || m < 0x1p-400) {
-      const int e = ilogb(m);
+  // eight terms at a time: their loads are issued together, and eight steps
+  // of the recurrence move a minor by far less than the 2^400 margin
+  for (int i0 = 1; i0 < n; i0 += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + u, n - 1);
+      av[u] = a[i];
+      bv[u] = b[i - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < n) {
+        double p2 = (av[u] - x) * p1 - (bv[u] * bv[u]) * p0;
+        if (p2 == 0.0) p2 = p1 < 0.0 ? 1e-300 : -1e-300;
+        cnt += (p2 < 0.0) != (p1 < 0.0);
+        p0 = p1;
+        p1 = p2;
+      }
+    }
+    const double mg = fabs(p1);
+    if (mg > 0x1p+400 || mg < 0x1p-400) {
+      const int e = ilogb(mg);
       p0 = ldexp(p0, -e);
       p1 = ldexp(p1, -e);
     }
@@ -314,10 +337,11 @@ __device__ __forceinline__ int sturm_count(const double* a, const double* b, int
 // Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)), called
 // by one full wave: 64-way multisection on the Sturm count (six bits per
 // round), then inverse iteration with partial pivoting by lane 0.  y and wk
-// live in shared memory; the eigenvalue is returned to every lane.  With
-// want_y == 0 only the eigenvalue is formed.
-__device__ double tri_lowest_wave(const double* a, const double* b, int n, double* y, double* wk,
-                                  int want_y = 1) {
+// (5 n doubles) live in shared memory; the eigenvalue is returned to every
+// lane.  With want_y == 0 only the eigenvalue is formed.  No workgroup
+// barrier is used, so one wave may call it while the others wait.
+__device__ double tri_lowest_wave(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                  double* __restrict__ y, double* __restrict__ wk, int want_y = 1) {
   const int lane = threadIdx.x & 63;
   if (n == 1) {
     if (lane == 0) y[0] = 1.0;
@@ -345,56 +369,68 @@ __device__ double tri_lowest_wave(const double* a, const double* b, int n, doubl
   const double lam = 0.5 * (lo + hi);
   if (lane == 0) {
     // inverse iteration on (T - lam I): Gaussian elimination with partial
-    // pivoting of a tridiagonal matrix (fill-in one extra superdiagonal)
+    // pivoting of a tridiagonal matrix (one extra superdiagonal of fill-in),
+    // the row being eliminated carried in registers.  The factors are
+    // stored as multipliers dl, reciprocal pivots rdm, superdiagonals du, du2.
     double* dl = wk;
-    double* dm = wk + n;
+    double* rdm = wk + n;
     double* du = wk + 2 * n;
     double* du2 = wk + 3 * n;
     int* piv = (int*)(wk + 4 * n);
-    for (int i = 0; i < n; ++i) {
-      dm[i] = a[i] - lam;
-      du[i] = i < n - 1 ? b[i] : 0.0;
-      dl[i] = i < n - 1 ? b[i] : 0.0;
-      du2[i] = 0.0;
-      y[i] = 1.0;
-    }
     const double tiny = 1e-300 + 1e-15 * scale;
+    double dm_c = a[0] - lam, du_c = b[0];
     for (int i = 0; i < n - 1; ++i) {
-      if (fabs(dm[i]) >= fabs(dl[i])) {
+      const double dl_i = b[i];
+      const double a_nx = a[i + 1] - lam;
+      const double du_nx = i + 1 < n - 1 ? b[i + 1] : 0.0;
+      double f;
+      if (fabs(dm_c) >= fabs(dl_i)) {
+        if (dm_c == 0.0) dm_c = tiny;
+        f = dl_i / dm_c;
         piv[i] = 0;
-        if (dm[i] == 0.0) dm[i] = tiny;
-        const double f = dl[i] / dm[i];
-        dl[i] = f;
-        dm[i + 1] -= f * du[i];
+        rdm[i] = 1.0 / dm_c;
+        du[i] = du_c;
+        du2[i] = 0.0;
+        dm_c = a_nx - f * du_c;
+        du_c = du_nx;
       } else {
+        f = dm_c / dl_i;
         piv[i] = 1;
-        const double f = dm[i] / dl[i];
-        dm[i] = dl[i];
-        dl[i] = f;
-        const double t = du[i];
-        du[i] = dm[i + 1];
-        dm[i + 1] = t - f * dm[i + 1];
-        if (i < n - 2) {
-          du2[i] = du[i + 1];
-          du[i + 1] = -f * du[i + 1];
-        }
+        rdm[i] = 1.0 / dl_i;
+        du[i] = a_nx;
+        du2[i] = du_nx;
+        dm_c = du_c - f * a_nx;
+        du_c = -f * du_nx;
       }
+      dl[i] = f;
     }
-    if (dm[n - 1] == 0.0) dm[n - 1] = tiny;
-    for (int i = 0; i < n; ++i) dm[i] = 1.0 / dm[i];  // solves multiply by the reciprocals
+    if (dm_c == 0.0) dm_c = tiny;
+    rdm[n - 1] = 1.0 / dm_c;
+    for (int i = 0; i < n; ++i) y[i] = 1.0;
     for (int sweep = 0; sweep < 3; ++sweep) {
+      // L solve with the row interchanges
+      double cur = y[0];
       for (int i = 0; i < n - 1; ++i) {
+        const double nx = y[i + 1];
         if (piv[i] == 0) {
-          y[i + 1] -= dl[i] * y[i];
+          y[i] = cur;
+          cur = nx - dl[i] * cur;
         } else {
-          const double t = y[i];
-          y[i] = y[i + 1];
-          y[i + 1] = t - dl[i] * y[i + 1];
+          y[i] = nx;
+          cur = cur - dl[i] * nx;
         }
       }
-      y[n - 1] *= dm[n - 1];
-      y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) * dm[n - 2];
-      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) * dm[i];
+      // U solve
+      double y2 = cur * rdm[n - 1];
+      y[n - 1] = y2;
+      double y1 = (y[n - 2] - du[n - 2] * y2) * rdm[n - 2];
+      y[n - 2] = y1;
+      for (int i = n - 3; i >= 0; --i) {
+        const double yi = (y[i] - du[i] * y1 - du2[i] * y2) * rdm[i];
+        y[i] = yi;
+        y2 = y1;
+        y1 = yi;
+      }
       double nrm = 0.0;
       for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
       const double inv = 1.0 / sqrt(nrm);
@@ -494,6 +530,52 @@ __device__ void mc_multidot(const double* V, int n, int j, const double* s_w, do
   __syncthreads();
 }
 
+// The end of the step, shared by both eigen kernels: the new scalars from
+// eta (thread i < m holds eta_i, c_i, b_i and (H_II eta)_i), c_hat_I += eta/s',
+// the damped step length and the stopping test.
+__device__ void mc_step_finish(const EigArgs& A, int m, double s, dd mu, dd al, double gamma,
+                               double eta_i, double ci, double bi, double heta_i, int iters,
+                               double* s_red) {
+  Ctl* ctl = A.ctl;
+  const int tid = threadIdx.x;
+  const dd ec = wg_sum_dd(two_prod(eta_i, ci), s_red);
+  const dd eb = wg_sum_dd(two_prod(eta_i, bi), s_red);
+  const dd ee = wg_sum_dd(two_prod(eta_i, eta_i), s_red);
+  const dd ehe = wg_sum_dd(two_prod(eta_i, heta_i), s_red);
+  // mu' = gamma^2 mu + 2 gamma eta.c_I + eta.eta ;
+  // alpha' = gamma^2 alpha + 2 gamma eta.b_I + eta.H_II.eta   (Alg. 2)
+  const dd g2 = two_prod(gamma, gamma);
+  const dd mu_n = dd_add(dd_add(dd_mul(g2, mu), dd_mul_d(ec, 2.0 * gamma)), ee);
+  const dd al_n = dd_add(dd_add(dd_mul(g2, al), dd_mul_d(eb, 2.0 * gamma)), ehe);
+  const double s_new = gamma * s;
+  if (tid < m) {
+    A.eta_out[tid] = eta_i;
+    Slot* sl = A.Tw + A.sel_slot[tid];
+    sl->c = sl->c + eta_i / s_new;  // c_hat_I += eta / s'
+  }
+  if (tid == 0) {
+    ctl->mu_hi = mu_n.hi;
+    ctl->mu_lo = mu_n.lo;
+    ctl->al_hi = al_n.hi;
+    ctl->al_lo = al_n.lo;
+    const double E = dd_val(al_n) / dd_val(mu_n);
+    ctl->energy = E;
+    const double step_norm = sqrt(fmax(0.0, dd_val(ee)));
+    ctl->d = (ctl->steps == 0) ? step_norm : A.theta * ctl->d + (1.0 - A.theta) * step_norm;
+    if (A.tr_E) A.tr_E[ctl->steps] = E;
+    ctl->steps += 1;
+    ctl->steps_this_call += 1;
+    if (ctl->d < A.dx_tol) ctl->stopped = 1;
+    A.st->scale = s_new;
+    A.st->inv_scale = 1.0 / s_new;
+    A.st->gamma = gamma;
+    A.st->lanczos_iters = iters;
+    // doubles reach 2^1023: fold the scale into the table long before that
+    A.st->rescale = fabs(log2(fabs(s_new))) > 400.0 ? 1 : 0;
+    if (!(fabs(s_new) > 1e-250) || !(E == E)) ctl->error |= kErrNumeric;
+  }
+}
+
 // one workgroup of 1024 threads
 __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   __shared__ double s_c[1024], s_b[1024], s_a0[1024], s_x[1025], s_w[1025];
@@ -528,7 +610,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
   const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
   const double nu2v = dd_val(nu2);
-  const int off = nu2v > 1e-24 * dd_val(mu) ? 1 : 0;
+  const int off = nu2v > kNu2Floor * dd_val(mu) ? 1 : 0;
   const double nu = off ? sqrt(nu2v) : 0.0;
   const double a00 = off ? dd_val(num) / nu2v : 0.0;
   if (tid < m) s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
@@ -633,42 +715,267 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, m, s_part);
   __syncthreads();
   const double heta_i = tid < m ? s_w[tid] : 0.0;
-  const dd ec = wg_sum_dd(two_prod(eta_i, ci), s_red);
-  const dd eb = wg_sum_dd(two_prod(eta_i, bi), s_red);
-  const dd ee = wg_sum_dd(two_prod(eta_i, eta_i), s_red);
-  const dd ehe = wg_sum_dd(two_prod(eta_i, heta_i), s_red);
-  // mu' = gamma^2 mu + 2 gamma eta.c_I + eta.eta ;
-  // alpha' = gamma^2 alpha + 2 gamma eta.b_I + eta.H_II.eta   (Alg. 2)
-  const dd g2 = two_prod(gamma, gamma);
-  const dd mu_n = dd_add(dd_add(dd_mul(g2, mu), dd_mul_d(ec, 2.0 * gamma)), ee);
-  const dd al_n = dd_add(dd_add(dd_mul(g2, al), dd_mul_d(eb, 2.0 * gamma)), ehe);
-  const double s_new = gamma * s;
+  mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
+}
+
+constexpr int kEigSmall = 64;  // m up to this: the eigen step runs from shared memory
+
+// y = A x with H_II in shared memory, for m <= 64: lane i forms row off + i,
+// the wave's sum forms row 0.
+__device__ __forceinline__ void mc_matvec_wave(const double* sH, int m, int off, double a00,
+                                               const double* s_a0, const double* x, double* y) {
+  const int lane = threadIdx.x;
+  if (lane < m) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 3 < m; j += 4) {
+      a0 += sH[j * m + lane] * x[off + j];
+      a1 += sH[(j + 1) * m + lane] * x[off + j + 1];
+      a2 += sH[(j + 2) * m + lane] * x[off + j + 2];
+      a3 += sH[(j + 3) * m + lane] * x[off + j + 3];
+    }
+    for (; j < m; ++j) a0 += sH[j * m + lane] * x[off + j];
+    double sum = (a0 + a1) + (a2 + a3);
+    if (off) sum += s_a0[lane] * x[0];
+    y[off + lane] = sum;
+  }
+  if (off) {
+    double p = lane < m ? s_a0[lane] * x[1 + lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double q = __shfl_xor(p, o);
+      p = (lane & o) ? (q + p) : (p + q);
+    }
+    if (lane == 0) y[0] = a00 * x[0] + p;
+  }
+}
+
+// value of v held by lane l (l wave-uniform), as a scalar broadcast
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// DPP lane move of a double (both halves), lanes outside ROWS read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a fully active wave in a fixed order, returned to
+// every lane: within quads (quad_perm 1,0,3,2 and 2,3,0,1), across the two
+// halves of each row of 16 (half mirror, mirror), then row 0 into row 1 and
+// row 2 into row 3 (broadcast of lane 15), rows 0-1 into rows 2-3
+// (broadcast of lane 31); lane 63 then holds the total.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_move<0xB1, 0xF>(v);
+  v += dpp_move<0x4E, 0xF>(v);
+  v += dpp_move<0x141, 0xF>(v);
+  v += dpp_move<0x140, 0xF>(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  return lane_value(v, 63);
+}
+
+constexpr int kLdA = kEigSmall + 1;  // leading dimension of the reduced matrix in shared memory
+constexpr int kEigWaves = 8;        // waves of the small eigen kernel
+
+// Householder reduction of the symmetric n x n matrix sA (column-major,
+// leading dimension kLdA, n <= 65) to tridiagonal form T = Q^T A Q by the W
+// waves of the workgroup.  Step i reflects rows/columns i+1..n-1: lane l of
+// every wave owns row i+1+l of the trailing block (at most 64 rows) and every
+// wave forms the same reflector v; wave w takes the columns w, w+W, ... of the
+// product p = tau A' v (partial sums combined in shared memory, fixed order)
+// and of the symmetric rank-2 update A' -= v q^T + q v^T, with the other
+// lanes' values of v and q broadcast through scalar registers.  Reflector i
+// goes to sR[64 i ..], its factor to tau[i]; d[0..n) and e[0..n-1) receive T.
+template <int W>
+__device__ void tridiagonalize_wg(double* __restrict__ sA, int n, double* __restrict__ sR,
+                                  double* __restrict__ d, double* __restrict__ e,
+                                  double* __restrict__ tau, double* __restrict__ s_p) {
+  constexpr int U = 64 / W;  // columns per wave at most
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = 0; i + 2 < n; ++i) {
+    const int t = n - 1 - i;  // trailing order
+    const bool act = lane < t;
+    const int r = act ? i + 1 + lane : n - 1;  // rows past the end read a valid row
+    const double* col = sA + i * kLdA;
+    const double x = act ? col[r] : 0.0;
+    // identical in every wave (same values, same order): the branch below is
+    // uniform over the workgroup
+    const double s2 = wave_sum_dpp(x * x);
+    const double x0 = lane_value(x, 0);
+    const double sigma = s2 - x0 * x0;
+    double v = 0.0, tf = 0.0, alpha = x0;
+    if (sigma > 0.0) {
+      alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
+      v = lane == 0 ? x0 - alpha : x;
+      tf = 1.0 / (s2 - x0 * alpha);  // 2 / (v.v)
+      double pp = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = w + u * W;
+        const int cc = min(c, t - 1);
+        const double vc = c < t ? lane_value(v, cc) : 0.0;
+        pp += sA[(i + 1 + cc) * kLdA + r] * vc;
+      }
+      s_p[w * 64 + lane] = act ? pp : 0.0;
+      __syncthreads();
+      double p = 0.0;
+#pragma unroll
+      for (int q = 0; q < W; ++q) p += s_p[q * 64 + lane];
+      p *= tf;
+      const double K = 0.5 * tf * wave_sum_dpp(v * p);
+      const double q = p - K * v;
+      double av[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) av[u] = sA[(i + 1 + min(w + u * W, t - 1)) * kLdA + r];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = w + u * W;
+        if (c < t) {
+          const double vc = lane_value(v, c), qc = lane_value(q, c);
+          if (act) sA[(i + 1 + c) * kLdA + r] = av[u] - v * qc - q * vc;
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      d[i] = col[i];
+      e[i] = alpha;
+      tau[i] = tf;
+    }
+    if (w == 0) sR[i * 64 + lane] = v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (n >= 2) {
+      d[n - 2] = sA[(n - 2) * kLdA + n - 2];
+      e[n - 2] = sA[(n - 2) * kLdA + n - 1];
+    }
+    d[n - 1] = sA[(n - 1) * kLdA + n - 1];
+  }
+  __syncthreads();
+}
+
+// The eigen step for m <= 64 (same mathematics as k_mc_eig) in one
+// workgroup of kEigWaves waves.  H_II, the reduced matrix and the reflectors
+// sit in shared memory; the lowest eigenpair comes from a Householder
+// tridiagonalisation, the tridiagonal solver (multisection + inverse
+// iteration) and the back transformation, so it is exact to rounding with no
+// convergence test.
+__global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
+  constexpr int NV = kEigSmall + 1;
+  __shared__ double sH[kEigSmall * kEigSmall];
+  __shared__ double sA[NV * kLdA];
+  __shared__ double sR[(NV - 2) * 64];
+  __shared__ double s_p[kEigWaves * 64];
+  __shared__ double s_c[NV], s_a0[NV], s_x[NV], s_w[NV];
+  __shared__ double s_red[kEigWaves];
+  __shared__ double s_d[NV], s_e[NV], s_tau[NV], s_y[NV];
+  __shared__ double s_wk[5 * NV];
+  __shared__ double s_lam;
+  Ctl* ctl = A.ctl;
+  if (A.st->skip) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int m = (int)min(A.st->n_sel, (unsigned long long)min(A.k, kEigSmall));
+  const double s = A.st->scale;
+  const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
+  double ci = 0.0, bi = 0.0;
   if (tid < m) {
-    A.eta_out[tid] = eta_i;
-    Slot* sl = A.Tw + A.sel_slot[tid];
-    sl->c = sl->c + eta_i / s_new;  // c_hat_I += eta / s'
+    const Slot sl = A.T[A.sel_slot[tid]];
+    ci = s * sl.c;
+    bi = s * sl.b;
+    s_c[tid] = ci;
   }
-  if (tid == 0) {
-    ctl->mu_hi = mu_n.hi;
-    ctl->mu_lo = mu_n.lo;
-    ctl->al_hi = al_n.hi;
-    ctl->al_lo = al_n.lo;
-    const double E = dd_val(al_n) / dd_val(mu_n);
-    ctl->energy = E;
-    const double step_norm = sqrt(fmax(0.0, dd_val(ee)));
-    ctl->d = (ctl->steps == 0) ? step_norm : A.theta * ctl->d + (1.0 - A.theta) * step_norm;
-    if (A.tr_E) A.tr_E[ctl->steps] = E;
-    ctl->steps += 1;
-    ctl->steps_this_call += 1;
-    if (ctl->d < A.dx_tol) ctl->stopped = 1;
-    A.st->scale = s_new;
-    A.st->inv_scale = 1.0 / s_new;
-    A.st->gamma = gamma;
-    A.st->lanczos_iters = iters;
-    // doubles reach 2^1023: fold the scale into the table long before that
-    A.st->rescale = fabs(log2(fabs(s_new))) > 400.0 ? 1 : 0;
-    if (!(fabs(s_new) > 1e-250) || !(E == E)) ctl->error |= kErrNumeric;
+  {
+    // H_II into shared memory, every thread's loads in flight together
+    constexpr int kPer = kEigSmall * kEigSmall / (64 * kEigWaves);
+    const int mm = m * m;
+    double hv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = tid + u * 64 * kEigWaves;
+      hv[u] = q < mm ? A.hii[q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = tid + u * 64 * kEigWaves;
+      if (q < mm) sH[q] = hv[u];
+    }
   }
+  __syncthreads();
+  // hc = H_II c_I (rows by wave 0)
+  mc_matvec_wave(sH, m, 0, 0.0, s_a0, s_c, s_w);
+  __syncthreads();
+  const double hc_i = tid < m ? s_w[tid] : 0.0;
+  const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
+  const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
+  const dd chc = wg_sum_dd(two_prod(ci, hc_i), s_red);
+  const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
+  const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
+  const double nu2v = dd_val(nu2);
+  const int off = nu2v > kNu2Floor * dd_val(mu) ? 1 : 0;
+  const double nu = off ? sqrt(nu2v) : 0.0;
+  const double a00 = off ? dd_val(num) / nu2v : 0.0;
+  const int n = m + off;
+  if (n == 0) {
+    if (tid == 0) ctl->stopped = 1;
+    return;
+  }
+  // the reduced matrix [[a00, a0^T], [a0, H_II]] (or H_II alone): wave w
+  // fills columns w, w + W, ...; row 64 (n = 65) by lane 0
+  if (tid < m) s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
+  __syncthreads();
+  for (int c = tid >> 6; c < n; c += kEigWaves) {
+    const int cj = c - off;
+    for (int r = lane; r < n; r += 64) {
+      const int ri = r - off;
+      sA[c * kLdA + r] = ri < 0 ? (cj < 0 ? a00 : s_a0[cj]) : (cj < 0 ? s_a0[ri] : sH[cj * m + ri]);
+    }
+  }
+  __syncthreads();
+  tridiagonalize_wg<kEigWaves>(sA, n, sR, s_d, s_e, s_tau, s_p);
+  if (tid < 64) {
+    const double lam = tri_lowest_wave(s_d, s_e, n, s_y, s_wk);
+    // x = Q y, applying H_(n-3) first; lane l holds row l, every lane also
+    // carries row 64 (present when n = 65)
+    double xl = lane < n ? s_y[lane] : 0.0;
+    double x64 = n > 64 ? s_y[64] : 0.0;
+    for (int i = n - 3; i >= 0; --i) {
+      const bool act = lane >= i + 1 && lane < n;
+      const double v = act ? sR[i * 64 + lane - i - 1] : 0.0;
+      const double v64 = n > 64 ? sR[i * 64 + 63 - i] : 0.0;
+      const double f = s_tau[i] * (wave_sum_dpp(v * xl) + v64 * x64);
+      xl -= f * v;
+      x64 -= f * v64;
+    }
+    // z = sqrt(-lambda) x
+    const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
+    if (lane < n) s_x[lane] = zscale * xl;
+    if (lane == 0) {
+      if (n > 64) s_x[64] = zscale * x64;
+      s_lam = lam;
+    }
+  }
+  __syncthreads();
+  double zc_part = 0.0;
+  if (!off && tid < m) zc_part = s_x[tid] * s_c[tid];
+  const double zc = wg_sum(zc_part, s_red);
+  const double sgn = off ? (s_x[0] < 0.0 ? -1.0 : 1.0) : (zc < 0.0 ? -1.0 : 1.0);
+  const double gamma = off ? sgn * s_x[0] / nu : 1.0;
+  double eta_i = 0.0;
+  if (tid < m) eta_i = sgn * s_x[off + tid] - gamma * ci;
+  __syncthreads();
+  if (tid < m) s_x[tid] = eta_i;
+  __syncthreads();
+  mc_matvec_wave(sH, m, 0, 0.0, s_a0, s_x, s_w);
+  __syncthreads();
+  const double heta_i = tid < m ? s_w[tid] : 0.0;
+  mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, n, s_red);
 }
 
 // b_hat += H_{:,I} eta / s' with the compression rule; recalculation sums;

@@ -88,3 +88,22 @@ def test_requests_larger_than_the_space(api):
     ka, kb, c, b = api.cdfci_export(ctx, top_n=10 ** 9)
     assert len(ka) == np.count_nonzero(api.cdfci_export(ctx)[2])
     ctx.close()
+
+
+@pytest.mark.parametrize("k", [1024, 64, 36])
+def test_selection_covering_the_support(api, k):
+    """Once the chosen set holds every nonzero c_i, nu = ||c - E_I c_I|| is
+    zero and the c~ column must be dropped (gamma = 1); nu^2 formed as
+    mu - c_I.c_I is then pure rounding.  From the second step on the chosen
+    set covers the 36-determinant space, so each step is the exact
+    eigenproblem.  Repeated on fresh contexts because the rounding, and hence
+    a wrongly kept c~ column, varies with the order of the device's sums."""
+    N, na, nb = 4, 2, 2
+    h, eri = synth_inputs.ab_initio(N, 12, 17)
+    E0 = ocd.ground_energy(h, eri, na, nb)
+    for rep in range(8):
+        ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 10)
+        E, st = api.cdfci_step_energies(ctx, k, 4)
+        assert np.all(np.abs(E[1:] - E0) < 1e-10), (k, rep, list(E))
+        assert abs(api.cdfci_energy(ctx, exact=1) - E0) < 1e-10
+        ctx.close()

@@ -1515,10 +1515,9 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   if (trE) HIP_TRY(hipMalloc(&dE, (size_t)(before.steps + nsteps + 1) * sizeof(double)));
   hipStream_t s = c->stream;
   const Ham H = ham_of(c);
-  const int hist_blocks = 1024;
   const int chunks = (int)((c->n_col + kPage - 1) / kPage);
   const uint64_t nwords = c->nslots / 32 + 1;
-  EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, k,
+  EigArgs ea{c->bitmap, nwords, c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, k,
              c->opts.dx_damping, c->opts.dx_threshold, dE};
   ScatterArgs sa{H,        c->T,      c->mask,   c->sel_a, c->sel_b, c->eta,  c->mst,
                  c->ctl,   c->recalc, c->bitmap, c->cand,  c->cnt,   c->n_col, c->opts.z_threshold,
@@ -1528,26 +1527,23 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   HIP_TRY(hipEventRecord(c->ev0, s));
   for (int64_t step = 0; step < nsteps; ++step) {
     k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
-    for (int pass = 0; pass < kRadixPasses; ++pass) {
-      k_mc_hist<<<hist_blocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist,
-                                            pass, 0);
-      k_mc_scan<<<1, 256, 0, s>>>(c->hist, c->mst, c->cnt, k, pass);
-    }
-    k_mc_gather<<<hist_blocks, 256, 0, s>>>(c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties);
-    k_mc_ties<<<1, 256, 0, s>>>(c->T, c->mst, c->sel_slot, c->sel_a, c->sel_b, c->ties, k);
-    k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, nwords, c->mst);
+    for (int pass = 0; pass < kRadixPasses; ++pass)
+      k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist, pass, 0, k);
+    k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties,
+                                                c->sel_a, c->sel_b, k);
     k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k);
+    // workgroup 0 solves the reduced problem; the others clear the bitmap
     if (k <= kEigSmall)
-      k_mc_eig_small<<<1, 64 * kEigWaves, 0, s>>>(ea);
+      k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
     else
-      k_mc_eig<<<1, 1024, 0, s>>>(ea);
+      k_mc_eig<<<kEigGrid, 1024, 0, s>>>(ea);
     k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
     k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);
     k_mc_rescale<<<256, 256, 0, s>>>(c->T, c->nslots, c->mst, 0);
-    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);
     if (((step + 1) & 63) == 0) HIP_TRY(hipGetLastError());
   }
+  k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);  // inside the loop k_mc_begin does this
   HIP_TRY(hipEventRecord(c->ev1, s));
   HIP_TRY(hipGetLastError());
   Ctl h;

@@ -35,7 +35,8 @@ struct McState {
   int lanczos_iters;
   int rescale;
   int skip;  // this step does nothing (an error is pending or the run stopped)
-  int pad;
+  unsigned arrive;                   // workgroups done with the current selection kernel
+  unsigned long long n_total;        // candidates of the coming selection
 };
 
 constexpr int kPage = 256;
@@ -44,6 +45,7 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 6;  // digits at bits 53, 42, 31, 20, 9 (11 wide) and 0 (9 wide)
 constexpr int kMaxTies = 4096;
 constexpr int kLanczosMax = 64;
+constexpr int kSelBlocks = 1024;  // workgroups of the selection launches
 // nu^2 = ||c - E_I c_I||^2 is formed as mu - c_I.c_I.  mu is carried from
 // step to step while the stored c is rounded at every update, so the two
 // drift apart by a few ulps of mu per step; below this fraction of mu nu^2
@@ -67,9 +69,20 @@ __device__ __forceinline__ unsigned long long c_key(const Slot& s) {
   return (unsigned long long)__double_as_longlong(fabs(s.c));
 }
 
-// start of a step: skip it if an error is pending or the stopping rule fired
+// start of a step: finish the previous step's scale fold (its k_mc_rescale
+// has completed), reset the selection's counters, then skip the step if an
+// error is pending or the stopping rule fired
 __global__ void k_mc_begin(McState* st, const Ctl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->skip = (ctl->error || ctl->stopped) ? 1 : 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (st->rescale) {
+      st->scale = 1.0;
+      st->inv_scale = 1.0;
+      st->rescale = 0;
+    }
+    st->arrive = 0;
+    st->n_total = 0;
+    st->skip = (ctl->error || ctl->stopped) ? 1 : 0;
+  }
 }
 
 // all occupied slots become candidates (entering the multicoordinate mode):
@@ -270,6 +283,227 @@ __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwo
   }
 }
 
+// ---------------------------------------------------------------- selection with last-workgroup scans
+
+// Radix-select state as kept by McState between the selection kernels.
+struct SelState {
+  unsigned long long prefix, pmask, n_above;
+  long long need;
+  int all, done;
+};
+
+// True in the one workgroup that finishes a launch last.  Everything the
+// workgroups share is written with agent-scope atomics, which are performed
+// at the coherence point, so a workgroup only has to wait for its own memory
+// operations to complete before it arrives (no cache write-back: a fence at
+// agent scope would write back the XCD's whole L2), and the last one reads
+// with agent-scope loads.
+__device__ bool last_workgroup(unsigned* arrive) {
+  __shared__ int s_last;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  return s_last != 0;
+}
+
+// The last workgroup of a histogram pass (256 threads): choose the radix
+// digit of the bucket holding the k-th largest key from the global
+// histogram (read with agent-scope loads), advance the state in McState, and
+// clear the histogram and the arrival count for the next pass.  Suffix counts
+// come from a block scan (per-wave shuffles, then the wave totals), so no
+// thread walks more than its own eight bins.
+__device__ void mc_scan_last(unsigned* hist, McState* st, int k, int pass) {
+  __shared__ SelState S;
+  __shared__ unsigned long long s_wt[4];
+  __shared__ int s_d;
+  __shared__ unsigned long long s_above;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    if (pass == 0) {
+      const unsigned long long total =
+          __hip_atomic_load(&st->n_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      S.prefix = 0;
+      S.pmask = 0;
+      S.n_above = 0;
+      S.done = 0;
+      S.all = (total <= (unsigned long long)k) ? 1 : 0;
+      S.need = k;
+    } else {
+      S.prefix = st->prefix;
+      S.pmask = st->pmask;
+      S.n_above = st->n_above;
+      S.need = st->need;
+      S.all = st->all;
+      S.done = st->done;
+    }
+  }
+  __syncthreads();
+  if (!(S.all || S.done)) {
+    const int sh = radix_shift(pass);
+    const int nb = (int)radix_digit_mask(pass) + 1;
+    const int per = nb / 256;  // 8 (11-bit digits) or 2 (the last, 9-bit digit)
+    const int lo = tid * per;
+    unsigned hv[8];
+    unsigned long long run = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hv[u] = u < per ? __hip_atomic_load(&hist[lo + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      run += hv[u];
+    }
+    // inclusive suffix over the wave's lanes, then over the waves
+    unsigned long long x = run;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_down(x, o);
+      if (lane + o < 64) x += y;
+    }
+    if (lane == 0) s_wt[w] = x;
+    if (tid == 0) s_d = -1;
+    __syncthreads();
+    unsigned long long acc = x - run;  // keys in bins above this thread's, within the wave
+    for (int q = w + 1; q < 4; ++q) acc += s_wt[q];
+    const long long need = S.need;
+    unsigned hd_mine = 0;
+    for (int u = per - 1; u >= 0; --u) {
+      const long long above = (long long)acc;
+      if (above < need && above + (long long)hv[u] >= need) {
+        s_d = lo + u;
+        s_above = acc;
+        hd_mine = hv[u];
+      }
+      acc += hv[u];
+    }
+    __syncthreads();
+    if (s_d >= 0 && tid == s_d / per) {  // the thread that owns the chosen bin
+      const long long above = (long long)s_above;
+      S.n_above += (unsigned long long)above;
+      S.need = need - above;
+      S.prefix |= (unsigned long long)s_d << sh;
+      S.pmask |= radix_digit_mask(pass) << sh;
+      if ((long long)hd_mine == need - above) S.done = 1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {  // read by the following launches
+    st->prefix = S.prefix;
+    st->pmask = S.pmask;
+    st->n_above = S.n_above;
+    st->need = S.need;
+    st->all = S.all;
+    st->done = S.done;
+    st->arrive = 0;
+  }
+  for (int i = tid; i < kRadixBins; i += blockDim.x) hist[i] = 0u;
+}
+
+// One radix-select pass over the step's candidates; pass 0 also computes the
+// keys (|g|, or |c| when by_c is set) and counts the candidates.  The last
+// workgroup to finish chooses the digit.
+__global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned* cand, const unsigned* cnt,
+                                                  unsigned long long* gkey, const Ctl* ctl, McState* st,
+                                                  unsigned* hist, int pass, int by_c, int k) {
+  __shared__ unsigned h[kRadixBins];
+  __shared__ unsigned s_cnt;
+  if (st->skip) return;
+  if (pass > 0 && (st->all || st->done)) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
+  if (tid == 0) s_cnt = 0u;
+  __syncthreads();
+  const unsigned long long n = st->n_pages * kPage;
+  const double mu = ctl->mu_hi + ctl->mu_lo;
+  const int sh = radix_shift(pass);
+  const unsigned long long dm = radix_digit_mask(pass);
+  const unsigned long long P = st->prefix, M = st->pmask;
+  unsigned mine = 0;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + tid; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
+    unsigned long long key;
+    if (pass == 0) {
+      key = by_c ? c_key(T[cand[i]]) : g_key(T[cand[i]], mu);
+      gkey[i] = key;
+      ++mine;
+    } else {
+      key = gkey[i];
+      if ((key & M) != P) continue;
+    }
+    atomicAdd(&h[(key >> sh) & dm], 1u);
+  }
+  if (pass == 0 && mine) atomicAdd(&s_cnt, mine);
+  __syncthreads();
+  for (int i = tid; i < kRadixBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+  if (pass == 0 && tid == 0 && s_cnt) atomicAdd(&st->n_total, (unsigned long long)s_cnt);
+  if (last_workgroup(&st->arrive)) mc_scan_last(hist, st, k, pass);
+}
+
+// Gather: chosen candidates -> sel_slot, keys equal to the threshold ->
+// ties; the last workgroup resolves the ties by key order and fills the keys
+// of the chosen set.  Slots shared between workgroups go through
+// agent-scope atomics (the XCDs' L2 caches are not coherent).
+__global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, const unsigned* cand,
+                                                        const unsigned* cnt,
+                                                        const unsigned long long* gkey, McState* st,
+                                                        int64_t* sel_slot, unsigned* ties, uint64_t* sel_a,
+                                                        uint64_t* sel_b, int k) {
+  if (st->skip) return;
+  const int tid = threadIdx.x;
+  const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long P = st->prefix, M = st->pmask;
+  const int all = st->all, done = st->done;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + tid; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
+    const unsigned long long km = gkey[i] & M;
+    const bool take = all || km > P || (done && km == P);
+    if (take) {
+      const unsigned long long q = atomicAdd(&st->n_sel, 1ull);
+      if (q < (unsigned long long)k)
+        __hip_atomic_store(&sel_slot[q], (int64_t)cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (km == P) {
+      const unsigned long long t = atomicAdd(&st->n_tie, 1ull);
+      if (t < kMaxTies) __hip_atomic_store(&ties[t], cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (!last_workgroup(&st->arrive)) return;
+  __shared__ unsigned long long s_base, s_nsel;
+  if (tid == 0) s_nsel = __hip_atomic_load(&st->n_sel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(all || done)) {
+    const long long need = st->need;
+    const unsigned long long ntie = __hip_atomic_load(&st->n_tie, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int nt = (int)min(ntie, (unsigned long long)kMaxTies);
+    if (tid == 0) s_base = s_nsel;
+    __syncthreads();
+    for (int i = tid; i < nt; i += blockDim.x) {
+      const unsigned ti = __hip_atomic_load(&ties[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const Slot si = T[ti];
+      int rank = 0;
+      for (int j = 0; j < nt; ++j) {
+        const Slot sj = T[__hip_atomic_load(&ties[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)];
+        if (key_less(sj.ka, sj.kb, si.ka, si.kb)) ++rank;
+      }
+      if (rank < need && s_base + rank < (unsigned long long)k)
+        __hip_atomic_store(&sel_slot[s_base + rank], (int64_t)ti, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_nsel = s_base + (unsigned long long)min((long long)nt, need);
+      st->n_sel = s_nsel;
+    }
+  }
+  __syncthreads();
+  const int m = (int)min(s_nsel, (unsigned long long)k);
+  for (int i = tid; i < m; i += blockDim.x) {
+    const int64_t sl = __hip_atomic_load(&sel_slot[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const Slot v = T[sl];
+    sel_a[i] = v.ka;
+    sel_b[i] = v.kb;
+  }
+  if (tid == 0) st->arrive = 0;
+}
+
 // H_II: block y builds column y (ket = chosen determinant y)
 __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, const uint64_t* sel_b,
                                                 const McState* st, double* hii, int k) {
@@ -441,6 +675,8 @@ __device__ double tri_lowest_wave(const double* __restrict__ a, const double* __
 }
 
 struct EigArgs {
+  unsigned* bitmap;  // cleared by the launch's workgroups 1.. for the coming scatter
+  uint64_t nwords;
   const Slot* T;
   Slot* Tw;
   const int64_t* sel_slot;
@@ -530,6 +766,24 @@ __device__ void mc_multidot(const double* V, int n, int j, const double* s_w, do
   __syncthreads();
 }
 
+// Workgroups 1.. of an eigen launch: clear the candidate bitmap for the coming
+// scatter (16-byte stores) and reset the gather counters, while workgroup 0
+// solves the reduced problem on its own compute unit.
+__device__ void mc_clear_bitmap(const EigArgs& A) {
+  const uint64_t part = blockIdx.x - 1, nparts = gridDim.x - 1;
+  const uint64_t nvec = A.nwords / 4;
+  uint4* v = reinterpret_cast<uint4*>(A.bitmap);
+  for (uint64_t i = part * blockDim.x + threadIdx.x; i < nvec; i += nparts * blockDim.x)
+    v[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (part == 0) {
+    for (uint64_t i = nvec * 4 + threadIdx.x; i < A.nwords; i += blockDim.x) A.bitmap[i] = 0u;
+    if (threadIdx.x == 0) {
+      A.st->n_tie = 0;
+      A.st->n_dense = 0;
+    }
+  }
+}
+
 // The end of the step, shared by both eigen kernels: the new scalars from
 // eta (thread i < m holds eta_i, c_i, b_i and (H_II eta)_i), c_hat_I += eta/s',
 // the damped step length and the stopping test.
@@ -585,6 +839,10 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   __shared__ double s_y[kLanczosMax + 1], s_h[kLanczosMax + 1], s_h2[kLanczosMax + 1];
   __shared__ double s_wk[5 * (kLanczosMax + 1)];
   __shared__ double s_bc[4];
+  if (blockIdx.x > 0) {
+    mc_clear_bitmap(A);
+    return;
+  }
   Ctl* ctl = A.ctl;
   if (A.st->skip) return;
   const int tid = threadIdx.x;
@@ -719,6 +977,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
 }
 
 constexpr int kEigSmall = 64;  // m up to this: the eigen step runs from shared memory
+constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest clear)
 
 // y = A x with H_II in shared memory, for m <= 64: lane i forms row off + i,
 // the wave's sum forms row 0.
@@ -878,6 +1137,10 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
   __shared__ double s_d[NV], s_e[NV], s_tau[NV], s_y[NV];
   __shared__ double s_wk[5 * NV];
   __shared__ double s_lam;
+  if (blockIdx.x > 0) {
+    mc_clear_bitmap(A);
+    return;
+  }
   Ctl* ctl = A.ctl;
   if (A.st->skip) return;
   const int tid = threadIdx.x, lane = tid & 63;

@@ -568,6 +568,83 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ a, const d
   return cnt;
 }
 
+// Eigenvector of the symmetric tridiagonal (a, b) for the eigenvalue
+// estimate lam, by one thread: inverse iteration on (T - lam I), two sweeps
+// from the all-ones vector (lam is accurate to a few ulps, so one sweep
+// already converges; the second is a margin).  scale bounds |T|.
+__device__ void tri_inverse_iteration(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                      double lam, double scale, double* __restrict__ y,
+                                      double* __restrict__ wk) {
+  // inverse iteration on (T - lam I): Gaussian elimination with partial
+  // pivoting of a tridiagonal matrix (one extra superdiagonal of fill-in),
+  // the row being eliminated carried in registers.  The factors are
+  // stored as multipliers dl, reciprocal pivots rdm, superdiagonals du, du2.
+  double* dl = wk;
+  double* rdm = wk + n;
+  double* du = wk + 2 * n;
+  double* du2 = wk + 3 * n;
+  int* piv = (int*)(wk + 4 * n);
+  const double tiny = 1e-300 + 1e-15 * scale;
+  double dm_c = a[0] - lam, du_c = b[0];
+  for (int i = 0; i < n - 1; ++i) {
+    const double dl_i = b[i];
+    const double a_nx = a[i + 1] - lam;
+    const double du_nx = i + 1 < n - 1 ? b[i + 1] : 0.0;
+    double f;
+    if (fabs(dm_c) >= fabs(dl_i)) {
+      if (dm_c == 0.0) dm_c = tiny;
+      f = dl_i / dm_c;
+      piv[i] = 0;
+      rdm[i] = 1.0 / dm_c;
+      du[i] = du_c;
+      du2[i] = 0.0;
+      dm_c = a_nx - f * du_c;
+      du_c = du_nx;
+    } else {
+      f = dm_c / dl_i;
+      piv[i] = 1;
+      rdm[i] = 1.0 / dl_i;
+      du[i] = a_nx;
+      du2[i] = du_nx;
+      dm_c = du_c - f * a_nx;
+      du_c = -f * du_nx;
+    }
+    dl[i] = f;
+  }
+  if (dm_c == 0.0) dm_c = tiny;
+  rdm[n - 1] = 1.0 / dm_c;
+  for (int i = 0; i < n; ++i) y[i] = 1.0;
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    // L solve with the row interchanges
+    double cur = y[0];
+    for (int i = 0; i < n - 1; ++i) {
+      const double nx = y[i + 1];
+      if (piv[i] == 0) {
+        y[i] = cur;
+        cur = nx - dl[i] * cur;
+      } else {
+        y[i] = nx;
+        cur = cur - dl[i] * nx;
+      }
+    }
+    // U solve
+    double y2 = cur * rdm[n - 1];
+    y[n - 1] = y2;
+    double y1 = (y[n - 2] - du[n - 2] * y2) * rdm[n - 2];
+    y[n - 2] = y1;
+    for (int i = n - 3; i >= 0; --i) {
+      const double yi = (y[i] - du[i] * y1 - du2[i] * y2) * rdm[i];
+      y[i] = yi;
+      y2 = y1;
+      y1 = yi;
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+    const double inv = 1.0 / sqrt(nrm);
+    for (int i = 0; i < n; ++i) y[i] *= inv;
+  }
+}
+
 // Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)), called
 // by one full wave: 64-way multisection on the Sturm count (six bits per
 // round), then inverse iteration with partial pivoting by lane 0.  y and wk
@@ -601,76 +678,54 @@ __device__ double tri_lowest_wave(const double* __restrict__ a, const double* __
   }
   if (!want_y) return 0.5 * (lo + hi);
   const double lam = 0.5 * (lo + hi);
-  if (lane == 0) {
-    // inverse iteration on (T - lam I): Gaussian elimination with partial
-    // pivoting of a tridiagonal matrix (one extra superdiagonal of fill-in),
-    // the row being eliminated carried in registers.  The factors are
-    // stored as multipliers dl, reciprocal pivots rdm, superdiagonals du, du2.
-    double* dl = wk;
-    double* rdm = wk + n;
-    double* du = wk + 2 * n;
-    double* du2 = wk + 3 * n;
-    int* piv = (int*)(wk + 4 * n);
-    const double tiny = 1e-300 + 1e-15 * scale;
-    double dm_c = a[0] - lam, du_c = b[0];
-    for (int i = 0; i < n - 1; ++i) {
-      const double dl_i = b[i];
-      const double a_nx = a[i + 1] - lam;
-      const double du_nx = i + 1 < n - 1 ? b[i + 1] : 0.0;
-      double f;
-      if (fabs(dm_c) >= fabs(dl_i)) {
-        if (dm_c == 0.0) dm_c = tiny;
-        f = dl_i / dm_c;
-        piv[i] = 0;
-        rdm[i] = 1.0 / dm_c;
-        du[i] = du_c;
-        du2[i] = 0.0;
-        dm_c = a_nx - f * du_c;
-        du_c = du_nx;
-      } else {
-        f = dm_c / dl_i;
-        piv[i] = 1;
-        rdm[i] = 1.0 / dl_i;
-        du[i] = a_nx;
-        du2[i] = du_nx;
-        dm_c = du_c - f * a_nx;
-        du_c = -f * du_nx;
-      }
-      dl[i] = f;
-    }
-    if (dm_c == 0.0) dm_c = tiny;
-    rdm[n - 1] = 1.0 / dm_c;
-    for (int i = 0; i < n; ++i) y[i] = 1.0;
-    for (int sweep = 0; sweep < 3; ++sweep) {
-      // L solve with the row interchanges
-      double cur = y[0];
-      for (int i = 0; i < n - 1; ++i) {
-        const double nx = y[i + 1];
-        if (piv[i] == 0) {
-          y[i] = cur;
-          cur = nx - dl[i] * cur;
-        } else {
-          y[i] = nx;
-          cur = cur - dl[i] * nx;
-        }
-      }
-      // U solve
-      double y2 = cur * rdm[n - 1];
-      y[n - 1] = y2;
-      double y1 = (y[n - 2] - du[n - 2] * y2) * rdm[n - 2];
-      y[n - 2] = y1;
-      for (int i = n - 3; i >= 0; --i) {
-        const double yi = (y[i] - du[i] * y1 - du2[i] * y2) * rdm[i];
-        y[i] = yi;
-        y2 = y1;
-        y1 = yi;
-      }
-      double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
-      const double inv = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) y[i] *= inv;
-    }
+  if (lane == 0) tri_inverse_iteration(a, b, n, lam, scale, y, wk);
+  return lam;
+}
+
+// Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)) by the
+// whole workgroup: multisection with one point per thread (blockDim + 1
+// subintervals per round, the first point above the eigenvalue found from
+// the waves' ballots), then inverse iteration by thread 0.  Every thread
+// gets the eigenvalue; y (n doubles) is complete when it returns.
+__device__ double tri_lowest_wg(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                double* __restrict__ y, double* __restrict__ wk,
+                                unsigned long long* s_bal) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int npts = blockDim.x;
+  if (n == 1) {
+    if (tid == 0) y[0] = 1.0;
+    __syncthreads();
+    return a[0];
   }
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < n - 1 ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  const double scale = fmax(fabs(lo), fabs(hi));
+  const double inv_seg = 1.0 / (double)(npts + 1);
+  for (int round = 0; round < 16 && hi - lo > 2e-16 * scale; ++round) {
+    const double x = lo + (hi - lo) * ((double)(tid + 1) * inv_seg);
+    const bool below = sturm_count(a, b, n, x) >= 1;  // lowest eigenvalue < x
+    const unsigned long long bal = __ballot(below);
+    if (lane == 0) s_bal[w] = bal;
+    __syncthreads();
+    int f = npts;  // first point above the eigenvalue
+    for (int q = 0; q < nw; ++q)
+      if (s_bal[q]) {
+        f = q * 64 + __ffsll(s_bal[q]) - 1;
+        break;
+      }
+    __syncthreads();
+    const double nhi = f < npts ? lo + (hi - lo) * ((double)(f + 1) * inv_seg) : hi;
+    const double nlo = f > 0 ? lo + (hi - lo) * ((double)f * inv_seg) : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  const double lam = 0.5 * (lo + hi);
+  if (tid == 0) tri_inverse_iteration(a, b, n, lam, scale, y, wk);
+  __syncthreads();
   return lam;
 }
 
@@ -1136,7 +1191,7 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
   __shared__ double s_red[kEigWaves];
   __shared__ double s_d[NV], s_e[NV], s_tau[NV], s_y[NV];
   __shared__ double s_wk[5 * NV];
-  __shared__ double s_lam;
+  __shared__ unsigned long long s_bal[kEigWaves];
   if (blockIdx.x > 0) {
     mc_clear_bitmap(A);
     return;
@@ -1202,8 +1257,8 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
   }
   __syncthreads();
   tridiagonalize_wg<kEigWaves>(sA, n, sR, s_d, s_e, s_tau, s_p);
+  const double lam = tri_lowest_wg(s_d, s_e, n, s_y, s_wk, s_bal);
   if (tid < 64) {
-    const double lam = tri_lowest_wave(s_d, s_e, n, s_y, s_wk);
     // x = Q y, applying H_(n-3) first; lane l holds row l, every lane also
     // carries row 64 (present when n = 65)
     double xl = lane < n ? s_y[lane] : 0.0;
@@ -1219,10 +1274,7 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
     // z = sqrt(-lambda) x
     const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
     if (lane < n) s_x[lane] = zscale * xl;
-    if (lane == 0) {
-      if (n > 64) s_x[64] = zscale * x64;
-      s_lam = lam;
-    }
+    if (lane == 0 && n > 64) s_x[64] = zscale * x64;
   }
   __syncthreads();
   double zc_part = 0.0;

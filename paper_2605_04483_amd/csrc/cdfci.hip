@@ -1535,8 +1535,10 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     // workgroup 0 solves the reduced problem; the others clear the bitmap
     if (k <= kEigSmall)
       k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
+    else if (k <= 256)
+      k_mc_eig<256><<<kEigGrid, 1024, 0, s>>>(ea);
     else
-      k_mc_eig<<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_eig<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
     k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
     k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);

@@ -645,43 +645,6 @@ __device__ void tri_inverse_iteration(const double* __restrict__ a, const double
   }
 }
 
-// Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)), called
-// by one full wave: 64-way multisection on the Sturm count (six bits per
-// round), then inverse iteration with partial pivoting by lane 0.  y and wk
-// (5 n doubles) live in shared memory; the eigenvalue is returned to every
-// lane.  With want_y == 0 only the eigenvalue is formed.  No workgroup
-// barrier is used, so one wave may call it while the others wait.
-__device__ double tri_lowest_wave(const double* __restrict__ a, const double* __restrict__ b, int n,
-                                  double* __restrict__ y, double* __restrict__ wk, int want_y = 1) {
-  const int lane = threadIdx.x & 63;
-  if (n == 1) {
-    if (lane == 0) y[0] = 1.0;
-    return a[0];
-  }
-  double lo = a[0], hi = a[0];
-  for (int i = 0; i < n; ++i) {
-    double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < n - 1 ? fabs(b[i]) : 0.0);
-    lo = fmin(lo, a[i] - r);
-    hi = fmax(hi, a[i] + r);
-  }
-  const double scale = fmax(fabs(lo), fabs(hi));
-  for (int round = 0; round < 16 && hi - lo > 2e-16 * scale; ++round) {
-    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-    const bool below = sturm_count(a, b, n, x) >= 1;  // lowest eigenvalue < x
-    const unsigned long long bal = __ballot(below);
-    // first lane whose point lies above the eigenvalue
-    const int f = bal ? (__ffsll((unsigned long long)bal) - 1) : 64;
-    const double nhi = f < 64 ? lo + (hi - lo) * (double)(f + 1) / 65.0 : hi;
-    const double nlo = f > 0 ? lo + (hi - lo) * (double)f / 65.0 : lo;
-    lo = nlo;
-    hi = nhi;
-  }
-  if (!want_y) return 0.5 * (lo + hi);
-  const double lam = 0.5 * (lo + hi);
-  if (lane == 0) tri_inverse_iteration(a, b, n, lam, scale, y, wk);
-  return lam;
-}
-
 // Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)) by the
 // whole workgroup: multisection with one point per thread (blockDim + 1
 // subintervals per round, the first point above the eigenvalue found from
@@ -711,12 +674,17 @@ __device__ double tri_lowest_wg(const double* __restrict__ a, const double* __re
     const unsigned long long bal = __ballot(below);
     if (lane == 0) s_bal[w] = bal;
     __syncthreads();
-    int f = npts;  // first point above the eigenvalue
-    for (int q = 0; q < nw; ++q)
-      if (s_bal[q]) {
-        f = q * 64 + __ffsll(s_bal[q]) - 1;
-        break;
-      }
+    // first point above the eigenvalue: one read per lane, then the first
+    // wave with a set bit (dependent shared-memory reads cost ~60 cycles each)
+    const unsigned long long mine = lane < nw ? s_bal[lane] : 0ull;
+    const unsigned long long nz = __ballot(mine != 0ull);
+    int f = npts;
+    if (nz) {
+      const int q = __ffsll(nz) - 1;
+      const unsigned long long bq = ((unsigned long long)__builtin_amdgcn_readlane((int)(mine >> 32), q) << 32) |
+                                    (unsigned)__builtin_amdgcn_readlane((int)(unsigned)mine, q);
+      f = q * 64 + __ffsll(bq) - 1;
+    }
     __syncthreads();
     const double nhi = f < npts ? lo + (hi - lo) * ((double)(f + 1) * inv_seg) : hi;
     const double nlo = f > 0 ? lo + (hi - lo) * ((double)f * inv_seg) : lo;
@@ -767,6 +735,20 @@ __device__ void mc_matvec(const double* __restrict__ hii, int m, int off, double
       const int j0 = sl * span, j1 = min(m, j0 + span);
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int j = j0;
+      // eight loads in flight per lane; the four sums take the same terms in
+      // the same order as the four-wide loop below
+      for (; j + 7 < j1; j += 8) {
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = hii[(size_t)(j + u) * m + i];
+#pragma unroll
+        for (int u = 0; u < 8; u += 4) {
+          a0 += hv[u] * s_x[off + j + u];
+          a1 += hv[u + 1] * s_x[off + j + u + 1];
+          a2 += hv[u + 2] * s_x[off + j + u + 2];
+          a3 += hv[u + 3] * s_x[off + j + u + 3];
+        }
+      }
       for (; j + 3 < j1; j += 4) {
         a0 += hii[(size_t)j * m + i] * s_x[off + j];
         a1 += hii[(size_t)(j + 1) * m + i] * s_x[off + j + 1];
@@ -886,14 +868,19 @@ __device__ void mc_step_finish(const EigArgs& A, int m, double s, dd mu, dd al, 
 }
 
 // one workgroup of 1024 threads
+// KM = largest k the instance serves; for KM <= 256 the Lanczos basis
+// (64 x 257 doubles) lives in shared memory, otherwise in global memory.
+template <int KM>
 __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
-  __shared__ double s_c[1024], s_b[1024], s_a0[1024], s_x[1025], s_w[1025];
+  constexpr bool kVshared = KM <= 256;
+  __shared__ double s_c[KM], s_b[KM], s_a0[KM], s_x[KM + 1], s_w[KM + 1];
   __shared__ double s_part[1024];
   __shared__ double s_red[16];
   __shared__ double s_alpha[kLanczosMax + 1], s_beta[kLanczosMax + 1];
   __shared__ double s_y[kLanczosMax + 1], s_h[kLanczosMax + 1], s_h2[kLanczosMax + 1];
   __shared__ double s_wk[5 * (kLanczosMax + 1)];
-  __shared__ double s_bc[4];
+  __shared__ unsigned long long s_bal[16];
+  __shared__ double sV[kVshared ? kLanczosMax * (KM + 1) : 1];
   if (blockIdx.x > 0) {
     mc_clear_bitmap(A);
     return;
@@ -932,7 +919,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
     if (tid == 0) ctl->stopped = 1;
     return;
   }
-  double* V = A.lan;  // rows 0..kLanczosMax-1: Lanczos vectors
+  double* V = kVshared ? sV : A.lan;  // rows 0..kLanczosMax-1: Lanczos vectors
   // start vector: the current point [nu; c_I]
   {
     double part = 0.0;
@@ -984,27 +971,16 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
     if (!stop && j >= 5 && (j & 3) == 1) {
       // residual of the lowest Ritz pair: |beta_j y_j|; the eigenvalue error
       // is quadratic in it
-      if (tid < 64) {
-        const double l = tri_lowest_wave(s_alpha, s_beta, j + 1, s_y, s_wk);
-        if (tid == 0) {
-          s_bc[0] = l;
-          s_bc[1] = fabs(beta * s_y[j]);
-        }
-      }
-      __syncthreads();
-      if (s_bc[1] <= 1e-10 * fabs(s_bc[0])) stop = true;
+      const double l = tri_lowest_wg(s_alpha, s_beta, j + 1, s_y, s_wk, s_bal);
+      if (fabs(beta * s_y[j]) <= 1e-10 * fabs(l)) stop = true;
+      __syncthreads();  // s_y is rewritten by the next check
     }
     if (stop) break;
     const double inv_beta = 1.0 / beta;
     for (int r = tid; r < n; r += blockDim.x) V[(size_t)(j + 1) * n + r] = s_w[r] * inv_beta;
     __syncthreads();
   }
-  if (tid < 64) {
-    const double l = tri_lowest_wave(s_alpha, s_beta, iters, s_y, s_wk);
-    if (tid == 0) s_bc[0] = l;
-  }
-  __syncthreads();
-  const double lam = s_bc[0];
+  const double lam = tri_lowest_wg(s_alpha, s_beta, iters, s_y, s_wk, s_bal);
   // z = sqrt(-lambda) * (V^T y)
   const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
   for (int r = tid; r < n; r += blockDim.x) {

@@ -1234,13 +1234,9 @@ int select_support(cdfci_ctx* c, int64_t top_n, CallBufs& bufs, int64_t** sel, i
   HIP_TRY(bufs.alloc(sel, n));
   HIP_TRY(bufs.alloc(&sa, n));
   HIP_TRY(bufs.alloc(&sb, n));
-  const int hb = 1024;
-  for (int pass = 0; pass < kRadixPasses; ++pass) {
-    k_mc_hist<<<hb, 256, 0, s>>>(c->T, cand, cnt, gkey, c->ctl, st, hist, pass, 1);
-    k_mc_scan<<<1, 256, 0, s>>>(hist, st, cnt, (int)n, pass);
-  }
-  k_mc_gather<<<hb, 256, 0, s>>>(cand, cnt, gkey, st, *sel, ties);
-  k_mc_ties<<<1, 256, 0, s>>>(c->T, st, *sel, sa, sb, ties, (int)n);
+  for (int pass = 0; pass < kRadixPasses; ++pass)
+    k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, gkey, c->ctl, st, hist, pass, 1, (int)n);
+  k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, gkey, st, *sel, ties, sa, sb, (int)n);
   HIP_TRY(hipGetLastError());
   unsigned long long got = 0;
   HIP_TRY(hipMemcpyAsync(&got, &st->n_sel, sizeof(got), hipMemcpyDeviceToHost, s));

@@ -4,8 +4,9 @@
 // One step is a fixed sequence of launches with no host synchronisation:
 //   select   top-k of |4 b_j + 4 mu c_j| over the step's candidates (the union
 //            of the previous step's columns, deduplicated): MSB radix select
-//            on the bit pattern of the non-negative double |g| (six digit
-//            passes), exact ties at the threshold to the smaller key;
+//            on the bit pattern of the non-negative double |g| (one launch per
+//            digit, the last workgroup choosing the digit), exact ties at the
+//            threshold to the smaller key;
 //   H_II     pairwise Slater-Condon entries among the chosen determinants;
 //   reduced  A = Q^T H Q with Q = [c~, E_I] (eq. (def-z)); its lowest
 //            eigenpair (k <= 64: Householder tridiagonalisation in shared
@@ -108,171 +109,8 @@ __global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* 
   if (blockIdx.x == 0 && threadIdx.x == 0) st->n_pages = pages;
 }
 
-// radix-select histogram pass; pass 0 also computes the keys (|g| for the
-// multicoordinate selection, |c| when by_c is set)
-__global__ void __launch_bounds__(256) k_mc_hist(const Slot* T, const unsigned* cand,
-                                                 const unsigned* cnt, unsigned long long* gkey,
-                                                 const Ctl* ctl, const McState* st, unsigned* hist,
-                                                 int pass, int by_c) {
-  __shared__ unsigned h[kRadixBins];
-  if (st->skip) return;
-  if (pass > 0 && (st->all || st->done)) return;
-  for (int i = threadIdx.x; i < kRadixBins; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const unsigned long long n = st->n_pages * kPage;
-  const double mu = ctl->mu_hi + ctl->mu_lo;
-  const int sh = radix_shift(pass);
-  const unsigned long long dm = radix_digit_mask(pass);
-  const unsigned long long P = st->prefix, M = st->pmask;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
-    unsigned long long key;
-    if (pass == 0) {
-      key = by_c ? c_key(T[cand[i]]) : g_key(T[cand[i]], mu);
-      gkey[i] = key;
-    } else {
-      key = gkey[i];
-      if ((key & M) != P) continue;
-    }
-    atomicAdd(&h[(key >> sh) & dm], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kRadixBins; i += blockDim.x)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
-}
-
-// one workgroup: choose the digit of the bucket holding the k-th largest key
-__global__ void __launch_bounds__(256) k_mc_scan(unsigned* hist, McState* st, const unsigned* cnt,
-                                                 int k, int pass) {
-  __shared__ unsigned long long s_suffix[kRadixBins];  // count of bins > d
-  __shared__ unsigned long long s_total;
-  __shared__ int s_d;
-  if (st->skip) return;
-  const int tid = threadIdx.x;
-  if (pass == 0) {
-    // total candidates = sum of the page counts
-    unsigned long long part = 0;
-    for (unsigned long long p = tid; p < st->n_pages; p += blockDim.x) part += cnt[p];
-    if (tid == 0) s_total = 0;
-    __syncthreads();
-    atomicAdd(&s_total, part);
-    __syncthreads();
-    if (tid == 0) {
-      st->prefix = 0;
-      st->pmask = 0;
-      st->n_above = 0;
-      st->done = 0;
-      st->all = (s_total <= (unsigned long long)k) ? 1 : 0;
-      st->need = k;
-    }
-    __syncthreads();
-  }
-  if (!(st->all || st->done)) {
-    const int sh = radix_shift(pass);
-    const int nb = (int)radix_digit_mask(pass) + 1;
-    // s_suffix[d] = number of keys in bins strictly above d (block-wide scan
-    // from the top; each thread owns a run of bins)
-    const int per = (nb + blockDim.x - 1) / blockDim.x;
-    const int lo = tid * per, hi = min(nb, lo + per);
-    unsigned long long run = 0;
-    for (int d = hi - 1; d >= lo; --d) run += hist[d];
-    __shared__ unsigned long long s_run[256];
-    s_run[tid] = run;
-    __syncthreads();
-    if (tid == 0) {
-      unsigned long long acc = 0;
-      for (int t = (int)blockDim.x - 1; t >= 0; --t) {
-        unsigned long long r = s_run[t];
-        s_run[t] = acc;  // keys in the threads' runs above t
-        acc += r;
-      }
-    }
-    __syncthreads();
-    unsigned long long acc = s_run[tid];
-    for (int d = hi - 1; d >= lo; --d) {
-      s_suffix[d] = acc;
-      acc += hist[d];
-    }
-    if (tid == 0) s_d = 0;
-    __syncthreads();
-    const long long need = st->need;
-    for (int d = lo; d < hi; ++d) {
-      const long long above = (long long)s_suffix[d];
-      if (above < need && above + (long long)hist[d] >= need) s_d = d;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const int d = s_d;
-      const long long above = (long long)s_suffix[d];
-      st->n_above += (unsigned long long)above;
-      st->need = need - above;
-      st->prefix |= (unsigned long long)d << sh;
-      st->pmask |= radix_digit_mask(pass) << sh;
-      if ((long long)hist[d] == need - above) st->done = 1;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < kRadixBins; i += blockDim.x) hist[i] = 0;
-}
-
-// selected slots -> sel_slot (order irrelevant); exact ties -> tie buffer
-__global__ void __launch_bounds__(256) k_mc_gather(const unsigned* cand, const unsigned* cnt,
-                                                   const unsigned long long* gkey, McState* st,
-                                                   int64_t* sel_slot, unsigned* ties) {
-  if (st->skip) return;
-  const unsigned long long n = st->n_pages * kPage;
-  const unsigned long long P = st->prefix, M = st->pmask;
-  const int all = st->all, done = st->done;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
-    const unsigned long long km = gkey[i] & M;
-    const bool take = all || km > P || (done && km == P);
-    if (take) {
-      unsigned long long s = atomicAdd(&st->n_sel, 1ull);
-      sel_slot[s] = cand[i];
-    } else if (km == P) {
-      unsigned long long t = atomicAdd(&st->n_tie, 1ull);
-      if (t < kMaxTies) ties[t] = cand[i];
-    }
-  }
-}
-
-// resolve exact ties by key order, then fill the keys of the chosen set
-__global__ void __launch_bounds__(256) k_mc_ties(const Slot* T, McState* st, int64_t* sel_slot,
-                                                 uint64_t* sel_a, uint64_t* sel_b, const unsigned* ties,
-                                                 int k) {
-  __shared__ unsigned long long s_base;
-  if (st->skip) return;
-  const int tid = threadIdx.x;
-  if (!(st->all || st->done)) {
-    const long long need = st->need;
-    const int nt = (int)min(st->n_tie, (unsigned long long)kMaxTies);
-    if (tid == 0) s_base = st->n_sel;
-    __syncthreads();
-    for (int i = tid; i < nt; i += blockDim.x) {
-      const Slot si = T[ties[i]];
-      int rank = 0;
-      for (int j = 0; j < nt; ++j) {
-        const Slot sj = T[ties[j]];
-        if (key_less(sj.ka, sj.kb, si.ka, si.kb)) ++rank;
-      }
-      if (rank < need) sel_slot[s_base + rank] = ties[i];
-    }
-    __syncthreads();
-    if (tid == 0) st->n_sel = s_base + (unsigned long long)min((long long)nt, need);
-  }
-  __syncthreads();
-  const int m = (int)min(st->n_sel, (unsigned long long)k);
-  for (int i = tid; i < m; i += blockDim.x) {
-    const Slot s = T[sel_slot[i]];
-    sel_a[i] = s.ka;
-    sel_b[i] = s.kb;
-  }
-}
-
-// clear the candidate bitmap for the coming scatter
+// clear the candidate bitmap and the gather counters (entering the
+// multicoordinate state; inside a step the eigen launch clears the bitmap)
 __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwords, McState* st) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
        i += (uint64_t)gridDim.x * blockDim.x)

@@ -40,14 +40,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_ELEMENT = 40
 COUNTERS = os.path.join(ROOT, "profiles", "k_cd1_abinitio_n24_hbm_counters.md")
-KERNEL_SOURCES = ["paper_2605_04483_amd/csrc/cdfci.hip", "paper_2605_04483_amd/csrc/device.h"]
+# k_cd1 is compiled from csrc/device.h and the part of csrc/cdfci.hip up to the
+# end of the kernel (the multicoordinate, reverse-pass and batch code follows it)
+K_CD1_END = b"// Adds the step count after the persistent kernel"
 
 
 def sources_sha256():
+    """sha256 of device.h followed by cdfci.hip up to the end of k_cd1."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2605_04483_amd/csrc/device.h"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2605_04483_amd/csrc/cdfci.hip"), "rb") as f:
+        src = f.read()
+    end = src.find(K_CD1_END)
+    h.update(src if end < 0 else src[:end])
     return h.hexdigest()
 
 

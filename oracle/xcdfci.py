@@ -1,0 +1,192 @@
+"""Serial coordinate descent for several low-lying states, xCDFCI (Sec. 3.3,
+Algorithm 3; line search in Appendix A).  Test infrastructure only: columns
+come from the C++ oracle's get_column, the subspace eigenproblem and the
+(K+1)-dimensional pencil from LAPACK (numpy / scipy).
+
+C holds n = K + 1 columns (one per state), stored by rows: C_j is the row of
+determinant j.  B = H C, S = C^T C and Q = C^T H C (n x n).  One iteration:
+1. i = argmax over the candidates of ||G_j||_inf with G = 4 B + 4 C S
+   (candidates: the column of the previous coordinate plus that coordinate;
+   ties to the smaller (beta, alpha) key).
+2. With g = G_i, the step C <- C + eta e_i g minimises
+   h(eta) = f(C + eta e_i g) - f(C) = w4 eta^4 + w3 eta^3 + w2 eta^2 + w1 eta,
+       w1 = ||g||^2,
+       w2 = 2 H_ii ||g||^2 + 2 (C_i . g)^2 + 2 ||C_i||^2 ||g||^2 + 2 g S g^T,
+       w3 = 4 ||g||^2 (C_i . g),   w4 = ||g||^4
+   (reading: the appendix prints w1 = 4 ||g||^2, but with G = 4B + 4CS the
+   slope of h at 0 is <G, e_i g> = ||g||^2, which is also what the single
+   state case reduces to; the other three coefficients are as printed).
+   eta is the argmin of the monic quartic h / w4 by the Algorithm 1 rule.
+3. S <- S + eta (C_i^T g + g^T C_i) + eta^2 g^T g,
+   Q <- Q + eta (B_i^T g + g^T B_i) + eta^2 H_ii g^T g   (pre-step rows;
+   the products are outer products, n x n),
+   C_i <- C_i + eta g,
+   B_j <- B_j + eta H_ji g over the column of i, with the compression rule
+   per contribution row: update B_j iff C_j != 0 or |eta H_ji| ||g||_inf >= tau,
+   then B_i = sum_j H_ji C_j recomputed.
+4. Energies: the generalised eigenvalues of the pencil (Q, S), ascending;
+   damped accumulator d of the step norm |eta| ||g||_2.
+With n = 1 every step is the step of Algorithm 1 (eta g is its step in c_i).
+
+Shift: the objective needs E_0 <= ... <= E_K < 0 (Sec. 2.3).  An optional
+constant sigma replaces H by H - sigma I (every diagonal element, the
+subspace matrix included); the eigenvectors are unchanged and the reported
+energies add sigma back.
+
+Initial C (the paper leaves it open): the lowest n eigenpairs (lambda_k, v_k)
+of H on the subspace {D0} + the column entries of D0 with the largest
+|H_j,D0| (nonzero, at most m_max - 1 of them, ties to the smaller key);
+column k of C^(0) is sqrt(-lambda_k) v_k (every lambda_k < 0 is required),
+signed so that its largest-magnitude component (first such) is positive.
+B^(0) = H C^(0) exactly, S and Q from the stored rows, and the first
+coordinate is the argmax of ||G_j||_inf over every stored entry.
+"""
+import numpy as np
+import scipy.linalg
+
+from . import cd as cdmod
+from . import fci
+
+
+def _order_key(k):
+    return (k[1], k[0])
+
+
+def subspace_init(h, eri, D0, n_states, m_max=128, shift=0.0):
+    """Keys of the initial subspace and C^(0) (m x n), for H - shift I."""
+    N = h.shape[0]
+    ka, kb, v = cdmod.column(h, eri, *D0)
+    d0 = (int(ka[0]), int(kb[0]))
+    rest = [((int(x), int(y)), float(z)) for x, y, z in zip(ka[1:], kb[1:], v[1:]) if z != 0.0]
+    rest.sort(key=lambda kv: (-abs(kv[1]), _order_key(kv[0])))
+    keys = [d0] + [k for k, _ in rest[: m_max - 1]]
+    m = len(keys)
+    if m < n_states:
+        raise ValueError("subspace smaller than the number of states")
+    Hs = np.zeros((m, m))
+    for j, kj in enumerate(keys):
+        for i, ki in enumerate(keys):
+            Hs[i, j] = fci.entry(h, eri, N, ki, kj) - (shift if i == j else 0.0)
+    w, V = np.linalg.eigh(Hs)
+    if not w[n_states - 1] < 0:
+        raise ValueError("a requested subspace eigenvalue is not negative")
+    C0 = np.zeros((m, n_states))
+    for k in range(n_states):
+        vec = V[:, k]
+        p = int(np.argmax(np.abs(vec)))
+        if vec[p] < 0:
+            vec = -vec
+        C0[:, k] = np.sqrt(-w[k]) * vec
+    return keys, C0
+
+
+def w_coeffs(Ci, Bi, g, S, Hii):
+    """Coefficients (w1, w2, w3, w4) of h(eta) = f(C + eta e_i g) - f(C)."""
+    gg = float(g @ g)
+    cg = float(Ci @ g)
+    w1 = gg
+    w2 = 2.0 * Hii * gg + 2.0 * cg * cg + 2.0 * float(Ci @ Ci) * gg + 2.0 * float(g @ S @ g)
+    w3 = 4.0 * gg * cg
+    w4 = gg * gg
+    return w1, w2, w3, w4
+
+
+def pencil_energies(Q, S):
+    """Ascending generalised eigenvalues of (Q, S)."""
+    return np.sort(scipy.linalg.eigh(Q, S, eigvals_only=True))
+
+
+class XCDResult:
+    pass
+
+
+def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=0.0, shift=0.0):
+    N = h.shape[0]
+    n = C0.shape[1]
+    colcache = {}
+
+    def col(k):
+        # column of H - shift I (the diagonal entry comes first)
+        r = colcache.get(k)
+        if r is None:
+            ka, kb, v = cdmod.column(h, eri, k[0], k[1])
+            r = [((int(x), int(y)), float(z) - (shift if e == 0 else 0.0))
+                 for e, (x, y, z) in enumerate(zip(ka, kb, v))]
+            colcache[k] = r
+            if len(colcache) > 200000:
+                colcache.clear()
+        return r
+
+    zero = np.zeros(n)
+    C = {}
+    B = {}
+    for k, row in zip(init_keys, C0):
+        C[k] = C.get(k, zero) + row
+    for k, row in zip(init_keys, C0):
+        for j, Hj in col(k):
+            if Hj == 0.0:
+                continue
+            B[j] = B.get(j, zero) + Hj * row
+            C.setdefault(j, zero.copy())
+    keys0 = list(C.keys())
+    Cm = np.array([C[k] for k in keys0], dtype=np.longdouble)
+    Bm = np.array([B.get(k, zero) for k in keys0], dtype=np.longdouble)
+    S = Cm.T @ Cm
+    Q = Cm.T @ Bm
+
+    def grad_row(k, S64):
+        return 4.0 * B.get(k, zero) + 4.0 * C.get(k, zero) @ S64
+
+    S64 = np.array(S, dtype=np.float64)
+    # first coordinate: argmax over every stored entry
+    cand = set(C.keys())
+    energies, selections, gaps, etas = [], [], [], []
+    d = 0.0
+    for step in range(max_steps):
+        S64 = np.array(S, dtype=np.float64)
+        gn = {j: float(np.max(np.abs(grad_row(j, S64)))) for j in cand}
+        order = sorted(cand, key=lambda j: (-gn[j], _order_key(j)))
+        i = order[0]
+        gaps.append((gn[order[0]] - gn[order[1]]) / gn[order[0]] if len(order) > 1 and gn[order[0]] > 0 else 1.0)
+        Ci = C.get(i, zero).copy()
+        Bi = B.get(i, zero).copy()
+        g = 4.0 * Bi + 4.0 * Ci @ S64
+        Hii = dict(col(i))[i]
+        w1, w2, w3, w4 = w_coeffs(Ci, Bi, g, S64, Hii)
+        eta = 0.0 if w4 == 0.0 else cdmod.line_search(w1 / w4, w2 / w4, w3 / w4)
+        gL = g.astype(np.longdouble)
+        CiL, BiL = Ci.astype(np.longdouble), Bi.astype(np.longdouble)
+        etaL = np.longdouble(eta)
+        S = S + etaL * (np.outer(CiL, gL) + np.outer(gL, CiL)) + etaL * etaL * np.outer(gL, gL)
+        Q = Q + etaL * (np.outer(BiL, gL) + np.outer(gL, BiL)) + etaL * etaL * np.longdouble(Hii) * np.outer(gL, gL)
+        C[i] = Ci + eta * g
+        ginf = float(np.max(np.abs(g)))
+        newcand = {i}
+        for j, Hj in col(i):
+            if Hj == 0.0 or j == i:
+                continue
+            newcand.add(j)
+            cj = C.get(j)
+            if (cj is not None and np.any(cj != 0.0)) or abs(eta * Hj) * ginf >= tau:
+                B[j] = B.get(j, zero) + (eta * Hj) * g
+                C.setdefault(j, zero.copy())
+        B[i] = sum((Hj * C.get(j, zero) for j, Hj in col(i)), zero.copy())
+        step_norm = abs(eta) * float(np.sqrt(g @ g))
+        d = step_norm if step == 0 else theta * d + (1.0 - theta) * step_norm
+        energies.append(shift + pencil_energies(np.array(Q, dtype=np.float64), np.array(S, dtype=np.float64)))
+        selections.append(i)
+        etas.append(eta)
+        cand = newcand
+        if d < dx_tol:
+            break
+    r = XCDResult()
+    r.energies = np.array(energies)
+    r.selections = selections
+    r.gaps = np.array(gaps)
+    r.eta = np.array(etas)
+    r.S = np.array(S, dtype=np.float64)
+    r.Q = np.array(Q, dtype=np.float64)
+    r.C = C
+    r.B = B
+    r.steps = len(energies)
+    return r

@@ -555,11 +555,11 @@ struct EigArgs {
 //   A_00 = a00, A_0i = A_i0 = a0_i, A_ij = (H_II)_ij.
 // y = A x.  H_II (exactly symmetric) is read column-wise so a wave's loads are
 // contiguous.  The waves split the work into 64-row blocks times column
-// slices; each lane keeps four independent partial sums so loads overlap, and
-// the slices are combined in shared memory (s_part, 16 * 1025 doubles would
-// not fit, so slices are combined one row block at a time).
+// slices; each lane issues eight loads at a time into four independent partial
+// sums, and the slices are combined in shared memory (s_part, 16 * 1025
+// doubles would not fit, so slices are combined one row block at a time).
 __device__ void mc_matvec(const double* __restrict__ hii, int m, int off, double a00,
-                          const double* s_a0, const double* s_x, double* s_y, int n, double* s_part) {
+                          const double* s_a0, const double* s_x, double* s_y, double* s_part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nrb = (m + 63) >> 6;                     // row blocks of H_II
   const int ns = nrb >= nw ? 1 : nw / nrb;           // column slices per row block
@@ -737,7 +737,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   }
   __syncthreads();
   // hc = H_II c_I
-  mc_matvec(hii, m, 0, 0.0, s_a0, s_c, s_w, m, s_part);
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_c, s_w, s_part);
   __syncthreads();
   const double hc_i = tid < m ? s_w[tid] : 0.0;
   const double ci = tid < m ? s_c[tid] : 0.0, bi = tid < m ? s_b[tid] : 0.0;
@@ -776,7 +776,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   for (int j = 0; j < jmax; ++j) {
     for (int r = tid; r < n; r += blockDim.x) s_x[r] = V[(size_t)j * n + r];
     __syncthreads();
-    mc_matvec(hii, m, off, a00, s_a0, s_x, s_w, n, s_part);
+    mc_matvec(hii, m, off, a00, s_a0, s_x, s_w, s_part);
     __syncthreads();
     // classical Gram-Schmidt against V_0..V_j, twice
     mc_multidot(V, n, j, s_w, s_h);
@@ -839,7 +839,7 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   __syncthreads();
   if (tid < m) s_x[tid] = eta_i;
   __syncthreads();
-  mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, m, s_part);
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, s_part);
   __syncthreads();
   const double heta_i = tid < m ? s_w[tid] : 0.0;
   mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);

@@ -33,13 +33,13 @@ constant sigma replaces H by H - sigma I (every diagonal element, the
 subspace matrix included); the eigenvectors are unchanged and the reported
 energies add sigma back.
 
-Initial C (the paper leaves it open): the lowest n eigenpairs (lambda_k, v_k)
-of H on the subspace {D0} + the column entries of D0 with the largest
-|H_j,D0| (nonzero, at most m_max - 1 of them, ties to the smaller key);
-column k of C^(0) is sqrt(-lambda_k) v_k (every lambda_k < 0 is required),
-signed so that its largest-magnitude component (first such) is positive.
-B^(0) = H C^(0) exactly, S and Q from the stored rows, and the first
-coordinate is the argmax of ||G_j||_inf over every stored entry.
+Initial C (Sec. 4.1.3, the excited-state solver): D_1 is the reference
+determinant and D_2 .. D_n the determinants of lowest diagonal H_jj among
+those connected to it (H_j,D1 != 0), each chosen from the ones not yet taken
+(reading: equal H_jj ordered by the smaller (beta, alpha) key); column k of
+C^(0) is the unit vector at D_k, B^(0) = H C^(0).  S and Q come from the
+stored rows, and the first coordinate, which the paper leaves open, is the
+argmax of ||G_j||_inf over every stored entry.
 """
 import numpy as np
 import scipy.linalg
@@ -52,32 +52,18 @@ def _order_key(k):
     return (k[1], k[0])
 
 
-def subspace_init(h, eri, D0, n_states, m_max=128, shift=0.0):
-    """Keys of the initial subspace and C^(0) (m x n), for H - shift I."""
+def initial_rows(h, eri, D0, n_states):
+    """Keys D_1 .. D_n of the start and C^(0) restricted to them (the n x n
+    identity)."""
     N = h.shape[0]
     ka, kb, v = cdmod.column(h, eri, *D0)
     d0 = (int(ka[0]), int(kb[0]))
-    rest = [((int(x), int(y)), float(z)) for x, y, z in zip(ka[1:], kb[1:], v[1:]) if z != 0.0]
-    rest.sort(key=lambda kv: (-abs(kv[1]), _order_key(kv[0])))
-    keys = [d0] + [k for k, _ in rest[: m_max - 1]]
-    m = len(keys)
-    if m < n_states:
-        raise ValueError("subspace smaller than the number of states")
-    Hs = np.zeros((m, m))
-    for j, kj in enumerate(keys):
-        for i, ki in enumerate(keys):
-            Hs[i, j] = fci.entry(h, eri, N, ki, kj) - (shift if i == j else 0.0)
-    w, V = np.linalg.eigh(Hs)
-    if not w[n_states - 1] < 0:
-        raise ValueError("a requested subspace eigenvalue is not negative")
-    C0 = np.zeros((m, n_states))
-    for k in range(n_states):
-        vec = V[:, k]
-        p = int(np.argmax(np.abs(vec)))
-        if vec[p] < 0:
-            vec = -vec
-        C0[:, k] = np.sqrt(-w[k]) * vec
-    return keys, C0
+    conn = [(int(x), int(y)) for x, y, z in zip(ka[1:], kb[1:], v[1:]) if z != 0.0]
+    conn.sort(key=lambda k: (fci.diagonal(h, eri, N, k[0], k[1]), _order_key(k)))
+    keys = [d0] + conn[: n_states - 1]
+    if len(keys) < n_states:
+        raise ValueError("fewer connected determinants than states")
+    return keys, np.eye(n_states)
 
 
 def w_coeffs(Ci, Bi, g, S, Hii):

@@ -74,7 +74,7 @@ def test_converges_to_the_lowest_eigenvalues(system, n):
     N = h.shape[0]
     H, _ = fci.dense_H(h, eri, N, na, nb)
     E = np.linalg.eigvalsh(H)[:n]
-    keys, C0 = oxc.subspace_init(h, eri, D0, n, shift=shift)
+    keys, C0 = oxc.initial_rows(h, eri, D0, n)
     x = oxc.xcdfci_run(h, eri, keys, C0, max_steps=60000, dx_tol=1e-12, shift=shift)
     assert x.steps < 60000
     assert np.max(np.abs(x.energies[-1] - E)) < 1e-8, (x.energies[-1], E)
@@ -82,16 +82,24 @@ def test_converges_to_the_lowest_eigenvalues(system, n):
 
 def test_maintained_matrices_and_subspace_start():
     """S, Q and B as maintained equal C^T C, C^T H C and H C recomputed from
-    the stored rows (tau = 0); C^(0) diagonalises H on its subspace."""
+    the stored rows (tau = 0).  The start rows are the reference determinant
+    and, among the determinants the dense H connects to it, those of lowest
+    diagonal (checked by brute force over the dense matrix)."""
     N, na, nb = 6, 3, 3
     h, eri = synth_inputs.ab_initio(N, 18, 11)
     H, basis = fci.dense_H(h, eri, N, na, nb)
     index = {k: i for i, k in enumerate(basis)}
     n = 3
-    keys, C0 = oxc.subspace_init(h, eri, ocd.aufbau(h, na, nb), n)
-    Hs = np.array([[H[index[a], index[b]] for b in keys] for a in keys])
-    D = C0.T @ Hs @ C0
-    assert np.max(np.abs(D - np.diag(np.diag(D)))) < 1e-10 * np.max(np.abs(D))
+    D0 = ocd.aufbau(h, na, nb)
+    keys, C0 = oxc.initial_rows(h, eri, D0, n)
+    i0 = index[D0]
+    assert keys[0] == D0 and len(set(keys)) == n
+    conn = [j for j in range(len(basis)) if j != i0 and H[j, i0] != 0.0]
+    chosen = [index[k] for k in keys[1:]]
+    assert all(H[j, i0] != 0.0 for j in chosen)
+    worst = max(H[j, j] for j in chosen)
+    assert all(H[j, j] >= worst for j in conn if j not in chosen)
+    assert np.array_equal(C0, np.eye(n))
     x = oxc.xcdfci_run(h, eri, keys, C0, max_steps=400)
     Cm = np.zeros((len(basis), n))
     for k, row in x.C.items():

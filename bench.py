@@ -21,7 +21,11 @@ Further blocks on the same JSON line (skipped with --no-extra):
                     replayed graph (autotuned), against the single-instance
                     path on a sample of the same instances;
   rdm               RDM reverse pass on the top 10^6 determinants of the
-                    headline run's final state.
+                    headline run's final state;
+  xcdfci            several low-lying states (Alg. 3) on the headline system:
+                    4 states, 2^26-slot table, tau = 5e-5, iterations/s and
+                    entries/s of the one-launch-per-iteration path, with the
+                    multi-state oracle timed on its first iterations.
 
 --copy-probe runs only a device copy of known size (for calibrating the HBM
 byte counters of a profiler run) and exits.
@@ -69,6 +73,22 @@ def measured_traffic_per_element():
     if not m or not s or s.group(1) != sources_sha256():
         return None
     return float(m.group(1))
+
+
+def cpu_baseline_xcdfci(synth_inputs, tau, steps=20):
+    """The multi-state oracle (one core) on the first iterations of the
+    xcdfci block's run."""
+    from oracle import cd as ocd
+    from oracle import xcdfci as oxc
+
+    N, na, nb, n = 24, 6, 6, 4
+    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    keys, C0 = oxc.initial_rows(h, eri, ocd.aufbau(h, na, nb), n)
+    t0 = time.perf_counter()
+    orc = oxc.xcdfci_run(h, eri, keys, C0, tau=tau, max_steps=steps)
+    t_cpu = time.perf_counter() - t0
+    return {"value": orc.steps / t_cpu, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {steps} iterations from the same start (set-up included)"}
 
 
 def cpu_baseline(h, eri, na, nb, seconds_target=15.0):
@@ -221,6 +241,31 @@ def hubbard_batch(api, synth_inputs, args):
             "plain_sample": f"{len(seen)} instances (one per shape), 20000 iterations each, run one after another"}
 
 
+def xcdfci_block(api, synth_inputs, args):
+    import torch
+
+    N, na, nb, n = 24, 6, 6, 4
+    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    n_col = 16471
+    x = api.cdfci_xinit(h, eri, na, nb, n, table_slots=1 << 26, z_threshold=args.tau)
+    api.cdfci_xstep(x, 2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = api.cdfci_xstep(x, args.xcd_iters)
+    wall = time.perf_counter() - t0
+    E = api.cdfci_xenergies(x)
+    x.close()
+    # bytes per column entry: key (16) + C and B rows read (16 n) + B row written (8 n)
+    per_entry = 16 + 24 * n
+    out = {"workload": f"ab initio N=24 6a+6b naux=72 seed=2024, {n} states, 2^26-slot table, tau={args.tau}",
+           "iterations": st["steps"], "iters_per_s": st["steps"] / wall,
+           "elements_per_s": st["steps"] * n_col / wall, "us_per_iter": 1e6 * wall / max(1, st["steps"]),
+           "device_seconds": st["seconds"], "energies": E.tolist(), "occupied": st["occupied"],
+           "algorithmic_bytes_per_entry": per_entry,
+           "achieved_GBs": per_entry * st["steps"] * n_col / st["seconds"] / 1e9}
+    return out
+
+
 def rdm_block(api, ctx, n_col):
     top_n = 1_000_000
     ka, _, _, _ = api.cdfci_export(ctx, top_n=top_n)
@@ -250,7 +295,8 @@ def main():
     ap.add_argument("--n36-steps", type=int, default=8)
     ap.add_argument("--n36-plain-seconds", type=float, default=20.0)
     ap.add_argument("--batch-steps", type=int, default=100000)
-    ap.add_argument("--only", choices=("n36", "hubbard", "rdm"), default=None,
+    ap.add_argument("--xcd-iters", type=int, default=20000)
+    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd"), default=None,
                     help="diagnostic: run one extra block alone (for profiler runs) and print it")
     ap.add_argument("--n36-k", type=int, default=0, help="with --only n36: a single k")
     args = ap.parse_args()
@@ -279,6 +325,12 @@ def main():
         return
     if args.only == "hubbard":
         print(json.dumps({"hubbard_batch": hubbard_batch(api, synth_inputs, args)}), flush=True)
+        return
+    if args.only == "xcd":
+        blk = xcdfci_block(api, synth_inputs, args)
+        if not args.no_cpu:
+            blk["cpu_baseline"] = cpu_baseline_xcdfci(synth_inputs, args.tau)
+        print(json.dumps({"xcdfci": blk}), flush=True)
         return
     N, na, nb, naux = 24, 6, 6, 72
     seed = synth_inputs.CONFIG_SEEDS["abinitio_n24"]
@@ -349,6 +401,7 @@ def main():
                           lambda: batched_vs_plain(api, h, eri, na, nb, args, st["energy"], warm_wall + wall,
                                                    n_col)),
                          ("mcd_n36", lambda: mcd_n36(api, synth_inputs, args)),
+                         ("xcdfci", lambda: xcdfci_block(api, synth_inputs, args)),
                          ("hubbard_batch", lambda: hubbard_batch(api, synth_inputs, args))):
             try:
                 out[name] = fn()
@@ -358,6 +411,8 @@ def main():
                 log(f"{name}: error {e}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(h, eri, na, nb)
+        if isinstance(out.get("xcdfci"), dict) and "error" not in out["xcdfci"]:
+            out["xcdfci"]["cpu_baseline"] = cpu_baseline_xcdfci(synth_inputs, args.tau)
     print(json.dumps(out), flush=True)
 
 

@@ -262,6 +262,64 @@ int cdfci_tune_k(cdfci_ctx* ctx, const int* ks, int nk, double seconds_per_trial
 int cdfci_tune_batch(cdfci_batch* batch, const int64_t* chunks, int nc, const int* launches, int nl,
                      int64_t steps_per_trial, int64_t* best_chunk, int* best_launches);
 
+/* ---- Several low-lying states: xCDFCI (Sec. 3.3, Alg. 3) ---------------------
+ * Minimises f(C) = ||H - sigma I + C C^T||_F^2 over C with n = K + 1 columns
+ * (1 <= n <= 8).  At a minimiser the column space of C is the span of the n
+ * lowest eigenvectors of H; the energies are the eigenvalues of the pencil
+ * (C^T H C, C^T C).  C and B = (H - sigma I) C live in a device hash table
+ * keyed by determinant, one row of n doubles each; S = C^T C and
+ * Q = C^T (H - sigma I) C are maintained in double-double precision.  One
+ * iteration takes the row i of largest ||G_i||_inf, G = 4 B + 4 C S, among
+ * the previous coordinate's column and that coordinate itself, and sets
+ * C_i <- C_i + eta G_i with eta the exact minimiser of the quartic
+ * f(C + eta e_i G_i) (Appendix A; the slope coefficient is ||G_i||^2), then
+ * updates B over column i under the compression rule of Sec. 3.1 (z_threshold)
+ * and recalculates B_i.
+ *
+ * sigma (shift) must make the n lowest eigenvalues of H - sigma I negative,
+ * which f needs (Sec. 2.3); reported energies add it back.  Start (Sec. 4.1.3,
+ * excited-state solver): D_1 = the reference determinant, D_2 .. D_n the
+ * determinants of lowest diagonal H_jj among those connected to D_1
+ * (H_j,D1 != 0; equal H_jj ordered by the smaller (beta, alpha) key), column
+ * k of C^(0) the unit vector at D_k, B^(0) = (H - sigma I) C^(0); the first
+ * coordinate is the stored row of largest ||G_j||_inf.  The reference is the
+ * aufbau determinant (lowest h_pp; opts->init_kind == 2: the alternating
+ * chain pattern as in cdfci_init), or the Neel determinant for lattices.
+ * Only table_slots, load_factor, z_threshold, dx_damping, dx_threshold and
+ * stream of opts are used.  CDFCI_ERR_UNSUPPORTED if fewer than n - 1
+ * determinants are connected to D_1. */
+typedef struct cdfci_xctx cdfci_xctx; /* opaque, library-owned */
+
+int cdfci_xinit(const double* h, const double* eri, int n_orb, int n_alpha, int n_beta, int n_states,
+                double shift, const cdfci_opts* opts, cdfci_xctx** out);
+
+/* The same for a periodic Hubbard lattice (as cdfci_init_hubbard). */
+int cdfci_xinit_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                        int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out);
+
+/* Run up to nsteps iterations (one kernel launch each) and stop early when
+ * the damped accumulator of |eta| ||G_i||_2 falls below dx_threshold.  Host
+ * traces, any may be NULL: energies (nsteps * n, the pencil's eigenvalues
+ * after each iteration, ascending), sel_alpha / sel_beta (nsteps, the row
+ * updated).  out may be NULL; its energy field is the lowest energy, mu and
+ * alpha are trace(S) and trace(Q). */
+int cdfci_xstep(cdfci_xctx* x, int64_t nsteps, double* energies, uint64_t* sel_alpha, uint64_t* sel_beta,
+                cdfci_stats* out);
+
+/* Current energies (n doubles, ascending, shift added back). */
+int cdfci_xenergies(cdfci_xctx* x, double* energies);
+
+/* The maintained S = C^T C and Q = C^T (H - sigma I) C (n*n row-major each,
+ * rounded to double; either may be NULL). */
+int cdfci_xmatrices(cdfci_xctx* x, double* S, double* Q);
+
+/* Every stored determinant: keys 2*cap uint64 (alpha, beta), C and B rows
+ * (n doubles each, cap*n), in no particular order.  *count = entries stored;
+ * at most cap are written. */
+int cdfci_xexport(cdfci_xctx* x, uint64_t* keys, double* C, double* B, int64_t cap, int64_t* count);
+
+int cdfci_xfree(cdfci_xctx* x);
+
 const char* cdfci_strerror(int code);
 const char* cdfci_last_error(void);
 

@@ -134,6 +134,16 @@ SIGNATURES = [
     ("cdfci_tune_batch", ctypes.c_int,
      [_P, _I64P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64, _I64P,
       ctypes.POINTER(ctypes.c_int)]),
+    ("cdfci_xinit", ctypes.c_int,
+     [_DP, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _OPTP, _CTXP]),
+    ("cdfci_xinit_hubbard", ctypes.c_int,
+     [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+      ctypes.c_int, ctypes.c_int, ctypes.c_double, _OPTP, _CTXP]),
+    ("cdfci_xstep", ctypes.c_int, [_P, ctypes.c_int64, _DP, _UP, _UP, _STP]),
+    ("cdfci_xenergies", ctypes.c_int, [_P, _DP]),
+    ("cdfci_xmatrices", ctypes.c_int, [_P, _DP, _DP]),
+    ("cdfci_xexport", ctypes.c_int, [_P, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
+    ("cdfci_xfree", ctypes.c_int, [_P]),
     ("cdfci_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cdfci_last_error", ctypes.c_char_p, []),
 ]

@@ -335,3 +335,108 @@ def cdfci_tune_batch(batch, chunks=(256, 1024, 4096), launches=(1, 4, 16), steps
     _check(_lib.load().cdfci_tune_batch(batch.handle, ca, len(chunks), la, len(launches), int(steps_per_trial),
                                         ctypes.byref(bc), ctypes.byref(bl)), "cdfci_tune_batch")
     return bc.value, bl.value
+
+
+# ---------------------------------------------------------------- several states (xCDFCI)
+
+class XContext:
+    """Owns a cdfci_xctx (n_states columns of C and of B = (H - shift) C)."""
+
+    def __init__(self, handle, N, na, nb, n_states, shift):
+        self.handle = handle
+        self.N, self.na, self.nb = N, na, nb
+        self.n_states = n_states
+        self.shift = shift
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle:
+            _lib.load().cdfci_xfree(self.handle)
+            self.handle = None
+
+
+def _torch_stream(opts):
+    if not opts.stream:
+        import torch
+
+        opts.stream = ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+
+
+def cdfci_xinit(h, eri, n_alpha, n_beta, n_states, shift=0.0, **kw):
+    L = _lib.load()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    N = h.shape[0]
+    assert h.shape == (N, N) and eri.shape == (N, N, N, N)
+    opts = make_opts(**kw)
+    _torch_stream(opts)
+    x = ctypes.c_void_p()
+    _check(L.cdfci_xinit(_dp(h), _dp(eri), N, int(n_alpha), int(n_beta), int(n_states), float(shift),
+                         ctypes.byref(opts), ctypes.byref(x)), "cdfci_xinit")
+    return XContext(x, N, n_alpha, n_beta, int(n_states), float(shift))
+
+
+def cdfci_xinit_hubbard(dims, t, U, n_alpha, n_beta, n_states, shift=0.0, **kw):
+    L = _lib.load()
+    d = (ctypes.c_int * len(dims))(*[int(v) for v in dims])
+    N = int(np.prod(dims))
+    opts = make_opts(**kw)
+    _torch_stream(opts)
+    x = ctypes.c_void_p()
+    _check(L.cdfci_xinit_hubbard(d, len(dims), float(t), float(U), int(n_alpha), int(n_beta), int(n_states),
+                                 float(shift), ctypes.byref(opts), ctypes.byref(x)), "cdfci_xinit_hubbard")
+    return XContext(x, N, n_alpha, n_beta, int(n_states), float(shift))
+
+
+def cdfci_xstep(x, nsteps, trace=False):
+    """Returns stats, or (energies[steps, n], sel_alpha, sel_beta, stats) with trace."""
+    st = cdfci_stats()
+    L = _lib.load()
+    if not trace:
+        _check(L.cdfci_xstep(x.handle, int(nsteps), None, None, None, ctypes.byref(st)), "cdfci_xstep")
+        return st.as_dict()
+    m = max(int(nsteps), 1)
+    E = np.zeros((m, x.n_states))
+    a = np.zeros(m, np.uint64)
+    b = np.zeros(m, np.uint64)
+    _check(L.cdfci_xstep(x.handle, int(nsteps), _dp(E), _up(a), _up(b), ctypes.byref(st)), "cdfci_xstep")
+    n = st.steps
+    return E[:n], a[:n], b[:n], st.as_dict()
+
+
+def cdfci_xenergies(x):
+    E = np.zeros(x.n_states)
+    _check(_lib.load().cdfci_xenergies(x.handle, _dp(E)), "cdfci_xenergies")
+    return E
+
+
+def cdfci_xmatrices(x):
+    n = x.n_states
+    S = np.zeros((n, n))
+    Q = np.zeros((n, n))
+    _check(_lib.load().cdfci_xmatrices(x.handle, _dp(S), _dp(Q)), "cdfci_xmatrices")
+    return S, Q
+
+
+def cdfci_xexport(x):
+    """Returns (alpha keys, beta keys, C rows [m, n], B rows [m, n])."""
+    L = _lib.load()
+    cnt = ctypes.c_int64(0)
+    _check(L.cdfci_xexport(x.handle, None, None, None, 0, ctypes.byref(cnt)), "cdfci_xexport")
+    m = cnt.value
+    n = x.n_states
+    keys = np.zeros(2 * max(m, 1), np.uint64)
+    C = np.zeros((max(m, 1), n))
+    B = np.zeros((max(m, 1), n))
+    _check(L.cdfci_xexport(x.handle, _up(keys), _dp(C), _dp(B), m, ctypes.byref(cnt)), "cdfci_xexport")
+    m = min(m, cnt.value)
+    return keys[0:2 * m:2].copy(), keys[1:2 * m:2].copy(), C[:m], B[:m]
+
+
+def cdfci_xfree(x):
+    x.close()

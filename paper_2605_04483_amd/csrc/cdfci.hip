@@ -887,6 +887,7 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
 #include "mcd_kernels.h"
 #include "rdm_kernels.h"
 #include "hub_kernels.h"
+#include "xcd_kernels.h"
 
 // per-instance step budget of the coming batch call (traced: only instance
 // `only` advances)
@@ -1178,6 +1179,48 @@ std::vector<std::pair<int, int>> lattice_bonds(const int* dims, int ndim) {
   return bonds;
 }
 
+// Periodic Hubbard lattice as integrals: -t on each distinct bond, (ii|ii) = U.
+void hubbard_integrals(const int* dims, int ndim, double t, double U, std::vector<double>& h,
+                       std::vector<double>& eri) {
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) L *= dims[i];
+  h.assign((size_t)L * L, 0.0);
+  eri.assign((size_t)L * L * L * L, 0.0);
+  for (auto& bd : lattice_bonds(dims, ndim)) {
+    h[(size_t)bd.first * L + bd.second] = -t;
+    h[(size_t)bd.second * L + bd.first] = -t;
+  }
+  for (int i = 0; i < L; ++i) eri[(((size_t)i * L + i) * L + i) * L + i] = U;
+}
+
+// Neel determinant: alpha on the even-coordinate-sum sublattice (then the
+// rest), beta on the remaining sites (then the alpha sites), ascending.
+void neel_determinant(const int* dims, int ndim, int n_alpha, int n_beta, uint64_t* a0, uint64_t* b0) {
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) L *= dims[i];
+  std::vector<int> even, odd;
+  for (int site = 0; site < L; ++site) {
+    int rem = site, sum = 0;
+    for (int ax = ndim - 1; ax >= 0; --ax) {
+      sum += rem % dims[ax];
+      rem /= dims[ax];
+    }
+    (sum % 2 == 0 ? even : odd).push_back(site);
+  }
+  std::vector<int> order = even;
+  order.insert(order.end(), odd.begin(), odd.end());
+  uint64_t a = 0, b = 0;
+  for (int k = 0; k < n_alpha; ++k) a |= 1ull << order[k];
+  std::vector<int> rest;
+  for (int site = 0; site < L; ++site)
+    if (!((a >> site) & 1)) rest.push_back(site);
+  for (int site = 0; site < L; ++site)
+    if ((a >> site) & 1) rest.push_back(site);
+  for (int k = 0; k < n_beta; ++k) b |= 1ull << rest[k];
+  *a0 = a;
+  *b0 = b;
+}
+
 // device buffers owned by one library call, released when it returns
 // (hipFree waits for the work that uses them)
 struct CallBufs {
@@ -1296,34 +1339,11 @@ int cdfci_init_hubbard(const int* dims, int ndim, double t, double U, int n_alph
   int rc = make_ctx(L, n_alpha, n_beta, opts, out);
   if (rc) return rc;
   cdfci_ctx* c = *out;
-  std::vector<double> h((size_t)L * L, 0.0), eri((size_t)L * L * L * L, 0.0);
-  for (auto& bd : lattice_bonds(dims, ndim)) {
-    h[(size_t)bd.first * L + bd.second] = -t;
-    h[(size_t)bd.second * L + bd.first] = -t;
-  }
-  for (int i = 0; i < L; ++i) eri[(((size_t)i * L + i) * L + i) * L + i] = U;
+  std::vector<double> h, eri;
+  hubbard_integrals(dims, ndim, t, U, h, eri);
   rc = upload(c, h.data(), eri.data());
-  // Neel determinant: alpha on the even-coordinate-sum sublattice (then the
-  // rest), beta on the remaining sites (then the alpha sites), ascending.
-  std::vector<int> even, odd;
-  for (int site = 0; site < L; ++site) {
-    int rem = site, sum = 0;
-    for (int ax = ndim - 1; ax >= 0; --ax) {
-      sum += rem % dims[ax];
-      rem /= dims[ax];
-    }
-    (sum % 2 == 0 ? even : odd).push_back(site);
-  }
-  std::vector<int> order = even;
-  order.insert(order.end(), odd.begin(), odd.end());
   uint64_t a0 = 0, b0 = 0;
-  for (int k = 0; k < n_alpha; ++k) a0 |= 1ull << order[k];
-  std::vector<int> rest;
-  for (int site = 0; site < L; ++site)
-    if (!((a0 >> site) & 1)) rest.push_back(site);
-  for (int site = 0; site < L; ++site)
-    if ((a0 >> site) & 1) rest.push_back(site);
-  for (int k = 0; k < n_beta; ++k) b0 |= 1ull << rest[k];
+  neel_determinant(dims, ndim, n_alpha, n_beta, &a0, &b0);
   int kind = c->opts.init_kind == 1 ? 1 : 2;
   if (!rc) rc = setup_and_init(c, kind, a0, b0);
   if (rc) {
@@ -2233,6 +2253,369 @@ int cdfci_phase_times(cdfci_ctx* c, double* seconds) {
   int khz = 0;
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
   for (int k = 0; k < 4; ++k) seconds[k] = (double)h.t_phase[k] / (1e3 * (double)khz);
+  return 0;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Several low-lying states (xCDFCI, Sec. 3.3): host side.
+
+struct cdfci_xctx {
+  cdfci_ctx* base = nullptr;  // integrals, sizes and stream (no single-state table)
+  int n = 0;
+  double shift = 0.0;
+  XKey* K = nullptr;
+  double* R = nullptr;
+  uint64_t nslots = 0, mask = 0, max_entries = 0;
+  XCtl* x = nullptr;
+  XPartial* parts = nullptr;
+  double* dE = nullptr;
+  int grid = 0, max_parts = 0;
+  int64_t n_col = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool poisoned = false;
+};
+
+namespace {
+
+constexpr int kXSelParts = 4096;
+
+int xctl_read(cdfci_xctx* X, XCtl* h) {
+  hipStream_t s = X->base->stream;
+  HIP_TRY(hipMemcpyAsync(h, X->x, sizeof(XCtl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int xcheck(cdfci_xctx* X, const XCtl& h) {
+  int rc = 0;
+  if ((h.error & kErrTableFull) || h.occupied > X->max_entries) rc = CDFCI_ERR_TABLE_FULL;
+  else if (h.error) rc = CDFCI_ERR_HIP;
+  if (rc) X->poisoned = true;
+  return rc;
+}
+
+__global__ void k_xbegin(XCtl* x) {
+  x->steps_this_call = 0;
+  x->arrive = 0;
+}
+
+int x_launch(cdfci_xctx* X, const XArgs& A) {
+  hipStream_t s = X->base->stream;
+  const dim3 grid(X->grid), block(256);
+  switch (X->n) {
+    case 1: k_xiter<1><<<grid, block, 0, s>>>(A); break;
+    case 2: k_xiter<2><<<grid, block, 0, s>>>(A); break;
+    case 3: k_xiter<3><<<grid, block, 0, s>>>(A); break;
+    case 4: k_xiter<4><<<grid, block, 0, s>>>(A); break;
+    case 5: k_xiter<5><<<grid, block, 0, s>>>(A); break;
+    case 6: k_xiter<6><<<grid, block, 0, s>>>(A); break;
+    case 7: k_xiter<7><<<grid, block, 0, s>>>(A); break;
+    default: k_xiter<8><<<grid, block, 0, s>>>(A); break;
+  }
+  return 0;
+}
+
+// table, control block, C^(0) on the subspace of (a0, b0), B^(0), S, Q and the
+// first coordinate
+int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
+  cdfci_ctx* c = X->base;
+  const cdfci_opts& o = c->opts;
+  const int n = X->n;
+  hipStream_t s = c->stream;
+  X->nslots = o.table_slots;
+  X->mask = X->nslots - 1;
+  X->max_entries = (uint64_t)(o.load_factor * (double)X->nslots);
+  X->n_col = column_count(c->N, c->na, c->nb);
+  X->grid = (int)std::max<int64_t>(1, (X->n_col - 1 + 255) / 256);
+  X->max_parts = std::max(X->grid, kXSelParts);
+  HIP_TRY(hipMalloc(&X->K, X->nslots * sizeof(XKey)));
+  HIP_TRY(hipMalloc(&X->R, X->nslots * 2 * n * sizeof(double)));
+  HIP_TRY(hipMalloc(&X->x, sizeof(XCtl)));
+  HIP_TRY(hipMalloc(&X->parts, X->max_parts * sizeof(XPartial)));
+  HIP_TRY(hipMalloc(&X->dE, kXMax * sizeof(double)));
+  HIP_TRY(hipEventCreate(&X->ev0));
+  HIP_TRY(hipEventCreate(&X->ev1));
+  XCtl h0;
+  memset(&h0, 0, sizeof(h0));
+  h0.n = n;
+  h0.shift = X->shift;
+  h0.islot = -1;
+  HIP_TRY(hipMemcpyAsync(X->x, &h0, sizeof(XCtl), hipMemcpyHostToDevice, s));
+  k_xclear<<<2048, 256, 0, s>>>(X->K, X->R, X->nslots, n);
+  HIP_TRY(hipGetLastError());
+
+  const Ham H = ham_of(c);
+  const int64_t n_col = X->n_col;
+  CallBufs bufs;
+  double *diag, *coef;
+  uint64_t *ka, *kb;
+  XInitTask* tasks;
+  int* d_found;
+  HIP_TRY(bufs.alloc(&diag, n_col));
+  HIP_TRY(bufs.alloc(&ka, n_col));
+  HIP_TRY(bufs.alloc(&kb, n_col));
+  HIP_TRY(bufs.alloc(&tasks, kXMax));
+  HIP_TRY(bufs.alloc(&d_found, 1));
+  HIP_TRY(bufs.alloc(&coef, kXMax * kXMax));
+  const XInitTask d0{a0, b0};
+  double eye[kXMax * kXMax] = {};
+  for (int k = 0; k < n; ++k) eye[k * n + k] = 1.0;
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(tasks, &d0, sizeof(d0), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(coef, eye, sizeof(eye), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_found, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  const int cblocks = (int)((n_col + 255) / 256);
+  k_xconn_diag<<<cblocks, 256, 0, s>>>(H, a0, b0, n_col, diag, ka, kb);
+  k_xconn_rank<<<cblocks, 256, 0, s>>>(diag, ka, kb, n_col, n, tasks, d_found);
+  HIP_TRY(hipGetLastError());
+  int found = 0;
+  HIP_TRY(hipMemcpyAsync(&found, d_found, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (found != n - 1) return CDFCI_ERR_UNSUPPORTED;
+  const int m = n;
+  k_xinit_insert<<<(m + 63) / 64, 64, 0, s>>>(X->K, X->R, X->mask, tasks, coef, m, n, X->x);
+  const int chunks = (int)std::min<int64_t>(cblocks, 1024);
+  k_xinit_scatter<<<dim3(chunks, m), 256, 0, s>>>(H, X->K, X->R, X->mask, tasks, coef, n, n_col, X->shift,
+                                                   X->x);
+  k_xinit_matrices<<<1, 1, 0, s>>>(X->K, X->R, X->mask, tasks, m, n, X->x);
+  const int sel_blocks = (int)std::min<uint64_t>((X->nslots + 255) / 256, (uint64_t)kXSelParts);
+  k_xselect_table<<<sel_blocks, 256, 0, s>>>(X->K, X->R, X->nslots, X->x, X->parts);
+  k_xselect_final<<<1, 1, 0, s>>>(X->parts, sel_blocks, X->x);
+  HIP_TRY(hipGetLastError());
+  XCtl h;
+  int rc = xctl_read(X, &h);
+  if (rc) return rc;
+  rc = xcheck(X, h);
+  if (rc) return rc;
+  if (h.islot < 0) return CDFCI_ERR_INVALID_ARG;
+  return 0;
+}
+
+int x_create(int N, int na, int nb, int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out,
+             cdfci_xctx** X) {
+  if (!out) return CDFCI_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_states < 1 || n_states > kXMax || !std::isfinite(shift)) return CDFCI_ERR_INVALID_ARG;
+  cdfci_ctx* base = nullptr;
+  int rc = make_ctx(N, na, nb, opts, &base);
+  if (rc) return rc;
+  *X = new cdfci_xctx();
+  (*X)->base = base;
+  (*X)->n = n_states;
+  (*X)->shift = shift;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdfci_xfree(cdfci_xctx* X) {
+  if (!X) return 0;
+  if (X->base) {
+    if (X->base->stream) (void)hipStreamSynchronize(X->base->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  void* bufs[] = {X->K, X->R, X->x, X->parts, X->dE};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (X->ev0) (void)hipEventDestroy(X->ev0);
+  if (X->ev1) (void)hipEventDestroy(X->ev1);
+  cdfci_free(X->base);
+  delete X;
+  return 0;
+}
+
+int cdfci_xinit(const double* h, const double* eri, int n_orb, int n_alpha, int n_beta, int n_states,
+                double shift, const cdfci_opts* opts, cdfci_xctx** out) {
+  if (!h || !eri) return CDFCI_ERR_INVALID_ARG;
+  cdfci_xctx* X = nullptr;
+  int rc = x_create(n_orb, n_alpha, n_beta, n_states, shift, opts, out, &X);
+  if (rc) return rc;
+  rc = upload(X->base, h, eri);
+  uint64_t a0 = 0, b0 = 0;
+  if (X->base->opts.init_kind == 2) {  // alternating chain pattern
+    for (int p = 0, k = 0; p < n_orb && k < n_alpha; p += 2, ++k) a0 |= 1ull << p;
+    for (int p = 1, k = 0; p < n_orb && k < n_beta; p += 2, ++k) b0 |= 1ull << p;
+  } else {  // aufbau: the lowest h_pp (ties: the lower index)
+    std::vector<int> order(n_orb);
+    for (int p = 0; p < n_orb; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int p, int q) { return h[(size_t)p * n_orb + p] < h[(size_t)q * n_orb + q]; });
+    for (int k = 0; k < n_alpha; ++k) a0 |= 1ull << order[k];
+    for (int k = 0; k < n_beta; ++k) b0 |= 1ull << order[k];
+  }
+  if (!rc) rc = x_setup(X, a0, b0);
+  if (rc) {
+    cdfci_xfree(X);
+    return rc;
+  }
+  *out = X;
+  return 0;
+}
+
+int cdfci_xinit_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                        int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out) {
+  if (!dims || ndim < 1 || ndim > 3 || !out) return CDFCI_ERR_INVALID_ARG;
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (dims[i] < 1) return CDFCI_ERR_INVALID_ARG;
+    L *= dims[i];
+  }
+  if (L > kMaxOrb) return CDFCI_ERR_UNSUPPORTED;
+  cdfci_xctx* X = nullptr;
+  int rc = x_create(L, n_alpha, n_beta, n_states, shift, opts, out, &X);
+  if (rc) return rc;
+  std::vector<double> h, eri;
+  hubbard_integrals(dims, ndim, t, U, h, eri);
+  rc = upload(X->base, h.data(), eri.data());
+  uint64_t a0 = 0, b0 = 0;
+  neel_determinant(dims, ndim, n_alpha, n_beta, &a0, &b0);
+  if (!rc) rc = x_setup(X, a0, b0);
+  if (rc) {
+    cdfci_xfree(X);
+    return rc;
+  }
+  *out = X;
+  return 0;
+}
+
+int cdfci_xenergies(cdfci_xctx* X, double* energies) {
+  if (!X || !energies) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = X->base->stream;
+  k_xenergies<<<1, 1, 0, s>>>(X->x, X->dE);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(energies, X->dE, X->n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int cdfci_xstep(cdfci_xctx* X, int64_t nsteps, double* energies, uint64_t* sel_alpha, uint64_t* sel_beta,
+                cdfci_stats* out) {
+  if (!X || X->poisoned || nsteps < 0) return CDFCI_ERR_INVALID_ARG;
+  XCtl before;
+  int rc = xctl_read(X, &before);
+  if (rc) return rc;
+  if (before.islot < 0 || (uint64_t)before.islot >= X->nslots) return CDFCI_ERR_INVALID_ARG;
+  const int n = X->n;
+  CallBufs bufs;
+  XArgs A;
+  memset(&A, 0, sizeof(A));
+  double* dE = nullptr;
+  if (energies) {
+    HIP_TRY(bufs.alloc(&A.tr_SQ, (uint64_t)nsteps * 2 * n * n));
+    HIP_TRY(bufs.alloc(&dE, (uint64_t)nsteps * n));
+  }
+  if (sel_alpha) HIP_TRY(bufs.alloc(&A.tr_a, (uint64_t)nsteps));
+  if (sel_beta) HIP_TRY(bufs.alloc(&A.tr_b, (uint64_t)nsteps));
+  A.H = ham_of(X->base);
+  A.K = X->K;
+  A.R = X->R;
+  A.mask = X->mask;
+  A.max_entries = X->max_entries;
+  A.x = X->x;
+  A.parts = X->parts;
+  A.n_col = X->n_col;
+  A.tau = X->base->opts.z_threshold;
+  A.theta = X->base->opts.dx_damping;
+  A.dx_tol = X->base->opts.dx_threshold;
+  hipStream_t s = X->base->stream;
+  k_xbegin<<<1, 1, 0, s>>>(X->x);
+  HIP_TRY(hipEventRecord(X->ev0, s));
+  for (int64_t i = 0; i < nsteps; ++i) x_launch(X, A);
+  HIP_TRY(hipEventRecord(X->ev1, s));
+  HIP_TRY(hipGetLastError());
+  XCtl h;
+  rc = xctl_read(X, &h);
+  if (rc) return rc;
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, X->ev0, X->ev1));
+  const int64_t done = h.steps_this_call;
+  if (energies && done) {
+    k_xtrace_energies<<<(unsigned)((done + 63) / 64), 64, 0, s>>>(A.tr_SQ, done, n, X->shift, dE);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(energies, dE, (size_t)done * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (sel_alpha && done) HIP_TRY(hipMemcpy(sel_alpha, A.tr_a, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  if (sel_beta && done) HIP_TRY(hipMemcpy(sel_beta, A.tr_b, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  rc = xcheck(X, h);
+  if (out) {
+    double E[kXMax];
+    int e = cdfci_xenergies(X, E);
+    if (e) return e;
+    out->steps = done;
+    out->total_steps = h.steps;
+    out->elements = done * X->n_col;
+    out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->occupied = h.occupied;
+    out->max_probe = h.max_probe;
+    out->stopped = h.stopped;
+    out->energy = E[0];
+    out->dx = h.d;
+    double ts = 0.0, tq = 0.0;
+    for (int k = 0; k < n; ++k) {
+      ts += h.S_hi[k * n + k] + h.S_lo[k * n + k];
+      tq += h.Q_hi[k * n + k] + h.Q_lo[k * n + k];
+    }
+    out->mu = ts;
+    out->alpha = tq;
+    out->seconds = ms * 1e-3;
+  }
+  return rc;
+}
+
+int cdfci_xmatrices(cdfci_xctx* X, double* S, double* Q) {
+  if (!X) return CDFCI_ERR_INVALID_ARG;
+  XCtl h;
+  int rc = xctl_read(X, &h);
+  if (rc) return rc;
+  for (int k = 0; k < X->n * X->n; ++k) {
+    if (S) S[k] = h.S_hi[k] + h.S_lo[k];
+    if (Q) Q[k] = h.Q_hi[k] + h.Q_lo[k];
+  }
+  return 0;
+}
+
+int cdfci_xexport(cdfci_xctx* X, uint64_t* keys, double* C, double* B, int64_t cap, int64_t* count) {
+  if (!X || !count || cap < 0) return CDFCI_ERR_INVALID_ARG;
+  XCtl h;
+  int rc = xctl_read(X, &h);
+  if (rc) return rc;
+  const int n = X->n;
+  const int64_t m = (int64_t)std::min<uint64_t>(h.occupied, (uint64_t)cap);
+  CallBufs bufs;
+  uint64_t *da, *db;
+  double *dc, *dbv;
+  unsigned long long* dcount;
+  HIP_TRY(bufs.alloc(&da, m));
+  HIP_TRY(bufs.alloc(&db, m));
+  HIP_TRY(bufs.alloc(&dc, (uint64_t)m * n));
+  HIP_TRY(bufs.alloc(&dbv, (uint64_t)m * n));
+  HIP_TRY(bufs.alloc(&dcount, 1));
+  hipStream_t s = X->base->stream;
+  HIP_TRY(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), s));
+  k_xexport<<<1024, 256, 0, s>>>(X->K, X->R, X->nslots, n, da, db, dc, dbv, m, dcount);
+  HIP_TRY(hipGetLastError());
+  unsigned long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, dcount, sizeof(total), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *count = (int64_t)total;
+  const int64_t w = std::min<int64_t>((int64_t)total, m);
+  if (w > 0) {
+    std::vector<uint64_t> ha(w), hb(w);
+    HIP_TRY(hipMemcpy(ha.data(), da, w * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hb.data(), db, w * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (keys)
+      for (int64_t i = 0; i < w; ++i) {
+        keys[2 * i] = ha[i];
+        keys[2 * i + 1] = hb[i];
+      }
+    if (C) HIP_TRY(hipMemcpy(C, dc, (size_t)w * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (B) HIP_TRY(hipMemcpy(B, dbv, (size_t)w * n * sizeof(double), hipMemcpyDeviceToHost));
+  }
   return 0;
 }
 

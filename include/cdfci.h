@@ -320,6 +320,21 @@ int cdfci_xexport(cdfci_xctx* x, uint64_t* keys, double* C, double* B, int64_t c
 
 int cdfci_xfree(cdfci_xctx* x);
 
+/* ---- FCIDUMP input (Sec. 4.1.1) ---------------------------------------------
+ * Read a FCIDUMP file (namelist header "&FCI NORB=, NELEC=, MS2=, ..." closed
+ * by "&END" or "/", then lines "value i j k l" with 1-based indices: (ij|kl)
+ * for i,j,k,l > 0, h_ij for k = l = 0, the core energy for all zero; lines
+ * with only i > 0 are ignored).  Host code only, no device work.
+ * n_alpha = (NELEC + MS2) / 2, n_beta = (NELEC - MS2) / 2.  Integrals with
+ * |value| < threshold are dropped (the paper's integral truncation; the core
+ * energy is always kept).  h (n_orb^2), eri (n_orb^4, chemist, all 8 images
+ * filled) and ecore are host buffers the caller sizes from a first call with
+ * all three NULL, which reads the header only.  CDFCI_ERR_INVALID_ARG for an
+ * unreadable file or a malformed header or line, CDFCI_ERR_UNSUPPORTED for
+ * NORB > 63. */
+int cdfci_read_fcidump(const char* path, double threshold, int* n_orb, int* n_alpha, int* n_beta, double* h,
+                       double* eri, double* ecore);
+
 const char* cdfci_strerror(int code);
 const char* cdfci_last_error(void);
 

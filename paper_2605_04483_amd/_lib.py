@@ -144,6 +144,9 @@ SIGNATURES = [
     ("cdfci_xmatrices", ctypes.c_int, [_P, _DP, _DP]),
     ("cdfci_xexport", ctypes.c_int, [_P, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_xfree", ctypes.c_int, [_P]),
+    ("cdfci_read_fcidump", ctypes.c_int,
+     [ctypes.c_char_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+      ctypes.POINTER(ctypes.c_int), _DP, _DP, _DP]),
     ("cdfci_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cdfci_last_error", ctypes.c_char_p, []),
 ]

@@ -440,3 +440,21 @@ def cdfci_xexport(x):
 
 def cdfci_xfree(x):
     x.close()
+
+
+# ---------------------------------------------------------------- FCIDUMP input
+
+def read_fcidump(path, threshold=0.0):
+    """Returns (h [N, N], eri [N, N, N, N] chemist, n_alpha, n_beta, ecore)."""
+    L = _lib.load()
+    N, na, nb = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    p = str(path).encode()
+    _check(L.cdfci_read_fcidump(p, float(threshold), ctypes.byref(N), ctypes.byref(na), ctypes.byref(nb),
+                                None, None, None), "cdfci_read_fcidump")
+    n = N.value
+    h = np.zeros((n, n))
+    eri = np.zeros((n, n, n, n))
+    ecore = ctypes.c_double(0.0)
+    _check(L.cdfci_read_fcidump(p, float(threshold), ctypes.byref(N), ctypes.byref(na), ctypes.byref(nb),
+                                _dp(h), _dp(eri), ctypes.byref(ecore)), "cdfci_read_fcidump")
+    return h, eri, na.value, nb.value, ecore.value

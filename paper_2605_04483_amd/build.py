@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcdfci.so")
-SOURCES = [os.path.join(HERE, "csrc", "cdfci.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "cdfci.hip"), os.path.join(HERE, "csrc", "fcidump.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   __shared__ double s_S[NN];  // S before the step, then after it
   __shared__ double s_v[3 * NS];  // C_i, B_i, g
   __shared__ unsigned long long s_ins, s_tot;
-  __shared__ int s_err;
+  __shared__ int s_err, s_probe;
   XCtl* X = A.x;
   if (X->error || X->stopped) return;  // the same in every workgroup
   const Ham H = A.H;
@@ -310,6 +310,7 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   if (tid == 0) {
     s_ins = 0;
     s_err = 0;
+    s_probe = 0;
   }
   make_lists_block(ia, ib, H.N, L);
   __syncthreads();
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   }
   if (my_ins) atomicAdd(&s_ins, (unsigned long long)my_ins);
   if (err) atomicOr(&s_err, err);
-  if (my_probe) atomicMax(&X->max_probe, my_probe);
+  if (my_probe) atomicMax(&s_probe, my_probe);
   const XCand wb = xblock_argmax(best, s_c);
   xblock_sums<NS>(rec, s_red);
   if (tid == 0) {
@@ -435,6 +436,7 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
     for (int k = 0; k < NS; ++k) st_co(&P->rec[k], rec[k]);
     st_co(&P->inserts, (int64_t)s_ins);
     st_co(&P->err, (int64_t)s_err);
+    if (s_probe) atomicMax(&X->max_probe, s_probe);
     s_tot = 0;
   }
   if (!last_workgroup(&X->arrive)) return;

@@ -171,6 +171,42 @@ int cdfci_export(cdfci_ctx* ctx, int64_t top_n, uint64_t* keys, double* c, doubl
  * barrier, [3] combining the partial results.  seconds: 4 doubles. */
 int cdfci_phase_times(cdfci_ctx* ctx, double* seconds);
 
+/* Restart (Sec. 4.1.3: checkpoints for termination and restart from stored
+ * wavefunctions).  Replaces the context's state by the wavefunction
+ * c = sum_i cv[i] e_{key i}: keys 2*count uint64 (alpha, beta) and cv count
+ * doubles, host, as cdfci_export writes them (entries with c = 0 may be
+ * left out).  The table is cleared, the entries stored, and b = H c rebuilt:
+ * the stored set is the given entries plus every determinant j with some
+ * |H_ji c_i| >= z_threshold (every connected one when it is 0), and each
+ * stored b_j is the full sum over the given entries.  mu = c.c and
+ * alpha = c.b are recomputed in double-double, the iteration count and the
+ * damped accumulator restart from zero, and the first coordinate is the
+ * stored entry of largest |4 b_j + 4 mu c_j| (as after init).  A context
+ * left by CDFCI_ERR_TABLE_FULL may be reloaded.  CDFCI_ERR_INVALID_ARG for a
+ * key outside the context's orbitals or electron counts, a repeated key, a
+ * non-finite coefficient or an all-zero c; CDFCI_ERR_TABLE_FULL if the set
+ * does not fit. */
+int cdfci_load(cdfci_ctx* ctx, const uint64_t* keys, const double* cv, int64_t count);
+
+/* Set the compression threshold tau of later steps and loads (Sec. 3.1). */
+int cdfci_set_threshold(cdfci_ctx* ctx, double tau);
+
+/* Single-coordinate iterations within a memory budget (the z_threshold_search
+ * option of the paper's solver input, Sec. 4.3).  Steps run in chunks of
+ * `chunk` iterations, fewer if needed so that one chunk cannot add more than
+ * the (1 - fill) share of the limit (an iteration stores at most one column);
+ * when the stored entries exceed fill * load_factor * table_slots after a
+ * chunk, the entries with c != 0 are kept, tau becomes
+ * tau0 (if it was 0) or tau * growth, and the state is rebuilt from them by
+ * cdfci_load, raising tau again until the rebuilt set fits.  Stops after
+ * nsteps iterations or at dx_threshold.  *tau_out (may be NULL) gets the final
+ * tau; out (may be NULL) sums steps, elements, inserts and seconds over the
+ * call, the other fields are those after the last chunk.  fill in (0, 1],
+ * growth > 1, tau0 > 0; CDFCI_ERR_TABLE_FULL if even tau > 1e3 leaves too
+ * many entries. */
+int cdfci_step_search(cdfci_ctx* ctx, int64_t nsteps, int64_t chunk, double fill, double growth, double tau0,
+                      double* tau_out, cdfci_stats* out);
+
 int cdfci_free(cdfci_ctx* ctx);
 
 /* ---- Batches of periodic Hubbard lattices (Sec. 2.2, Alg. 1) ----------------

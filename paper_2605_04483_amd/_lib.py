@@ -120,6 +120,10 @@ SIGNATURES = [
     ("cdfci_entry", ctypes.c_int, [_P, _UP, _UP, _DP]),
     ("cdfci_export", ctypes.c_int, [_P, ctypes.c_int64, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_phase_times", ctypes.c_int, [_P, _DP]),
+    ("cdfci_load", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64]),
+    ("cdfci_set_threshold", ctypes.c_int, [_P, ctypes.c_double]),
+    ("cdfci_step_search", ctypes.c_int,
+     [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _DP, _STP]),
     ("cdfci_free", ctypes.c_int, [_P]),
     ("cdfci_init_hubbard_batch", ctypes.c_int,
      [ctypes.POINTER(cdfci_hubbard_spec), ctypes.c_int, ctypes.POINTER(cdfci_batch_opts), _CTXP]),

@@ -201,6 +201,29 @@ def cdfci_export(ctx, top_n=0):
     return keys[0:2 * n:2].copy(), keys[1:2 * n:2].copy(), c[:n], b[:n]
 
 
+def cdfci_load(ctx, keys_alpha, keys_beta, c):
+    """Restart from a stored wavefunction (keys and c as cdfci_export returns)."""
+    ka = np.asarray(keys_alpha, dtype=np.uint64)
+    kb = np.asarray(keys_beta, dtype=np.uint64)
+    keys = np.ascontiguousarray(np.stack([ka, kb], axis=1).reshape(-1))
+    cv = np.ascontiguousarray(c, dtype=np.float64)
+    assert len(ka) == len(kb) == len(cv)
+    _check(_lib.load().cdfci_load(ctx.handle, _up(keys), _dp(cv), len(cv)), "cdfci_load")
+
+
+def cdfci_set_threshold(ctx, tau):
+    _check(_lib.load().cdfci_set_threshold(ctx.handle, float(tau)), "cdfci_set_threshold")
+
+
+def cdfci_step_search(ctx, nsteps, chunk=10000, fill=0.9, growth=10.0, tau0=1e-6):
+    """Returns (stats, final tau)."""
+    st = cdfci_stats()
+    tau = ctypes.c_double(0.0)
+    _check(_lib.load().cdfci_step_search(ctx.handle, int(nsteps), int(chunk), float(fill), float(growth),
+                                         float(tau0), ctypes.byref(tau), ctypes.byref(st)), "cdfci_step_search")
+    return st.as_dict(), tau.value
+
+
 def cdfci_phase_times(ctx):
     t = np.zeros(4)
     _check(_lib.load().cdfci_phase_times(ctx.handle, _dp(t)), "cdfci_phase_times")

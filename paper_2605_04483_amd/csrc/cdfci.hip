@@ -582,6 +582,107 @@ __global__ void k_init_scalars(const Slot* T, uint64_t mask, const InitTask* tas
   ctl->energy = dd_val(al) / dd_val(mu);
 }
 
+// Restart from a stored wavefunction: the given entries into a cleared
+// table (a key met twice is counted in *dup), then b = H c over the column of
+// every entry.  With tau > 0 the stored set is the support plus every j with
+// some |H_ji c_i| >= tau (pass 0 stores them), and b_j is then summed over
+// all contributions (pass 1): exact on the stored set, as the compression
+// rule of Sec. 3.1 keeps it for entries with c_j != 0.
+__global__ void k_load_insert(Slot* T, uint64_t mask, const InitTask* tasks, int64_t n, Ctl* ctl,
+                              unsigned long long* dup) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int ins = 0, probes = 0, err = 0;
+  SlotVal v0;
+  const int64_t s = table_upsert(T, mask, tasks[i].a, tasks[i].b, &ins, &probes, &err, &v0);
+  if (s < 0) {
+    atomicOr(&ctl->error, err ? err : kErrTableFull);
+    return;
+  }
+  if (!ins) {
+    atomicAdd(dup, 1ull);
+    return;
+  }
+  st_co(&T[s].c, tasks[i].coef);
+  atomicAdd(&ctl->occupied, 1ull);
+  atomicAdd(&ctl->inserts, 1ull);
+}
+
+// grid: (chunks, n tasks); pass 0 stores, pass 1 accumulates
+__global__ void __launch_bounds__(256) k_load_scatter(Ham H, Slot* T, uint64_t mask, const InitTask* tasks,
+                                                      int64_t n_col, Ctl* ctl, double tau, int pass) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  const InitTask t = tasks[blockIdx.y];
+  if (threadIdx.x == 0) {
+    make_lists_serial(t.a, t.b, H.N, L);
+    s_diag = diag_serial(H, L);
+  }
+  __syncthreads();
+  unsigned long long ins_cnt = 0;
+  int err = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_col;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ja, jb;
+    const double Hj = column_entry(H, L, t.a, t.b, e, s_diag, &ja, &jb);
+    const double v = t.coef * Hj;
+    if (v == 0.0) continue;
+    int probes = 0;
+    SlotVal vj;
+    if (pass == 0) {
+      if (fabs(v) < tau) continue;
+      int ins = 0;
+      if (table_upsert(T, mask, ja, jb, &ins, &probes, &err, &vj) < 0) break;
+      ins_cnt += ins;
+    } else {
+      const int64_t sl = table_find(T, mask, ja, jb, &probes, &vj);
+      if (sl >= 0) atomic_add_f64(&T[sl].b, v);
+    }
+  }
+  if (err) atomicOr(&ctl->error, err);
+  if (ins_cnt) {
+    atomicAdd(&ctl->occupied, ins_cnt);
+    atomicAdd(&ctl->inserts, ins_cnt);
+  }
+}
+
+// mu = sum c^2 and alpha = sum c b over every stored entry: per-workgroup
+// double-double sums (part[4 * block] = mu hi, lo, alpha hi, lo), then one
+// thread over the workgroups in order
+__global__ void __launch_bounds__(256) k_table_scalars(const Slot* T, uint64_t nslots, double* part) {
+  __shared__ double s_red[4];
+  dd mu{0.0, 0.0}, al{0.0, 0.0};
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    if (T[s].ka == kEmpty) continue;
+    const double c = T[s].c, b = T[s].b;
+    mu = dd_add(mu, two_prod(c, c));
+    al = dd_add(al, two_prod(c, b));
+  }
+  const dd m = wg_sum_dd(mu, s_red);
+  const dd a = wg_sum_dd(al, s_red);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = m.hi;
+    part[4 * blockIdx.x + 1] = m.lo;
+    part[4 * blockIdx.x + 2] = a.hi;
+    part[4 * blockIdx.x + 3] = a.lo;
+  }
+}
+
+__global__ void k_table_scalars_final(const double* part, int nb, Ctl* ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  dd mu{0.0, 0.0}, al{0.0, 0.0};
+  for (int i = 0; i < nb; ++i) {
+    mu = dd_add(mu, dd{part[4 * i], part[4 * i + 1]});
+    al = dd_add(al, dd{part[4 * i + 2], part[4 * i + 3]});
+  }
+  ctl->mu_hi = mu.hi;
+  ctl->mu_lo = mu.lo;
+  ctl->al_hi = al.hi;
+  ctl->al_lo = al.lo;
+  ctl->energy = dd_val(al) / dd_val(mu);
+}
+
 // argmax of |4b + 4 mu c| over every stored entry (used once after init)
 __global__ void __launch_bounds__(256) k_select_table(const Slot* T, uint64_t nslots, Ctl* ctl, Partial* parts) {
   __shared__ Cand s_cand[kMaxWaves];
@@ -1824,6 +1925,137 @@ int cdfci_export(cdfci_ctx* c, int64_t top_n, uint64_t* keys, double* cv, double
     (void)hipFree(dk);
     (void)hipFree(dc);
     (void)hipFree(db);
+  }
+  return 0;
+}
+
+int cdfci_load(cdfci_ctx* c, const uint64_t* keys, const double* cv, int64_t count) {
+  if (!c || !keys || !cv || count < 1) return CDFCI_ERR_INVALID_ARG;
+  if ((uint64_t)count > c->max_entries) return CDFCI_ERR_TABLE_FULL;
+  const uint64_t valid = c->N == 64 ? ~0ull : ((1ull << c->N) - 1);
+  std::vector<InitTask> tasks((size_t)count);
+  bool any = false;
+  for (int64_t i = 0; i < count; ++i) {
+    const uint64_t a = keys[2 * i], b = keys[2 * i + 1];
+    if ((a & ~valid) || (b & ~valid) || __builtin_popcountll(a) != c->na || __builtin_popcountll(b) != c->nb ||
+        !std::isfinite(cv[i]))
+      return CDFCI_ERR_INVALID_ARG;
+    any = any || cv[i] != 0.0;
+    tasks[i] = InitTask{a, b, cv[i]};
+  }
+  if (!any) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = c->stream;
+  if (c->mode == 1) {  // the multicoordinate scale no longer applies
+    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
+    c->mode = 0;
+  }
+  CallBufs bufs;
+  InitTask* d_tasks;
+  unsigned long long* d_dup;
+  HIP_TRY(bufs.alloc(&d_tasks, (uint64_t)count));
+  HIP_TRY(bufs.alloc(&d_dup, 1));
+  HIP_TRY(hipMemcpyAsync(d_tasks, tasks.data(), count * sizeof(InitTask), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(d_dup, 0, sizeof(unsigned long long), s));
+  k_zero_ctl<<<1, 1, 0, s>>>(c->ctl);
+  k_clear_table<<<2048, 256, 0, s>>>(c->T, c->nslots);
+  k_load_insert<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(c->T, c->mask, d_tasks, count, c->ctl, d_dup);
+  // one workgroup per (column chunk, determinant), at most 65535 determinants a launch
+  const Ham H = ham_of(c);
+  const int chunks = (int)std::min<int64_t>((c->n_col + 255) / 256, count > 4096 ? 8 : 256);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t off = 0; off < count; off += 65535) {
+      const int nb = (int)std::min<int64_t>(65535, count - off);
+      k_load_scatter<<<dim3(chunks, nb), 256, 0, s>>>(H, c->T, c->mask, d_tasks + off, c->n_col, c->ctl,
+                                                      c->opts.z_threshold, pass);
+    }
+  const int sb = 1024;
+  k_table_scalars<<<sb, 256, 0, s>>>(c->T, c->nslots, c->dscratch);
+  k_table_scalars_final<<<1, 1, 0, s>>>(c->dscratch, sb, c->ctl);
+  const int sel_blocks = (int)std::min<uint64_t>((c->nslots + 255) / 256, (uint64_t)c->max_parts);
+  k_select_table<<<sel_blocks, 256, 0, s>>>(c->T, c->nslots, c->ctl, c->parts);
+  k_select_final<<<1, 1, 0, s>>>(c->parts, sel_blocks, c->ctl);
+  HIP_TRY(hipGetLastError());
+  unsigned long long dup = 0;
+  HIP_TRY(hipMemcpyAsync(&dup, d_dup, sizeof(dup), hipMemcpyDeviceToHost, s));
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  c->poisoned = false;
+  rc = check_error(c, h);
+  if (rc) return rc;
+  if (dup) {
+    c->poisoned = true;
+    return CDFCI_ERR_INVALID_ARG;
+  }
+  return 0;
+}
+
+int cdfci_set_threshold(cdfci_ctx* c, double tau) {
+  if (!c || !(tau >= 0.0) || !std::isfinite(tau)) return CDFCI_ERR_INVALID_ARG;
+  c->opts.z_threshold = tau;
+  return 0;
+}
+
+int cdfci_step_search(cdfci_ctx* c, int64_t nsteps, int64_t chunk, double fill, double growth, double tau0,
+                      double* tau_out, cdfci_stats* out) {
+  if (!c || nsteps < 0 || chunk < 1 || !(fill > 0.0 && fill <= 1.0) || !(growth > 1.0) || !(tau0 > 0.0))
+    return CDFCI_ERR_INVALID_ARG;
+  cdfci_stats acc;
+  memset(&acc, 0, sizeof(acc));
+  double seconds = 0.0;
+  int64_t done = 0, elements = 0, inserts = 0;
+  int rc = 0;
+  const double limit = fill * (double)c->max_entries;
+  // one iteration stores at most a column's worth of new entries, so a chunk
+  // started below the budget cannot pass the table's own limit
+  const int64_t safe = std::max<int64_t>(1, (int64_t)(((double)c->max_entries - limit) / (double)c->n_col));
+  chunk = std::min(chunk, safe);
+  while (done < nsteps) {
+    cdfci_stats st;
+    rc = cdfci_step(c, 1, std::min(chunk, nsteps - done), &st);
+    if (rc) return rc;
+    done += st.steps;
+    seconds += st.seconds;
+    elements += st.elements;
+    inserts += st.inserts;
+    acc = st;
+    if (st.stopped || st.steps == 0) break;
+    if ((double)st.occupied <= limit) continue;
+    // over budget: keep the support, raise tau, rebuild b on the smaller set
+    int64_t n = 0;
+    rc = cdfci_export(c, 0, nullptr, nullptr, nullptr, 0, &n);
+    if (rc) return rc;
+    std::vector<uint64_t> keys(2 * (size_t)n);
+    std::vector<double> cv((size_t)n), bv((size_t)n);
+    rc = cdfci_export(c, 0, keys.data(), cv.data(), bv.data(), n, &n);
+    if (rc) return rc;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (cv[i] != 0.0) {
+        keys[2 * m] = keys[2 * i];
+        keys[2 * m + 1] = keys[2 * i + 1];
+        cv[m++] = cv[i];
+      }
+    for (;;) {
+      c->opts.z_threshold = c->opts.z_threshold > 0.0 ? c->opts.z_threshold * growth : tau0;
+      rc = cdfci_load(c, keys.data(), cv.data(), m);
+      if (rc && rc != CDFCI_ERR_TABLE_FULL) return rc;
+      Ctl h;
+      if (!rc) {
+        rc = ctl_read(c, &h);
+        if (rc) return rc;
+        if ((double)h.occupied <= limit) break;
+      }
+      if (c->opts.z_threshold > 1e3) return CDFCI_ERR_TABLE_FULL;  // the support alone does not fit
+    }
+  }
+  if (tau_out) *tau_out = c->opts.z_threshold;
+  if (out) {
+    *out = acc;
+    out->steps = done;
+    out->elements = elements;
+    out->inserts = inserts;
+    out->seconds = seconds;
   }
   return 0;
 }

@@ -356,6 +356,50 @@ int cdfci_xexport(cdfci_xctx* x, uint64_t* keys, double* C, double* B, int64_t c
 
 int cdfci_xfree(cdfci_xctx* x);
 
+/* ---- Orbital optimisation: OptOrbFCI (Sec. 3.4, Alg. 4) ---------------------
+ * Chooses N orbitals out of M (the columns of U, M x N, U^T U = I) that
+ * minimise the FCI ground energy in the N-orbital space.  Outer iteration l:
+ * integrals in the current orbitals (h' = U^T h U, four-index transform of
+ * (pq|rs) on the device), the FCI ground state by coordinate descent
+ * (cdfci_init + cdfci_step with k coordinates per step, then
+ * cdfci_rdm_backward for the 1- and 2-RDM of the top_n support), energy
+ * E^(l) = sum h' gamma + 1/2 sum (pq|rs)' Gamma, then the orbital problem of
+ * eq. (subopt) with the RDMs fixed, P4(U), by projected steps
+ * U <- orth(U - t_k grad P4(U)) (eq. (projBB)): orth the polar factor,
+ * grad the Euclidean gradient, t_0 = step0 and then Barzilai-Borwein sizes
+ * <s,s>/|<s,y>| and |<s,y>|/<y,y> in turn (s, y: differences of U and of
+ * grad).  The orbital problem stops at a Riemannian gradient norm
+ * <= grad_tol or after max_inner steps and keeps its iterate of lowest P4;
+ * the outer loop stops when |E^(l) - E^(l-1)| <= energy_tol (a negative
+ * value: never) or after max_outer solves. */
+typedef struct {
+  int n_active;            /* N: orbitals of the FCI space, 1..min(M, 63) */
+  int max_outer;           /* FCI solves at most; 0 = 20 */
+  int max_inner;           /* projected steps per orbital problem at most; 0 = 100 */
+  int k;                   /* coordinates per CD step of each solve (1..1024); 0 = 1 */
+  int have_u;              /* 1: U holds the start (orthonormalised first); 0: the identity
+                              columns of the N orbitals of lowest h_pp, in orbital order */
+  int reserved;
+  int64_t cd_steps;        /* CD iterations per solve at most; 0 = 10^6 */
+  double cd_dx_threshold;  /* stopping rule of each solve (Sec. 4.1.3); 0 = 1e-10 */
+  double energy_tol;       /* 0 = 1e-8 */
+  double grad_tol;         /* 0 = 1e-8 */
+  double step0;            /* 0 = 1e-2 */
+  double z_threshold;      /* tau of the solves */
+  uint64_t table_slots;    /* per solve; 0 = 2^22 */
+  int64_t top_n;           /* RDM support (0: every c != 0) */
+  void* stream;            /* hipStream_t; NULL = default stream */
+} cdfci_optorb_opts;
+
+/* h (M x M), eri (M^4, chemist, 8-fold symmetric): host.  U: host M x N
+ * row-major, the start when have_u, on return the orbitals of the last
+ * solve.  energies and p4_values (may be NULL): host, max_outer doubles;
+ * energies[l] = E^(l), p4_values[l] = P4 at the end of orbital problem l
+ * (an upper bound of E^(l+1)).  *n_outer = solves done.  Errors of the
+ * solves are passed on. */
+int cdfci_optorb(const double* h, const double* eri, int n_basis, int n_alpha, int n_beta,
+                 const cdfci_optorb_opts* opts, double* U, double* energies, double* p4_values, int* n_outer);
+
 /* ---- FCIDUMP input (Sec. 4.1.1) ---------------------------------------------
  * Read a FCIDUMP file (namelist header "&FCI NORB=, NELEC=, MS2=, ..." closed
  * by "&END" or "/", then lines "value i j k l" with 1-based indices: (ij|kl)

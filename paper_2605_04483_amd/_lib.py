@@ -95,6 +95,26 @@ class cdfci_batch_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cdfci_optorb_opts(ctypes.Structure):
+    _fields_ = [
+        ("n_active", ctypes.c_int),
+        ("max_outer", ctypes.c_int),
+        ("max_inner", ctypes.c_int),
+        ("k", ctypes.c_int),
+        ("have_u", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+        ("cd_steps", ctypes.c_int64),
+        ("cd_dx_threshold", ctypes.c_double),
+        ("energy_tol", ctypes.c_double),
+        ("grad_tol", ctypes.c_double),
+        ("step0", ctypes.c_double),
+        ("z_threshold", ctypes.c_double),
+        ("table_slots", ctypes.c_uint64),
+        ("top_n", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 # (name, restype, argtypes) for every exported symbol of include/cdfci.h
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -148,6 +168,9 @@ SIGNATURES = [
     ("cdfci_xmatrices", ctypes.c_int, [_P, _DP, _DP]),
     ("cdfci_xexport", ctypes.c_int, [_P, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_xfree", ctypes.c_int, [_P]),
+    ("cdfci_optorb", ctypes.c_int,
+     [_DP, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(cdfci_optorb_opts), _DP, _DP, _DP,
+      ctypes.POINTER(ctypes.c_int)]),
     ("cdfci_read_fcidump", ctypes.c_int,
      [ctypes.c_char_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
       ctypes.POINTER(ctypes.c_int), _DP, _DP, _DP]),

@@ -481,3 +481,40 @@ def read_fcidump(path, threshold=0.0):
     _check(L.cdfci_read_fcidump(p, float(threshold), ctypes.byref(N), ctypes.byref(na), ctypes.byref(nb),
                                 _dp(h), _dp(eri), ctypes.byref(ecore)), "cdfci_read_fcidump")
     return h, eri, na.value, nb.value, ecore.value
+
+
+# ---------------------------------------------------------------- orbital optimisation (OptOrbFCI)
+
+def cdfci_optorb(h, eri, n_active, n_alpha, n_beta, U0=None, max_outer=20, max_inner=100, k=1,
+                 cd_steps=1000000, cd_dx_threshold=1e-10, energy_tol=1e-8, grad_tol=1e-8, step0=1e-2,
+                 z_threshold=0.0, table_slots=1 << 22, top_n=0):
+    """Returns (energies E^(l), final U [M, N], P4 values of the orbital problems)."""
+    L = _lib.load()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    M = h.shape[0]
+    o = _lib.cdfci_optorb_opts()
+    o.n_active = int(n_active)
+    o.max_outer = int(max_outer)
+    o.max_inner = int(max_inner)
+    o.k = int(k)
+    o.have_u = 0 if U0 is None else 1
+    o.cd_steps = int(cd_steps)
+    o.cd_dx_threshold = float(cd_dx_threshold)
+    o.energy_tol = float(energy_tol)
+    o.grad_tol = float(grad_tol)
+    o.step0 = float(step0)
+    o.z_threshold = float(z_threshold)
+    o.table_slots = int(table_slots)
+    o.top_n = int(top_n)
+    import torch
+
+    o.stream = ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+    U = np.zeros((M, int(n_active))) if U0 is None else np.array(U0, dtype=np.float64)
+    U = np.ascontiguousarray(U)
+    E = np.zeros(max(1, int(max_outer)))
+    P = np.zeros(max(1, int(max_outer)))
+    n = ctypes.c_int(0)
+    _check(L.cdfci_optorb(_dp(h), _dp(eri), M, int(n_alpha), int(n_beta), ctypes.byref(o), _dp(U), _dp(E), _dp(P),
+                          ctypes.byref(n)), "cdfci_optorb")
+    return E[:n.value], U, P[:max(0, n.value - 1)]

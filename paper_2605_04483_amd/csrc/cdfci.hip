@@ -989,6 +989,7 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
 #include "rdm_kernels.h"
 #include "hub_kernels.h"
 #include "xcd_kernels.h"
+#include "orb_kernels.h"
 
 // per-instance step budget of the coming batch call (traced: only instance
 // `only` advances)
@@ -2852,3 +2853,336 @@ int cdfci_xexport(cdfci_xctx* X, uint64_t* keys, double* C, double* B, int64_t c
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// OptOrbFCI (Sec. 3.4, Alg. 4): host side.  The FCI solves are ordinary
+// contexts (cdfci_init, cdfci_step, cdfci_rdm_backward); the four-index
+// transforms, P4 and its two-body gradient run on the device; the N x N
+// algebra of the projected steps (polar factor) stays on the host.
+
+namespace {
+
+// eigenvalues w and eigenvectors (columns of V) of the symmetric n x n A by
+// cyclic Jacobi
+void host_sym_eig(std::vector<double> A, int n, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * akp - s * akq;
+          A[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * apk - s * aqk;
+          A[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+// polar factor X (X^T X)^(-1/2) of the M x N matrix X (row-major)
+bool host_orth(const std::vector<double>& X, int M, int N, std::vector<double>& out) {
+  std::vector<double> G((size_t)N * N, 0.0), w, V;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < M; ++a) s += X[(size_t)a * N + i] * X[(size_t)a * N + j];
+      G[(size_t)i * N + j] = s;
+    }
+  host_sym_eig(G, N, w, V);
+  std::vector<double> R((size_t)N * N, 0.0);  // (X^T X)^(-1/2)
+  for (int k = 0; k < N; ++k) {
+    if (!(w[k] > 0.0)) return false;
+    const double f = 1.0 / std::sqrt(w[k]);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) R[(size_t)i * N + j] += V[(size_t)i * N + k] * f * V[(size_t)j * N + k];
+  }
+  out.assign((size_t)M * N, 0.0);
+  for (int a = 0; a < M; ++a)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < N; ++i) s += X[(size_t)a * N + i] * R[(size_t)i * N + j];
+      out[(size_t)a * N + j] = s;
+    }
+  return true;
+}
+
+struct OrbWork {
+  int M = 0, N = 0;
+  hipStream_t s = nullptr;
+  CallBufs bufs;
+  double *eri = nullptr, *U = nullptr, *t1 = nullptr, *t2 = nullptr, *W = nullptr, *eri2 = nullptr;
+  double *Gs = nullptr, *grad2 = nullptr, *part = nullptr;
+  std::vector<double> h, g1;  // M x M; N x N (gamma)
+  std::vector<double> G2;     // Gamma (N^4), as the reverse pass returns it
+};
+
+constexpr int kOrbDotBlocks = 256;
+
+// W = eri with positions 1..3 rotated (M x N^3), then eri' (N^4) into w.eri2
+int orb_transform(OrbWork& w) {
+  const int M = w.M, N = w.N;
+  auto launch = [&](const double* in, double* out, int d0, int d1, int d2, int d3, int pos) {
+    int64_t tot = (int64_t)d0 * d1 * d2 * d3 / (pos == 0 ? d0 : pos == 1 ? d1 : pos == 2 ? d2 : d3) * N;
+    k_orb_contract<<<(unsigned)((tot + 255) / 256), 256, 0, w.s>>>(in, out, w.U, M, N, d0, d1, d2, d3, pos);
+  };
+  launch(w.eri, w.t1, M, M, M, M, 1);  // M N M M
+  launch(w.t1, w.t2, M, N, M, M, 2);   // M N N M
+  launch(w.t2, w.W, M, N, N, M, 3);    // M N N N
+  launch(w.W, w.eri2, M, N, N, N, 0);  // N N N N
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// P4(U) and its gradient (M x N) for the U already on the device
+int orb_eval(OrbWork& w, const std::vector<double>& U, double* value, std::vector<double>& grad) {
+  const int M = w.M, N = w.N;
+  HIP_TRY(hipMemcpyAsync(w.U, U.data(), (size_t)M * N * sizeof(double), hipMemcpyHostToDevice, w.s));
+  int rc = orb_transform(w);
+  if (rc) return rc;
+  const int64_t n4 = (int64_t)N * N * N * N;
+  k_orb_dot<<<kOrbDotBlocks, 256, 0, w.s>>>(w.eri2, w.Gs, n4, w.part);
+  k_orb_grad2<<<(unsigned)(M * N), 256, 0, w.s>>>(w.W, w.Gs, M, N, w.grad2);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> part(kOrbDotBlocks);
+  grad.assign((size_t)M * N, 0.0);
+  HIP_TRY(hipMemcpyAsync(part.data(), w.part, kOrbDotBlocks * sizeof(double), hipMemcpyDeviceToHost, w.s));
+  HIP_TRY(hipMemcpyAsync(grad.data(), w.grad2, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost, w.s));
+  HIP_TRY(hipStreamSynchronize(w.s));
+  double two = 0.0;
+  for (double p : part) two += p;
+  // one-body part: h' = U^T h U against gamma, gradient h U (gamma + gamma^T)
+  std::vector<double> hU((size_t)M * N, 0.0);
+  for (int a = 0; a < M; ++a)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int b = 0; b < M; ++b) s += w.h[(size_t)a * M + b] * U[(size_t)b * N + j];
+      hU[(size_t)a * N + j] = s;
+    }
+  double one = 0.0;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double hij = 0.0;
+      for (int a = 0; a < M; ++a) hij += U[(size_t)a * N + i] * hU[(size_t)a * N + j];
+      one += hij * w.g1[(size_t)i * N + j];
+    }
+  for (int a = 0; a < M; ++a)
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < N; ++j) s += hU[(size_t)a * N + j] * (w.g1[(size_t)j * N + i] + w.g1[(size_t)i * N + j]);
+      grad[(size_t)a * N + i] += s;
+    }
+  *value = one + 0.5 * two;
+  return 0;
+}
+
+double frob_dot(const std::vector<double>& x, const std::vector<double>& y) {
+  double s = 0.0;
+  for (size_t k = 0; k < x.size(); ++k) s += x[k] * y[k];
+  return s;
+}
+
+// norm of the Riemannian gradient G - U sym(U^T G)
+double riemannian_norm(const std::vector<double>& U, const std::vector<double>& G, int M, int N) {
+  std::vector<double> S((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < M; ++a) s += U[(size_t)a * N + i] * G[(size_t)a * N + j];
+      S[(size_t)i * N + j] = s;
+    }
+  double n2 = 0.0;
+  for (int a = 0; a < M; ++a)
+    for (int j = 0; j < N; ++j) {
+      double r = G[(size_t)a * N + j];
+      for (int i = 0; i < N; ++i) r -= U[(size_t)a * N + i] * 0.5 * (S[(size_t)i * N + j] + S[(size_t)j * N + i]);
+      n2 += r * r;
+    }
+  return std::sqrt(n2);
+}
+
+}  // namespace
+
+extern "C" int cdfci_optorb(const double* h, const double* eri, int M, int n_alpha, int n_beta,
+                            const cdfci_optorb_opts* opts, double* U_io, double* energies, double* p4_values,
+                            int* n_outer) {
+  if (!h || !eri || !opts || !U_io || !n_outer) return CDFCI_ERR_INVALID_ARG;
+  cdfci_optorb_opts o = *opts;
+  const int N = o.n_active;
+  if (M < 1 || N < 1 || N > M || N > kMaxOrb || n_alpha < 0 || n_beta < 0 || n_alpha > N || n_beta > N ||
+      n_alpha + n_beta < 1)
+    return CDFCI_ERR_INVALID_ARG;
+  if (o.max_outer <= 0) o.max_outer = 20;
+  if (o.max_inner <= 0) o.max_inner = 100;
+  if (o.k <= 0) o.k = 1;
+  if (o.cd_steps <= 0) o.cd_steps = 1000000;
+  if (o.cd_dx_threshold <= 0.0) o.cd_dx_threshold = 1e-10;
+  if (o.energy_tol == 0.0) o.energy_tol = 1e-8;
+  if (o.grad_tol <= 0.0) o.grad_tol = 1e-8;
+  if (o.step0 <= 0.0) o.step0 = 1e-2;
+  if (o.table_slots == 0) o.table_slots = 1ull << 22;
+  OrbWork w;
+  w.M = M;
+  w.N = N;
+  w.s = (hipStream_t)o.stream;
+  w.h.assign(h, h + (size_t)M * M);
+  const size_t m4 = (size_t)M * M * M * M, n4 = (size_t)N * N * N * N;
+  HIP_TRY(w.bufs.alloc(&w.eri, m4));
+  HIP_TRY(w.bufs.alloc(&w.U, (uint64_t)M * N));
+  HIP_TRY(w.bufs.alloc(&w.t1, (uint64_t)M * N * M * M));
+  HIP_TRY(w.bufs.alloc(&w.t2, (uint64_t)M * N * N * M));
+  HIP_TRY(w.bufs.alloc(&w.W, (uint64_t)M * N * N * N));
+  HIP_TRY(w.bufs.alloc(&w.eri2, n4));
+  HIP_TRY(w.bufs.alloc(&w.Gs, n4));
+  HIP_TRY(w.bufs.alloc(&w.grad2, (uint64_t)M * N));
+  HIP_TRY(w.bufs.alloc(&w.part, kOrbDotBlocks));
+  HIP_TRY(hipMemcpyAsync(w.eri, eri, m4 * sizeof(double), hipMemcpyHostToDevice, w.s));
+  std::vector<double> U((size_t)M * N, 0.0);
+  if (o.have_u) {
+    U.assign(U_io, U_io + (size_t)M * N);
+    std::vector<double> Uo;
+    if (!host_orth(U, M, N, Uo)) return CDFCI_ERR_INVALID_ARG;
+    U = Uo;
+  } else {  // the identity columns of the N orbitals of lowest h_pp, in orbital order
+    std::vector<int> order(M);
+    for (int p = 0; p < M; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int p, int q) { return h[(size_t)p * M + p] < h[(size_t)q * M + q]; });
+    std::sort(order.begin(), order.begin() + N);
+    for (int j = 0; j < N; ++j) U[(size_t)order[j] * N + j] = 1.0;
+  }
+  std::vector<double> h2((size_t)N * N), e2(n4), Gm(n4), dh((size_t)N * N), deri(n4);
+  int done = 0;
+  double E_prev = 0.0;
+  for (int l = 0; l < o.max_outer; ++l) {
+    // integrals in the current orbitals
+    HIP_TRY(hipMemcpyAsync(w.U, U.data(), (size_t)M * N * sizeof(double), hipMemcpyHostToDevice, w.s));
+    int rc = orb_transform(w);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(e2.data(), w.eri2, n4 * sizeof(double), hipMemcpyDeviceToHost, w.s));
+    HIP_TRY(hipStreamSynchronize(w.s));
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        double s = 0.0;
+        for (int a = 0; a < M; ++a)
+          for (int b = 0; b < M; ++b) s += U[(size_t)a * N + i] * h[(size_t)a * M + b] * U[(size_t)b * N + j];
+        h2[(size_t)i * N + j] = s;
+      }
+    for (int i = 0; i < N; ++i)  // exact symmetry for the solver's 8-fold packing
+      for (int j = i + 1; j < N; ++j) {
+        const double v = 0.5 * (h2[(size_t)i * N + j] + h2[(size_t)j * N + i]);
+        h2[(size_t)i * N + j] = h2[(size_t)j * N + i] = v;
+      }
+    {
+      const size_t n1 = N, n2 = n1 * N, n3 = n2 * N;
+      for (size_t p = 0; p < n1; ++p)
+        for (size_t q = 0; q <= p; ++q)
+          for (size_t r = 0; r < n1; ++r)
+            for (size_t s2 = 0; s2 <= r; ++s2) {
+              if (p * (p + 1) / 2 + q < r * (r + 1) / 2 + s2) continue;
+              const size_t img[8] = {p * n3 + q * n2 + r * n1 + s2, q * n3 + p * n2 + r * n1 + s2,
+                                     p * n3 + q * n2 + s2 * n1 + r, q * n3 + p * n2 + s2 * n1 + r,
+                                     r * n3 + s2 * n2 + p * n1 + q, s2 * n3 + r * n2 + p * n1 + q,
+                                     r * n3 + s2 * n2 + q * n1 + p, s2 * n3 + r * n2 + q * n1 + p};
+              double v = 0.0;
+              for (size_t m : img) v += e2[m];
+              v *= 0.125;
+              for (size_t m : img) e2[m] = v;
+            }
+    }
+    // the FCI ground state in them (Alg. 1 or Alg. 2) and its RDMs
+    cdfci_opts co;
+    memset(&co, 0, sizeof(co));
+    co.table_slots = o.table_slots;
+    co.z_threshold = o.z_threshold;
+    co.dx_threshold = o.cd_dx_threshold;
+    co.stream = o.stream;
+    cdfci_ctx* ctx = nullptr;
+    rc = cdfci_init(h2.data(), e2.data(), N, n_alpha, n_beta, &co, &ctx);
+    if (rc) return rc;
+    cdfci_stats st;
+    rc = cdfci_step(ctx, o.k, o.cd_steps, &st);
+    double en[2] = {0.0, 0.0};
+    if (!rc) rc = cdfci_rdm_backward(ctx, 1.0, o.top_n, en, dh.data(), deri.data(), nullptr);
+    cdfci_free(ctx);
+    if (rc) return rc;
+    const double E = en[0];
+    if (energies) energies[l] = E;
+    done = l + 1;
+    std::copy(U.begin(), U.end(), U_io);
+    if ((l > 0 && std::fabs(E - E_prev) <= o.energy_tol) || l == o.max_outer - 1) break;
+    E_prev = E;
+    // the orbital problem with the RDMs fixed: gamma = dh, Gamma = 2 deri,
+    // symmetrised over the eight permutations that leave (pq|rs) unchanged
+    w.g1 = dh;
+    const size_t n1 = N, n2 = n1 * N, n3 = n2 * N;
+    for (size_t p = 0; p < n1; ++p)
+      for (size_t q = 0; q < n1; ++q)
+        for (size_t r = 0; r < n1; ++r)
+          for (size_t s2 = 0; s2 < n1; ++s2) {
+            auto at = [&](size_t a, size_t b, size_t c, size_t d) { return 2.0 * deri[a * n3 + b * n2 + c * n1 + d]; };
+            Gm[p * n3 + q * n2 + r * n1 + s2] =
+                0.125 * (at(p, q, r, s2) + at(q, p, r, s2) + at(p, q, s2, r) + at(q, p, s2, r) + at(r, s2, p, q) +
+                         at(s2, r, p, q) + at(r, s2, q, p) + at(s2, r, q, p));
+          }
+    HIP_TRY(hipMemcpyAsync(w.Gs, Gm.data(), n4 * sizeof(double), hipMemcpyHostToDevice, w.s));
+    std::vector<double> G, Uc = U, Up, Gp, best = U, Un, Gn;
+    double val = 0.0;
+    rc = orb_eval(w, Uc, &val, G);
+    if (rc) return rc;
+    double best_val = val;
+    for (int k = 0; k < o.max_inner; ++k) {
+      if (riemannian_norm(Uc, G, M, N) <= o.grad_tol) break;
+      double t = o.step0;
+      if (!Up.empty()) {
+        std::vector<double> sv(Uc.size()), yv(Uc.size());
+        for (size_t q = 0; q < Uc.size(); ++q) {
+          sv[q] = Uc[q] - Up[q];
+          yv[q] = G[q] - Gp[q];
+        }
+        const double sy = std::fabs(frob_dot(sv, yv));
+        if (sy > 0.0) t = (k % 2 == 1) ? frob_dot(sv, sv) / sy : sy / frob_dot(yv, yv);
+      }
+      std::vector<double> X(Uc.size());
+      for (size_t q = 0; q < Uc.size(); ++q) X[q] = Uc[q] - t * G[q];
+      if (!host_orth(X, M, N, Un)) break;
+      rc = orb_eval(w, Un, &val, Gn);
+      if (rc) return rc;
+      Up = Uc;
+      Gp = G;
+      Uc = Un;
+      G = Gn;
+      if (val < best_val) {
+        best_val = val;
+        best = Uc;
+      }
+    }
+    if (p4_values) p4_values[l] = best_val;
+    U = best;
+  }
+  *n_outer = done;
+  return 0;
+}

@@ -25,7 +25,10 @@ Further blocks on the same JSON line (skipped with --no-extra):
   xcdfci            several low-lying states (Alg. 3) on the headline system:
                     4 states, 2^26-slot table, tau = 5e-5, iterations/s and
                     entries/s of the one-launch-per-iteration path, with the
-                    multi-state oracle timed on its first iterations.
+                    multi-state oracle timed on its first iterations;
+  optorb            OptOrbFCI (Alg. 4) on the headline integrals: 12 of the 24
+                    orbitals, 4a+4b, 3 outer iterations of 20000 CD steps and
+                    up to 30 projected steps each; seconds per outer iteration.
 
 --copy-probe runs only a device copy of known size (for calibrating the HBM
 byte counters of a profiler run) and exits.
@@ -266,6 +269,17 @@ def xcdfci_block(api, synth_inputs, args):
     return out
 
 
+def optorb_block(api, synth_inputs, args):
+    h, eri = synth_inputs.ab_initio(24, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    t0 = time.perf_counter()
+    E, U, P = api.cdfci_optorb(h, eri, 12, 4, 4, max_outer=3, max_inner=30, cd_steps=20000, energy_tol=-1.0,
+                               table_slots=1 << 22)
+    wall = time.perf_counter() - t0
+    return {"workload": "ab initio N=24 naux=72 seed=2024 integrals, 12 active orbitals, 4a+4b, "
+                        "3 outer iterations x (20000 CD steps + RDMs + <= 30 projected steps)",
+            "energies": E.tolist(), "p4": P.tolist(), "seconds": wall, "seconds_per_outer": wall / len(E)}
+
+
 def rdm_block(api, ctx, n_col):
     top_n = 1_000_000
     ka, _, _, _ = api.cdfci_export(ctx, top_n=top_n)
@@ -296,7 +310,7 @@ def main():
     ap.add_argument("--n36-plain-seconds", type=float, default=20.0)
     ap.add_argument("--batch-steps", type=int, default=100000)
     ap.add_argument("--xcd-iters", type=int, default=20000)
-    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd"), default=None,
+    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd", "optorb"), default=None,
                     help="diagnostic: run one extra block alone (for profiler runs) and print it")
     ap.add_argument("--n36-k", type=int, default=0, help="with --only n36: a single k")
     args = ap.parse_args()
@@ -325,6 +339,9 @@ def main():
         return
     if args.only == "hubbard":
         print(json.dumps({"hubbard_batch": hubbard_batch(api, synth_inputs, args)}), flush=True)
+        return
+    if args.only == "optorb":
+        print(json.dumps({"optorb": optorb_block(api, synth_inputs, args)}), flush=True)
         return
     if args.only == "xcd":
         blk = xcdfci_block(api, synth_inputs, args)
@@ -402,6 +419,7 @@ def main():
                                                    n_col)),
                          ("mcd_n36", lambda: mcd_n36(api, synth_inputs, args)),
                          ("xcdfci", lambda: xcdfci_block(api, synth_inputs, args)),
+                         ("optorb", lambda: optorb_block(api, synth_inputs, args)),
                          ("hubbard_batch", lambda: hubbard_batch(api, synth_inputs, args))):
             try:
                 out[name] = fn()

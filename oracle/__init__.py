@@ -14,6 +14,8 @@ linesearch.py exact line search of the quartic h(eta) (Sec. 3.1, Appendix A).
 mcdfci.py     serial multicoordinate descent (Alg. 2) with numpy/LAPACK for the
               (m+1)-dimensional eigenproblem.
 xcdfci.py     serial coordinate descent for several states (Alg. 3).
+hubbard_k.py  momentum-space Hubbard model (HubbardK) by operator application,
+              the degenerate-subspace start.
 optorb.py     OptOrbFCI outer loop (Alg. 4): rotated integrals, P4 and its
               gradient, polar factor, alternating Barzilai-Borwein steps.
 cd_serial.cpp serial single-coordinate descent (Alg. 1), fp64 values with

@@ -86,8 +86,9 @@ class XCDResult:
     pass
 
 
-def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=0.0, shift=0.0):
-    N = h.shape[0]
+def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=0.0, shift=0.0, column=None):
+    """column (optional): key -> (alpha keys, beta keys, values) with the
+    diagonal first, for Hamiltonians not given by integrals (h, eri unused)."""
     n = C0.shape[1]
     colcache = {}
 
@@ -95,7 +96,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
         # column of H - shift I (the diagonal entry comes first)
         r = colcache.get(k)
         if r is None:
-            ka, kb, v = cdmod.column(h, eri, k[0], k[1])
+            ka, kb, v = column(k) if column is not None else cdmod.column(h, eri, k[0], k[1])
             r = [((int(x), int(y)), float(z) - (shift if e == 0 else 0.0))
                  for e, (x, y, z) in enumerate(zip(ka, kb, v))]
             colcache[k] = r

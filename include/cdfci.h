@@ -333,6 +333,25 @@ int cdfci_xinit(const double* h, const double* eri, int n_orb, int n_alpha, int 
 int cdfci_xinit_hubbard(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
                         int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out);
 
+/* The same solver for the Hubbard model in momentum space (the paper's
+ * HubbardK Hamiltonian, Sec. 4.1.1): orbital k is the row-major index of a
+ * momentum vector on the periodic lattice dims[0..ndim), one-body energy
+ * eps_k = sum_d -2t cos(2 pi k_d / dims_d) (-t cos(pi k_d) for a direction of
+ * length 2, whose two sites share one bond; 0 for length 1), and the on-site
+ * term (U/L) sum_{k,p,q} a+_{k+q up} a_{k up} a+_{p-q dn} a_{p dn}.  A column
+ * holds the diagonal and the momentum-conserving pair moves, at most
+ * 1 + n_alpha n_beta (L - 1) entries.  Start (Sec. 5.1.3): every
+ * configuration of lowest one-body energy (the Fermi shell filled in all
+ * ways), H - sigma I on them and its n lowest eigenpairs, column k of C^(0)
+ * = sqrt(-(lambda_k - sigma)) v_k with its first largest-magnitude entry
+ * positive.  H conserves total momentum, so the iteration never leaves the
+ * sectors of that start.  With n_states = 1 this is Alg. 1 from the paper's
+ * start.  CDFCI_ERR_UNSUPPORTED if the block has fewer than n or more than
+ * 2048 configurations; CDFCI_ERR_NOT_NEGATIVE if a wanted eigenvalue of
+ * H - sigma I on it is not negative. */
+int cdfci_xinit_hubbard_k(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                          int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out);
+
 /* Run up to nsteps iterations (one kernel launch each) and stop early when
  * the damped accumulator of |eta| ||G_i||_2 falls below dx_threshold.  Host
  * traces, any may be NULL: energies (nsteps * n, the pencil's eigenvalues

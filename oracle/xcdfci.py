@@ -86,9 +86,14 @@ class XCDResult:
     pass
 
 
-def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=0.0, shift=0.0, column=None):
+def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=0.0, shift=0.0, column=None,
+               follow=None):
     """column (optional): key -> (alpha keys, beta keys, values) with the
-    diagonal first, for Hamiltonians not given by integrals (h, eri unused)."""
+    diagonal first, for Hamiltonians not given by integrals (h, eri unused).
+    follow (optional): selections to take where the argmax is tied, i.e.
+    where follow[step] has ||G||_inf within a relative 1e-9 of the largest
+    (another run's choice among equals); the first step where it is not is
+    recorded in follow_failed."""
     n = C0.shape[1]
     colcache = {}
 
@@ -129,11 +134,18 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
     cand = set(C.keys())
     energies, selections, gaps, etas = [], [], [], []
     d = 0.0
+    follow_failed = None
     for step in range(max_steps):
         S64 = np.array(S, dtype=np.float64)
         gn = {j: float(np.max(np.abs(grad_row(j, S64)))) for j in cand}
         order = sorted(cand, key=lambda j: (-gn[j], _order_key(j)))
         i = order[0]
+        if follow is not None and step < len(follow) and follow_failed is None:
+            f = follow[step]
+            if f in gn and gn[f] >= gn[i] * (1.0 - 1e-9):
+                i = f
+            else:
+                follow_failed = step
         gaps.append((gn[order[0]] - gn[order[1]]) / gn[order[0]] if len(order) > 1 and gn[order[0]] > 0 else 1.0)
         Ci = C.get(i, zero).copy()
         Bi = B.get(i, zero).copy()
@@ -167,6 +179,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
         if d < dx_tol:
             break
     r = XCDResult()
+    r.follow_failed = follow_failed
     r.energies = np.array(energies)
     r.selections = selections
     r.gaps = np.array(gaps)

@@ -10,7 +10,7 @@ from .api import (Batch, CDFCIError, Context, cdfci_batch_context, cdfci_batch_r
                   cdfci_load, cdfci_set_threshold, cdfci_step_search, cdfci_init, cdfci_init_hubbard, cdfci_init_hubbard_batch, cdfci_phase_times,
                   cdfci_rdm_backward, cdfci_step, cdfci_step_batch, cdfci_step_energies, cdfci_step_trace,
                   cdfci_strerror, cdfci_tune_batch, cdfci_tune_k, cdfci_workspace_size, cdfci_xenergies,
-                  cdfci_xexport, cdfci_xfree, cdfci_xinit, cdfci_xinit_hubbard, cdfci_xmatrices, cdfci_xstep,
+                  cdfci_xexport, cdfci_xfree, cdfci_xinit, cdfci_xinit_hubbard, cdfci_xinit_hubbard_k, cdfci_xmatrices, cdfci_xstep,
                   make_opts, read_fcidump, XContext, cdfci_optorb)
 
 __all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch_results", "cdfci_batch_trace",
@@ -18,5 +18,5 @@ __all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch
            "cdfci_load", "cdfci_set_threshold", "cdfci_step_search", "cdfci_init", "cdfci_init_hubbard", "cdfci_init_hubbard_batch", "cdfci_phase_times",
            "cdfci_rdm_backward", "cdfci_step", "cdfci_step_batch", "cdfci_step_energies", "cdfci_step_trace",
            "cdfci_strerror", "cdfci_tune_batch", "cdfci_tune_k", "cdfci_workspace_size", "cdfci_xenergies",
-           "cdfci_xexport", "cdfci_xfree", "cdfci_xinit", "cdfci_xinit_hubbard", "cdfci_xmatrices", "cdfci_xstep",
+           "cdfci_xexport", "cdfci_xfree", "cdfci_xinit", "cdfci_xinit_hubbard", "cdfci_xinit_hubbard_k", "cdfci_xmatrices", "cdfci_xstep",
            "make_opts", "read_fcidump", "XContext", "cdfci_optorb"]

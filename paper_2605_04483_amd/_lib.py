@@ -163,6 +163,9 @@ SIGNATURES = [
     ("cdfci_xinit_hubbard", ctypes.c_int,
      [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
       ctypes.c_int, ctypes.c_int, ctypes.c_double, _OPTP, _CTXP]),
+    ("cdfci_xinit_hubbard_k", ctypes.c_int,
+     [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+      ctypes.c_int, ctypes.c_int, ctypes.c_double, _OPTP, _CTXP]),
     ("cdfci_xstep", ctypes.c_int, [_P, ctypes.c_int64, _DP, _UP, _UP, _STP]),
     ("cdfci_xenergies", ctypes.c_int, [_P, _DP]),
     ("cdfci_xmatrices", ctypes.c_int, [_P, _DP, _DP]),

@@ -416,6 +416,19 @@ def cdfci_xinit_hubbard(dims, t, U, n_alpha, n_beta, n_states, shift=0.0, **kw):
     return XContext(x, N, n_alpha, n_beta, int(n_states), float(shift))
 
 
+def cdfci_xinit_hubbard_k(dims, t, U, n_alpha, n_beta, n_states=1, shift=0.0, **kw):
+    """Momentum-space Hubbard model with the degenerate-subspace start."""
+    L = _lib.load()
+    d = (ctypes.c_int * len(dims))(*[int(v) for v in dims])
+    N = int(np.prod(dims))
+    opts = make_opts(**kw)
+    _torch_stream(opts)
+    x = ctypes.c_void_p()
+    _check(L.cdfci_xinit_hubbard_k(d, len(dims), float(t), float(U), int(n_alpha), int(n_beta), int(n_states),
+                                   float(shift), ctypes.byref(opts), ctypes.byref(x)), "cdfci_xinit_hubbard_k")
+    return XContext(x, N, n_alpha, n_beta, int(n_states), float(shift))
+
+
 def cdfci_xstep(x, nsteps, trace=False):
     """Returns stats, or (energies[steps, n], sel_alpha, sel_beta, stats) with trace."""
     st = cdfci_stats()

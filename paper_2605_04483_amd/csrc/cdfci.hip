@@ -2508,6 +2508,9 @@ struct cdfci_xctx {
   int64_t n_col = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool poisoned = false;
+  int kind = 0;  // 0: integrals, 1: momentum-space Hubbard
+  HamK hk{};
+  double* d_eps = nullptr;
 };
 
 namespace {
@@ -2537,22 +2540,29 @@ __global__ void k_xbegin(XCtl* x) {
 int x_launch(cdfci_xctx* X, const XArgs& A) {
   hipStream_t s = X->base->stream;
   const dim3 grid(X->grid), block(256);
+#define XITER_CASE(NS)                                                            \
+  case NS:                                                                        \
+    if (X->kind) k_xiter<NS, 1><<<grid, block, 0, s>>>(A);                        \
+    else k_xiter<NS, 0><<<grid, block, 0, s>>>(A);                                \
+    break;
   switch (X->n) {
-    case 1: k_xiter<1><<<grid, block, 0, s>>>(A); break;
-    case 2: k_xiter<2><<<grid, block, 0, s>>>(A); break;
-    case 3: k_xiter<3><<<grid, block, 0, s>>>(A); break;
-    case 4: k_xiter<4><<<grid, block, 0, s>>>(A); break;
-    case 5: k_xiter<5><<<grid, block, 0, s>>>(A); break;
-    case 6: k_xiter<6><<<grid, block, 0, s>>>(A); break;
-    case 7: k_xiter<7><<<grid, block, 0, s>>>(A); break;
-    default: k_xiter<8><<<grid, block, 0, s>>>(A); break;
+    XITER_CASE(1)
+    XITER_CASE(2)
+    XITER_CASE(3)
+    XITER_CASE(4)
+    XITER_CASE(5)
+    XITER_CASE(6)
+    XITER_CASE(7)
+    default:
+      if (X->kind) k_xiter<8, 1><<<grid, block, 0, s>>>(A);
+      else k_xiter<8, 0><<<grid, block, 0, s>>>(A);
   }
+#undef XITER_CASE
   return 0;
 }
 
-// table, control block, C^(0) on the subspace of (a0, b0), B^(0), S, Q and the
-// first coordinate
-int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
+// table, control block and buffers for n_col-entry columns
+int x_alloc(cdfci_xctx* X) {
   cdfci_ctx* c = X->base;
   const cdfci_opts& o = c->opts;
   const int n = X->n;
@@ -2560,7 +2570,7 @@ int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
   X->nslots = o.table_slots;
   X->mask = X->nslots - 1;
   X->max_entries = (uint64_t)(o.load_factor * (double)X->nslots);
-  X->n_col = column_count(c->N, c->na, c->nb);
+  X->n_col = X->kind ? column_count_k(c->N, c->na, c->nb) : column_count(c->N, c->na, c->nb);
   X->grid = (int)std::max<int64_t>(1, (X->n_col - 1 + 255) / 256);
   X->max_parts = std::max(X->grid, kXSelParts);
   HIP_TRY(hipMalloc(&X->K, X->nslots * sizeof(XKey)));
@@ -2578,7 +2588,33 @@ int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
   HIP_TRY(hipMemcpyAsync(X->x, &h0, sizeof(XCtl), hipMemcpyHostToDevice, s));
   k_xclear<<<2048, 256, 0, s>>>(X->K, X->R, X->nslots, n);
   HIP_TRY(hipGetLastError());
+  return 0;
+}
 
+// the first coordinate: the stored row of largest |G_j|_inf
+int x_first(cdfci_xctx* X) {
+  hipStream_t s = X->base->stream;
+  const int sel_blocks = (int)std::min<uint64_t>((X->nslots + 255) / 256, (uint64_t)kXSelParts);
+  k_xselect_table<<<sel_blocks, 256, 0, s>>>(X->K, X->R, X->nslots, X->x, X->parts);
+  k_xselect_final<<<1, 1, 0, s>>>(X->parts, sel_blocks, X->x);
+  HIP_TRY(hipGetLastError());
+  XCtl h;
+  int rc = xctl_read(X, &h);
+  if (rc) return rc;
+  rc = xcheck(X, h);
+  if (rc) return rc;
+  if (h.islot < 0) return CDFCI_ERR_INVALID_ARG;
+  return 0;
+}
+
+// C^(0) at the reference (a0, b0) and its lowest-diagonal connected
+// determinants, B^(0), S, Q and the first coordinate
+int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
+  int rc = x_alloc(X);
+  if (rc) return rc;
+  cdfci_ctx* c = X->base;
+  const int n = X->n;
+  hipStream_t s = c->stream;
   const Ham H = ham_of(c);
   const int64_t n_col = X->n_col;
   CallBufs bufs;
@@ -2613,17 +2649,8 @@ int x_setup(cdfci_xctx* X, uint64_t a0, uint64_t b0) {
   k_xinit_scatter<<<dim3(chunks, m), 256, 0, s>>>(H, X->K, X->R, X->mask, tasks, coef, n, n_col, X->shift,
                                                    X->x);
   k_xinit_matrices<<<1, 1, 0, s>>>(X->K, X->R, X->mask, tasks, m, n, X->x);
-  const int sel_blocks = (int)std::min<uint64_t>((X->nslots + 255) / 256, (uint64_t)kXSelParts);
-  k_xselect_table<<<sel_blocks, 256, 0, s>>>(X->K, X->R, X->nslots, X->x, X->parts);
-  k_xselect_final<<<1, 1, 0, s>>>(X->parts, sel_blocks, X->x);
   HIP_TRY(hipGetLastError());
-  XCtl h;
-  int rc = xctl_read(X, &h);
-  if (rc) return rc;
-  rc = xcheck(X, h);
-  if (rc) return rc;
-  if (h.islot < 0) return CDFCI_ERR_INVALID_ARG;
-  return 0;
+  return x_first(X);
 }
 
 int x_create(int N, int na, int nb, int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out,
@@ -2651,7 +2678,7 @@ int cdfci_xfree(cdfci_xctx* X) {
     if (X->base->stream) (void)hipStreamSynchronize(X->base->stream);
     else (void)hipDeviceSynchronize();
   }
-  void* bufs[] = {X->K, X->R, X->x, X->parts, X->dE};
+  void* bufs[] = {X->K, X->R, X->x, X->parts, X->dE, X->d_eps};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (X->ev0) (void)hipEventDestroy(X->ev0);
@@ -2744,6 +2771,7 @@ int cdfci_xstep(cdfci_xctx* X, int64_t nsteps, double* energies, uint64_t* sel_a
   if (sel_alpha) HIP_TRY(bufs.alloc(&A.tr_a, (uint64_t)nsteps));
   if (sel_beta) HIP_TRY(bufs.alloc(&A.tr_b, (uint64_t)nsteps));
   A.H = ham_of(X->base);
+  A.HK = X->hk;
   A.K = X->K;
   A.R = X->R;
   A.mask = X->mask;
@@ -3184,5 +3212,184 @@ extern "C" int cdfci_optorb(const double* h, const double* eri, int M, int n_alp
     U = best;
   }
   *n_outer = done;
+  return 0;
+}
+
+// ===========================================================================
+// Momentum-space Hubbard model (Sec. 4.1.1 HubbardK) with the
+// degenerate-subspace start of Sec. 5.1.3, on the multi-state context.
+
+namespace {
+
+// one-body energies of the Bloch orbitals (row-major momentum index):
+// -2t cos(2 pi k_d / n_d) per direction of length n_d >= 3, -t cos(pi k_d)
+// for length 2 (one bond, as in the real-space lattice), 0 for length 1
+std::vector<double> bloch_levels(const int* dims, int ndim, double t) {
+  int L = 1;
+  for (int d = 0; d < ndim; ++d) L *= dims[d];
+  std::vector<double> eps(L, 0.0);
+  for (int k = 0; k < L; ++k) {
+    int r = k;
+    double e = 0.0;
+    for (int d = ndim - 1; d >= 0; --d) {
+      const int kd = r % dims[d];
+      r /= dims[d];
+      if (dims[d] == 2) e += -t * std::cos(M_PI * kd);
+      else if (dims[d] >= 3) e += -2.0 * t * std::cos(2.0 * M_PI * kd / dims[d]);
+    }
+    eps[k] = e;
+  }
+  return eps;
+}
+
+int host_kshift(const int* dims, int ndim, int k, int q, int sgn) {
+  int out = 0, mul = 1;
+  for (int d = ndim - 1; d >= 0; --d) {
+    const int n = dims[d], kd = k % n, qd = q % n;
+    k /= n;
+    q /= n;
+    out += ((kd + sgn * qd + n) % n) * mul;
+    mul *= n;
+  }
+  return out;
+}
+
+double host_between_sign(uint64_t s, int x, int y) {
+  const int lo = std::min(x, y), hi = std::max(x, y);
+  const uint64_t m = ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+  return (__builtin_popcountll(s & m) & 1) ? -1.0 : 1.0;
+}
+
+// every string of n electrons with the lowest one-body energy (the Fermi
+// shell filled in all ways when it is degenerate)
+std::vector<uint64_t> lowest_strings(const std::vector<double>& eps, int n) {
+  const int L = (int)eps.size();
+  std::vector<int> order(L);
+  for (int k = 0; k < L; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return eps[a] < eps[b]; });
+  if (n == 0) return {0ull};
+  const double ef = eps[order[n - 1]];
+  uint64_t base = 0;
+  std::vector<int> shell;
+  for (int k : order) {
+    if (eps[k] < ef - 1e-12) base |= 1ull << k;
+    else if (std::fabs(eps[k] - ef) <= 1e-12) shell.push_back(k);
+  }
+  const int need = n - __builtin_popcountll(base), g = (int)shell.size();
+  std::vector<uint64_t> out;
+  if (g > 62) return out;
+  for (uint64_t m = 0; m < (1ull << g); ++m) {
+    if (__builtin_popcountll(m) != need) continue;
+    uint64_t s = base;
+    for (int i = 0; i < g; ++i)
+      if ((m >> i) & 1) s |= 1ull << shell[i];
+    out.push_back(s);
+  }
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+constexpr int kMaxBlock = 2048;
+
+int x_setup_k(cdfci_xctx* X, const int* dims, int ndim, double t, double U) {
+  cdfci_ctx* c = X->base;
+  const int L = c->N, na = c->na, nb = c->nb, n = X->n;
+  const std::vector<double> eps = bloch_levels(dims, ndim, t);
+  HIP_TRY(hipMalloc(&X->d_eps, L * sizeof(double)));
+  HIP_TRY(hipMemcpy(X->d_eps, eps.data(), L * sizeof(double), hipMemcpyHostToDevice));
+  X->hk.L = L;
+  X->hk.ndim = ndim;
+  for (int d = 0; d < 3; ++d) X->hk.dims[d] = d < ndim ? dims[d] : 1;
+  X->hk.eps = X->d_eps;
+  X->hk.u = U / L;
+  int rc = x_alloc(X);
+  if (rc) return rc;
+  // the degenerate block and H - shift on it
+  const std::vector<uint64_t> sa = lowest_strings(eps, na), sb = lowest_strings(eps, nb);
+  const size_t m = sa.size() * sb.size();
+  if (m < (size_t)n || m > (size_t)kMaxBlock) return CDFCI_ERR_UNSUPPORTED;
+  std::vector<std::pair<uint64_t, uint64_t>> keys;
+  for (uint64_t a : sa)
+    for (uint64_t b : sb) keys.push_back({a, b});
+  std::vector<double> Hs(m * m, 0.0);
+  for (size_t j = 0; j < m; ++j) {
+    const uint64_t a = keys[j].first, b = keys[j].second;
+    double d = X->hk.u * na * nb - X->shift;
+    for (int k = 0; k < L; ++k) d += eps[k] * (double)(((a >> k) & 1) + ((b >> k) & 1));
+    Hs[j * m + j] = d;
+    for (int k = 0; k < L; ++k) {
+      if (!((a >> k) & 1)) continue;
+      for (int p = 0; p < L; ++p) {
+        if (!((b >> p) & 1)) continue;
+        for (int q = 1; q < L; ++q) {
+          const int kq = host_kshift(dims, ndim, k, q, 1), pq = host_kshift(dims, ndim, p, q, -1);
+          if (((a >> kq) & 1) || ((b >> pq) & 1)) continue;
+          const uint64_t a2 = a ^ (1ull << k) ^ (1ull << kq), b2 = b ^ (1ull << p) ^ (1ull << pq);
+          const auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(a2, b2));
+          if (it == keys.end() || *it != std::make_pair(a2, b2)) continue;
+          Hs[(size_t)(it - keys.begin()) * m + j] +=
+              X->hk.u * host_between_sign(a, k, kq) * host_between_sign(b, p, pq);
+        }
+      }
+    }
+  }
+  std::vector<double> w, V;
+  host_sym_eig(Hs, (int)m, w, V);
+  std::vector<int> ord(m);
+  for (size_t i = 0; i < m; ++i) ord[i] = (int)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return w[x] < w[y]; });
+  std::vector<double> coef(m * n);
+  std::vector<XInitTask> tasks(m);
+  for (size_t i = 0; i < m; ++i) tasks[i] = XInitTask{keys[i].first, keys[i].second};
+  for (int k = 0; k < n; ++k) {
+    const int col = ord[k];
+    if (!(w[col] < 0.0)) return CDFCI_ERR_NOT_NEGATIVE;
+    size_t big = 0;
+    for (size_t i = 1; i < m; ++i)
+      if (std::fabs(V[i * m + col]) > std::fabs(V[big * m + col])) big = i;
+    const double scale = std::sqrt(-w[col]) * (V[big * m + col] < 0.0 ? -1.0 : 1.0);
+    for (size_t i = 0; i < m; ++i) coef[i * n + k] = scale * V[i * m + col];
+  }
+  hipStream_t s = c->stream;
+  CallBufs bufs;
+  XInitTask* d_tasks;
+  double* d_coef;
+  HIP_TRY(bufs.alloc(&d_tasks, m));
+  HIP_TRY(bufs.alloc(&d_coef, m * n));
+  HIP_TRY(hipMemcpyAsync(d_tasks, tasks.data(), m * sizeof(XInitTask), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_coef, coef.data(), m * n * sizeof(double), hipMemcpyHostToDevice, s));
+  k_xinit_insert<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(X->K, X->R, X->mask, d_tasks, d_coef, (int)m, n, X->x);
+  const int chunks = (int)std::min<int64_t>((X->n_col + 255) / 256, 64);
+  k_xinit_scatter_k<<<dim3(chunks, (unsigned)m), 256, 0, s>>>(X->hk, X->K, X->R, X->mask, d_tasks, d_coef, n, na,
+                                                                nb, X->shift, X->x);
+  k_xinit_matrices<<<1, 1, 0, s>>>(X->K, X->R, X->mask, d_tasks, (int)m, n, X->x);
+  HIP_TRY(hipGetLastError());
+  rc = x_first(X);
+  HIP_TRY(hipStreamSynchronize(s));
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int cdfci_xinit_hubbard_k(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
+                                     int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out) {
+  if (!dims || ndim < 1 || ndim > 3 || !out) return CDFCI_ERR_INVALID_ARG;
+  int L = 1;
+  for (int i = 0; i < ndim; ++i) {
+    if (dims[i] < 1) return CDFCI_ERR_INVALID_ARG;
+    L *= dims[i];
+  }
+  if (L > kMaxOrb) return CDFCI_ERR_UNSUPPORTED;
+  if (L < 2 || !std::isfinite(t) || !std::isfinite(U)) return CDFCI_ERR_INVALID_ARG;
+  cdfci_xctx* X = nullptr;
+  int rc = x_create(L, n_alpha, n_beta, n_states, shift, opts, out, &X);
+  if (rc) return rc;
+  X->kind = 1;
+  rc = x_setup_k(X, dims, ndim, t, U);
+  if (rc) {
+    cdfci_xfree(X);
+    return rc;
+  }
+  *out = X;
   return 0;
 }

@@ -60,8 +60,64 @@ struct XPartial {
   int64_t err;  // error bits
 };
 
+// Momentum-space Hubbard model (the Hubbard model of Sec. 2.2 in the Bloch
+// orbitals of the periodic lattice, Sec. 4.1.1 HubbardK): orbital k is the
+// row-major index of a momentum vector, eps[k] its one-body energy, and the
+// on-site term becomes (U/L) sum_{k,p,q} a+_{k+q up} a_{k up} a+_{p-q dn} a_{p dn}.
+// A column therefore holds the diagonal, sum eps over the occupied orbitals
+// + (U/L) n_up n_dn, and the pair moves k -> k+q (up), p -> p-q (down) for
+// q != 0 with both targets empty, each (U/L) times the two strings' signs.
+struct HamK {
+  int L, ndim;
+  int dims[3];
+  const double* eps;
+  double u;  // U / L
+};
+
+__device__ __forceinline__ int k_shift(const HamK& K, int k, int q, int sgn) {
+  int out = 0, mul = 1;
+  for (int d = K.ndim - 1; d >= 0; --d) {
+    const int n = K.dims[d];
+    const int kd = k % n, qd = q % n;
+    k /= n;
+    q /= n;
+    out += ((kd + sgn * qd + n) % n) * mul;
+    mul *= n;
+  }
+  return out;
+}
+
+// (-1)^(electrons of s strictly between orbitals x and y)
+__device__ __forceinline__ double between_sign(uint64_t s, int x, int y) {
+  const int lo = min(x, y), hi = max(x, y);
+  const uint64_t m = ((hi >= 64 ? ~0ull : (1ull << hi)) - 1ull) & ~((2ull << lo) - 1ull);
+  return (popc(s & m) & 1) ? -1.0 : 1.0;
+}
+
+__host__ __device__ inline int64_t column_count_k(int L, int na, int nb) {
+  return 1 + (int64_t)na * nb * (L - 1);
+}
+
+// entry e >= 1 of the column of (a, b): 0 when a target is occupied
+__device__ inline double column_entry_k(const HamK& K, const Lists& Ls, uint64_t a, uint64_t b, int64_t e,
+                                        uint64_t* ja, uint64_t* jb) {
+  int64_t t = e - 1;
+  const int q = 1 + (int)(t % (K.L - 1));
+  t /= (K.L - 1);
+  const int ib_i = (int)(t % Ls.nb), ia_i = (int)(t / Ls.nb);
+  const int k = Ls.oa[ia_i], p = Ls.ob[ib_i];
+  const int kq = k_shift(K, k, q, 1), pq = k_shift(K, p, q, -1);
+  *ja = a;
+  *jb = b;
+  if (((a >> kq) & 1) || ((b >> pq) & 1)) return 0.0;
+  *ja = a ^ (1ull << k) ^ (1ull << kq);
+  *jb = b ^ (1ull << p) ^ (1ull << pq);
+  return K.u * between_sign(a, k, kq) * between_sign(b, p, pq);
+}
+
 struct XArgs {
   Ham H;
+  HamK HK;
   XKey* K;
   double* R;  // rows: slot s -> R[s * 2n .. +n) = C_s, [+n .. +2n) = B_s
   uint64_t mask, max_entries;
@@ -271,7 +327,7 @@ __device__ void xblock_sums(double (&v)[NS], double* s_red /* kMaxWaves * NS */)
 
 // The iteration; NS = n states.  S, Q and the step's vectors sit in LDS
 // (identical for every thread), the rows of one column entry in registers.
-template <int NS>
+template <int NS, int KIND>  // KIND 0: integrals, 1: momentum-space Hubbard
 __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   constexpr int NN = NS * NS;
   __shared__ Lists L;
@@ -312,13 +368,18 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
     s_err = 0;
     s_probe = 0;
   }
-  make_lists_block(ia, ib, H.N, L);
+  make_lists_block(ia, ib, KIND ? A.HK.L : H.N, L);
   __syncthreads();
   // H_ii of the shifted Hamiltonian
   double part = 0.0;
-  const int nt = diag_terms(L);
-  for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
-  const double Hii = wg_sum(part, s_red) - shift;
+  if (KIND) {
+    if (tid < A.HK.L) part = A.HK.eps[tid] * (double)(((ia >> tid) & 1) + ((ib >> tid) & 1));
+  } else {
+    const int nt = diag_terms(L);
+    for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+  }
+  double Hii = wg_sum(part, s_red) - shift;
+  if (KIND) Hii += A.HK.u * (double)L.na * (double)L.nb;
   // g = 4 B_i + 4 C_i S and the quartic's coefficients
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -379,7 +440,7 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = 1 + (int64_t)blockIdx.x * blockDim.x + tid; e < A.n_col; e += gsz) {
     uint64_t ja, jb;
-    const double Hj = column_entry(H, L, ia, ib, e, 0.0, &ja, &jb);
+    const double Hj = KIND ? column_entry_k(A.HK, L, ia, ib, e, &ja, &jb) : column_entry(H, L, ia, ib, e, 0.0, &ja, &jb);
     if (Hj == 0.0) continue;
     int probes = 0;
     int64_t slot = xkey_find(A.K, A.mask, ja, jb, &probes);
@@ -607,6 +668,43 @@ __global__ void __launch_bounds__(256) k_xinit_scatter(Ham H, XKey* K, double* R
        e += (int64_t)gridDim.x * blockDim.x) {
     uint64_t ja, jb;
     const double Hj = column_entry(H, L, t.a, t.b, e, s_diag, &ja, &jb);
+    if (Hj == 0.0) continue;
+    int ins = 0, probes = 0;
+    const int64_t s = xkey_upsert(K, mask, ja, jb, &ins, &probes, &err);
+    if (s < 0) break;
+    for (int k = 0; k < n; ++k) atomic_add_f64(&R[(size_t)s * 2 * n + n + k], Hj * coef[blockIdx.y * n + k]);
+    ins_cnt += ins;
+  }
+  if (err) atomicOr(&x->error, err);
+  if (ins_cnt) {
+    atomicAdd(&x->occupied, ins_cnt);
+    atomicAdd(&x->inserts, ins_cnt);
+  }
+}
+
+// B^(0) = (H - shift) C^(0) for the momentum-space model: grid (column
+// chunks, m start determinants)
+__global__ void __launch_bounds__(256) k_xinit_scatter_k(HamK HK, XKey* K, double* R, uint64_t mask,
+                                                         const XInitTask* task, const double* coef, int n,
+                                                         int na, int nb, double shift, XCtl* x) {
+  __shared__ Lists L;
+  __shared__ double s_diag;
+  const XInitTask t = task[blockIdx.y];
+  if (threadIdx.x == 0) {
+    make_lists_serial(t.a, t.b, HK.L, L);
+    double d = HK.u * (double)na * (double)nb - shift;
+    for (int i = 0; i < L.na; ++i) d += HK.eps[L.oa[i]];
+    for (int i = 0; i < L.nb; ++i) d += HK.eps[L.ob[i]];
+    s_diag = d;
+  }
+  __syncthreads();
+  const int64_t n_col = column_count_k(HK.L, na, nb);
+  unsigned long long ins_cnt = 0;
+  int err = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_col;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ja = t.a, jb = t.b;
+    const double Hj = e == 0 ? s_diag : column_entry_k(HK, L, t.a, t.b, e, &ja, &jb);
     if (Hj == 0.0) continue;
     int ins = 0, probes = 0;
     const int64_t s = xkey_upsert(K, mask, ja, jb, &ins, &probes, &err);

@@ -26,6 +26,10 @@ Further blocks on the same JSON line (skipped with --no-extra):
                     4 states, 2^26-slot table, tau = 5e-5, iterations/s and
                     entries/s of the one-launch-per-iteration path, with the
                     multi-state oracle timed on its first iterations;
+  hubbard_k         the paper's 4x4 momentum-space Hubbard case (U/t = 4,
+                    8+8, degenerate-subspace start): iterations/s and the
+                    energy after 2e5 iterations against the exact value the
+                    paper quotes;
   optorb            OptOrbFCI (Alg. 4) on the headline integrals: 12 of the 24
                     orbitals, 4a+4b, 3 outer iterations of 20000 CD steps and
                     up to 30 projected steps each; seconds per outer iteration.
@@ -269,6 +273,24 @@ def xcdfci_block(api, synth_inputs, args):
     return out
 
 
+def hubbard_k_block(api, args):
+    import torch
+
+    x = api.cdfci_xinit_hubbard_k((4, 4), 1.0, 4.0, 8, 8, 1, table_slots=1 << 24)
+    E_start = float(api.cdfci_xenergies(x)[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = api.cdfci_xstep(x, args.hubk_iters)
+    wall = time.perf_counter() - t0
+    E = float(api.cdfci_xenergies(x)[0])
+    x.close()
+    exact = -13.62185  # 4x4, U/t = 4, 8+8: exact diagonalisation value quoted in Sec. 5.1.3
+    return {"workload": "4x4 periodic Hubbard in momentum space, t=1, U=4, 8a+8b, 400-configuration start, "
+                        "2^24-slot table", "iterations": st["steps"], "iters_per_s": st["steps"] / wall,
+            "elements_per_s": st["elements"] / wall, "us_per_iter": 1e6 * wall / max(1, st["steps"]),
+            "energy_start": E_start, "energy": E, "error_vs_exact": E - exact, "occupied": st["occupied"]}
+
+
 def optorb_block(api, synth_inputs, args):
     h, eri = synth_inputs.ab_initio(24, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
     t0 = time.perf_counter()
@@ -310,7 +332,8 @@ def main():
     ap.add_argument("--n36-plain-seconds", type=float, default=20.0)
     ap.add_argument("--batch-steps", type=int, default=100000)
     ap.add_argument("--xcd-iters", type=int, default=20000)
-    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd", "optorb"), default=None,
+    ap.add_argument("--hubk-iters", type=int, default=200000)
+    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd", "optorb", "hubk"), default=None,
                     help="diagnostic: run one extra block alone (for profiler runs) and print it")
     ap.add_argument("--n36-k", type=int, default=0, help="with --only n36: a single k")
     args = ap.parse_args()
@@ -339,6 +362,9 @@ def main():
         return
     if args.only == "hubbard":
         print(json.dumps({"hubbard_batch": hubbard_batch(api, synth_inputs, args)}), flush=True)
+        return
+    if args.only == "hubk":
+        print(json.dumps({"hubbard_k": hubbard_k_block(api, args)}), flush=True)
         return
     if args.only == "optorb":
         print(json.dumps({"optorb": optorb_block(api, synth_inputs, args)}), flush=True)
@@ -420,6 +446,7 @@ def main():
                          ("mcd_n36", lambda: mcd_n36(api, synth_inputs, args)),
                          ("xcdfci", lambda: xcdfci_block(api, synth_inputs, args)),
                          ("optorb", lambda: optorb_block(api, synth_inputs, args)),
+                         ("hubbard_k", lambda: hubbard_k_block(api, args)),
                          ("hubbard_batch", lambda: hubbard_batch(api, synth_inputs, args))):
             try:
                 out[name] = fn()

@@ -32,6 +32,10 @@ def api():
 
 
 CASES = [((2, 3), 3, 3), ((6,), 2, 2), ((2, 2), 2, 2)]
+# the degenerate start reaches the ground state on these (not on every
+# lattice: e.g. 2 x 2 x 2 with 2 + 2 electrons it starts in other symmetry
+# sectors and ends 0.06 Ha above)
+GROUND = CASES + [((5,), 3, 2), ((2, 2, 2), 4, 4), ((2, 2, 2), 3, 2)]
 
 
 @pytest.mark.parametrize("dims,na,nb", CASES)
@@ -54,7 +58,7 @@ def test_start_and_trajectory(api, dims, na, nb):
     x.close()
 
 
-@pytest.mark.parametrize("dims,na,nb", CASES)
+@pytest.mark.parametrize("dims,na,nb", GROUND)
 def test_ground_state(api, dims, na, nb):
     t, U = 1.0, 4.0
     Hk, _ = hk.dense_H(dims, t, U, na, nb)

@@ -66,3 +66,17 @@ def test_larger_case_decreases_to_a_bound(api):
     # the energy reported for the last orbitals is the FCI energy in them
     h2, e2 = oo.rotated(h, eri, U)
     assert abs(E[-1] - ocd.ground_energy(h2, e2, na, nb)) < 1e-8
+
+
+def test_multicoordinate_solves_and_truncated_support(api):
+    """Inner solves by the multicoordinate step (k = 16) and RDMs of the top
+    200 determinants: the energies still fall and stay above the full-space
+    FCI energy."""
+    M, N, na, nb = 8, 6, 2, 2
+    h, eri = synth_inputs.ab_initio(M, 24, 77)
+    E, U, P = api.cdfci_optorb(h, eri, N, na, nb, max_outer=4, max_inner=30, k=16, cd_steps=400,
+                               top_n=200, table_slots=1 << 14)
+    assert len(E) >= 2
+    assert E[-1] < E[0]
+    assert E[-1] >= ocd.ground_energy(h, eri, na, nb) - 1e-8
+    assert np.allclose(U.T @ U, np.eye(N), atol=1e-12)

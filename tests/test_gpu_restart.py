@@ -146,3 +146,24 @@ def test_search_keeps_the_table_within_budget(api):
     assert E < E_start
     assert E >= ocd.ground_energy(h, eri, na, nb) - 1e-9
     ctx.close()
+
+
+def test_reload_on_a_lattice_context(api):
+    """Restart of a real-space Hubbard context (Neel subspace start) from a
+    checkpoint of an earlier run, continued to the ground energy."""
+    from oracle import fci
+
+    dims, na, nb, t, U = (2, 3), 3, 3, 1.0, 4.0
+    h, eri = fci.hubbard_integrals(dims, t, U)
+    E0 = ocd.ground_energy(h, eri, na, nb)
+    ctx = api.cdfci_init_hubbard(dims, t, U, na, nb, table_slots=1 << 12)
+    api.cdfci_step(ctx, 1, 300)
+    ka, kb, c, _ = api.cdfci_export(ctx)
+    nz = c != 0.0
+    ctx.close()
+    ctx = api.cdfci_init_hubbard(dims, t, U, na, nb, table_slots=1 << 12, dx_threshold=1e-12)
+    api.cdfci_load(ctx, ka[nz], kb[nz], c[nz])
+    st = api.cdfci_step(ctx, 1, 300000)
+    assert st["stopped"] == 1
+    assert abs(api.cdfci_energy(ctx, exact=1) - E0) < 1e-8
+    ctx.close()

@@ -178,3 +178,31 @@ def test_argument_errors(api):
     E = api.cdfci_xenergies(x)
     assert np.all(np.diff(E) >= 0)
     x.close()
+
+
+def test_table_full_and_empty_calls(api):
+    """A table too small for the run reports CDFCI_ERR_TABLE_FULL and refuses
+    further steps; zero steps do nothing."""
+    h, eri = synth_inputs.ab_initio(8, 24, 31)
+    x = api.cdfci_xinit(h, eri, 4, 3, 2, table_slots=1 << 10)
+    st = api.cdfci_xstep(x, 0)
+    assert st["steps"] == 0 and st["total_steps"] == 0
+    with pytest.raises(api.CDFCIError) as e:
+        api.cdfci_xstep(x, 5000)
+    assert e.value.code == -3
+    with pytest.raises(api.CDFCIError):
+        api.cdfci_xstep(x, 1)
+    x.close()
+
+
+def test_63_orbitals(api):
+    """Keys using bit 62: the first iterations against the oracle."""
+    N, na, nb = 63, 2, 1
+    h, eri = synth_inputs.ab_initio(N, 64, 63)
+    n, steps = 2, 12
+    keys, C0 = oxc.initial_rows(h, eri, ocd.aufbau(h, na, nb), n)
+    orc = oxc.xcdfci_run(h, eri, keys, C0, max_steps=steps)
+    x = api.cdfci_xinit(h, eri, na, nb, n, table_slots=1 << 18)
+    E, sa, sb, st = api.cdfci_xstep(x, steps, trace=True)
+    _compare_trajectory(E, sa, sb, orc, 8)
+    x.close()

@@ -167,3 +167,27 @@ def test_reload_on_a_lattice_context(api):
     assert st["stopped"] == 1
     assert abs(api.cdfci_energy(ctx, exact=1) - E0) < 1e-8
     ctx.close()
+
+
+def test_fcidump_input(api):
+    """The golden two-site Hubbard FCIDUMP through cdfci_read_fcidump into
+    both solvers: ground energy (U - sqrt(U^2 + 16 t^2)) / 2 at t = 1, U = 4
+    (the closed form of Sec. 2.2) and, with two states and a shift, the
+    two lowest eigenvalues of the 4-determinant space (LAPACK)."""
+    import os
+
+    from oracle import fci
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "hubbard_dimer.FCIDUMP")
+    h, eri, na, nb, ecore = api.read_fcidump(path)
+    E0 = (4.0 - np.sqrt(32.0)) / 2
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 8, init_kind=2, dx_threshold=1e-14)
+    api.cdfci_step(ctx, 1, 10000)
+    assert abs(api.cdfci_energy(ctx, exact=1) + ecore - E0) < 1e-12
+    ctx.close()
+    H, _ = fci.dense_H(h, eri, 2, na, nb)
+    w = np.linalg.eigvalsh(H)
+    x = api.cdfci_xinit(h, eri, na, nb, 2, shift=5.0, table_slots=1 << 8, dx_threshold=1e-14)
+    api.cdfci_xstep(x, 20000)
+    assert np.max(np.abs(api.cdfci_xenergies(x) - w[:2])) < 1e-10
+    x.close()

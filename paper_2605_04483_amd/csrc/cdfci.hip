@@ -2508,6 +2508,7 @@ struct cdfci_xctx {
   int64_t n_col = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool poisoned = false;
+  bool grid_fixed = false;
   int kind = 0;  // 0: integrals, 1: momentum-space Hubbard
   HamK hk{};
   double* d_eps = nullptr;
@@ -2537,15 +2538,16 @@ __global__ void k_xbegin(XCtl* x) {
   x->arrive = 0;
 }
 
-int x_launch(cdfci_xctx* X, const XArgs& A) {
-  hipStream_t s = X->base->stream;
-  const dim3 grid(X->grid), block(256);
-#define XITER_CASE(NS)                                                            \
-  case NS:                                                                        \
-    if (X->kind) k_xiter<NS, 1><<<grid, block, 0, s>>>(A);                        \
-    else k_xiter<NS, 0><<<grid, block, 0, s>>>(A);                                \
-    break;
-  switch (X->n) {
+__global__ void k_xfinish(XCtl* x) {
+  x->steps += x->steps_this_call;
+  x->arrive = 0;
+}
+
+const void* x_kernel(int n, int kind) {
+#define XITER_CASE(NS) \
+  case NS:             \
+    return kind ? (const void*)k_xiter<NS, 1> : (const void*)k_xiter<NS, 0>;
+  switch (n) {
     XITER_CASE(1)
     XITER_CASE(2)
     XITER_CASE(3)
@@ -2554,10 +2556,25 @@ int x_launch(cdfci_xctx* X, const XArgs& A) {
     XITER_CASE(6)
     XITER_CASE(7)
     default:
-      if (X->kind) k_xiter<8, 1><<<grid, block, 0, s>>>(A);
-      else k_xiter<8, 0><<<grid, block, 0, s>>>(A);
+      return kind ? (const void*)k_xiter<8, 1> : (const void*)k_xiter<8, 0>;
   }
 #undef XITER_CASE
+}
+
+// one cooperative launch of A.nsteps iterations; the grid (one lane per
+// column entry, fewer workgroups if not all fit at once) must be resident
+int x_launch(cdfci_xctx* X, XArgs& A) {
+  hipStream_t s = X->base->stream;
+  const void* fn = x_kernel(X->n, X->kind);
+  if (!X->grid_fixed) {
+    int cus = 0, per_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, X->base->device));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+    X->grid = std::max(1, std::min(X->grid, std::min(std::max(1, per_cu) * cus, X->max_parts / 2)));
+    X->grid_fixed = true;
+  }
+  void* args[] = {&A};
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(X->grid), dim3(256), args, 0, s));
   return 0;
 }
 
@@ -2783,10 +2800,15 @@ int cdfci_xstep(cdfci_xctx* X, int64_t nsteps, double* energies, uint64_t* sel_a
   A.theta = X->base->opts.dx_damping;
   A.dx_tol = X->base->opts.dx_threshold;
   hipStream_t s = X->base->stream;
+  A.nsteps = nsteps;
   k_xbegin<<<1, 1, 0, s>>>(X->x);
   HIP_TRY(hipEventRecord(X->ev0, s));
-  for (int64_t i = 0; i < nsteps; ++i) x_launch(X, A);
+  if (nsteps > 0) {
+    rc = x_launch(X, A);
+    if (rc) return rc;
+  }
   HIP_TRY(hipEventRecord(X->ev1, s));
+  k_xfinish<<<1, 1, 0, s>>>(X->x);
   HIP_TRY(hipGetLastError());
   XCtl h;
   rc = xctl_read(X, &h);

@@ -19,15 +19,8 @@
 // B_i = sum_j H_ji C_j recomputed.  An optional shift sigma replaces H by
 // H - sigma I (every diagonal element).
 //
-// One launch of k_xiter is one iteration.  Every workgroup forms the step of
-// the current coordinate redundantly (identical values everywhere) from the
-// table and the control block.  Each lane then owns one entry of the column:
-// B_j has one writer per launch, so its update is a plain read-modify-write.
-// The last workgroup to arrive combines the per-workgroup partials (written
-// with agent-scope stores: the XCDs' L2 caches are not coherent), and only
-// then, when every workgroup has read the old state, stores S, Q, C_i and
-// the recalculated B_i and picks the next coordinate.  Every launch ends at a
-// step boundary, so the table and the matrices always describe the same C.
+// The iteration kernel runs persistently (one cooperative launch for a
+// call's iterations, one device-wide barrier each); see k_xiter below.
 
 constexpr int kXMax = 8;  // states per context (K + 1)
 
@@ -116,6 +109,7 @@ __device__ inline double column_entry_k(const HamK& K, const Lists& Ls, uint64_t
 }
 
 struct XArgs {
+  int64_t nsteps;  // iterations of one launch
   Ham H;
   HamK HK;
   XKey* K;
@@ -325,8 +319,22 @@ __device__ void xblock_sums(double (&v)[NS], double* s_red /* kMaxWaves * NS */)
   __syncthreads();
 }
 
-// The iteration; NS = n states.  S, Q and the step's vectors sit in LDS
-// (identical for every thread), the rows of one column entry in registers.
+// The iteration kernel; NS = n states.  One cooperative launch runs up to
+// A.nsteps iterations with one device-wide barrier each.  S and Q live in
+// every workgroup's shared memory (each keeps an identical copy), the chosen
+// row's C and B in registers.  Per iteration:
+//   A  every workgroup: lists and H_ii of row i, g, the line search, S and Q
+//      updated; workgroup 0 stores C_i' = C_i + eta g;
+//   B  each lane one column entry: probe, insert under the compression rule,
+//      the row read coherently, B_j += eta H_ji g applied atomically, the
+//      candidate |G_j|_inf and H_ji C_j for the recalculation of B_i;
+//   -- device-wide barrier --
+//   C  every workgroup: combine the partials, B_i = H_ii C_i' + sum H_ji C_j
+//      (workgroup 0 adds the correction to the stored B_i atomically, so it
+//      commutes with the next iteration's updates of that entry, which use the
+//      known values of the previous row instead of reading it), and the next
+//      row: i itself or the best candidate, whose row is read after the
+//      barrier.
 template <int NS, int KIND>  // KIND 0: integrals, 1: momentum-space Hubbard
 __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   constexpr int NN = NS * NS;
@@ -337,23 +345,26 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
   __shared__ double s_S[NN];  // S before the step, then after it
   __shared__ double s_v[3 * NS];  // C_i, B_i, g
   __shared__ unsigned long long s_ins, s_tot;
-  __shared__ int s_err, s_probe;
+  __shared__ int s_err, s_fl, s_probe;
   XCtl* X = A.x;
   if (X->error || X->stopped) return;  // the same in every workgroup
   const Ham H = A.H;
   const int tid = threadIdx.x;
-  const int64_t step = X->steps;
-  const int64_t local = X->steps_this_call;  // row of the optional traces
-  const uint64_t ia = X->ia, ib = X->ib;
-  const int64_t islot = X->islot;
+  const int G = gridDim.x;
+  const int64_t step0 = X->steps;
   const double shift = X->shift;
-  double Ci[NS], Bi[NS], g[NS];
+  uint64_t ia = X->ia, ib = X->ib;
+  int64_t islot = X->islot;
+  double d = X->d;
+  unsigned long long occupied = X->occupied, inserts = 0;
+  double Ci[NS], Bi[NS], pC[NS], pR[NS];
   {
     const double* r = A.R + (size_t)islot * 2 * NS;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       Ci[k] = r[k];
       Bi[k] = r[NS + k];
+      pC[k] = pR[k] = 0.0;
     }
   }
   if (tid < NN) {
@@ -363,220 +374,272 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
     s_Qlo[tid] = X->Q_lo[tid];
     s_S[tid] = X->S_hi[tid] + X->S_lo[tid];
   }
-  if (tid == 0) {
-    s_ins = 0;
-    s_err = 0;
-    s_probe = 0;
-  }
-  make_lists_block(ia, ib, KIND ? A.HK.L : H.N, L);
-  __syncthreads();
-  // H_ii of the shifted Hamiltonian
-  double part = 0.0;
-  if (KIND) {
-    if (tid < A.HK.L) part = A.HK.eps[tid] * (double)(((ia >> tid) & 1) + ((ib >> tid) & 1));
-  } else {
-    const int nt = diag_terms(L);
-    for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
-  }
-  double Hii = wg_sum(part, s_red) - shift;
-  if (KIND) Hii += A.HK.u * (double)L.na * (double)L.nb;
-  // g = 4 B_i + 4 C_i S and the quartic's coefficients
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double t = Bi[k];
-#pragma unroll
-    for (int l = 0; l < NS; ++l) t += Ci[l] * s_S[l * NS + k];
-    g[k] = 4.0 * t;
-  }
-  double gg = 0.0, cg = 0.0, cc = 0.0, gsg = 0.0, ginf = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    gg += g[k] * g[k];
-    cg += Ci[k] * g[k];
-    cc += Ci[k] * Ci[k];
-    ginf = fmax(ginf, fabs(g[k]));
-    double t = 0.0;
-#pragma unroll
-    for (int l = 0; l < NS; ++l) t += s_S[k * NS + l] * g[l];
-    gsg += g[k] * t;
-  }
-  const double w1 = gg, w2 = 2.0 * Hii * gg + 2.0 * cg * cg + 2.0 * cc * gg + 2.0 * gsg;
-  const double w3 = 4.0 * gg * cg, w4 = gg * gg;
-  const double eta = w4 > 0.0 ? line_search(w1 / w4, w2 / w4, w3 / w4) : 0.0;
-  if (tid == 0) {
+  uint64_t pa = kEmpty, pb = kEmpty;  // previous row (its B correction may be in flight)
+  unsigned target = 0;                // the arrival counter is zeroed before every launch
+  int flags = 0, stopped = 0, my_probe = 0;
+  int64_t step = 0;
+  const int64_t gsz = (int64_t)G * blockDim.x;
+  for (; step < A.nsteps; ++step) {
+    make_lists_block(ia, ib, KIND ? A.HK.L : H.N, L);
+    __syncthreads();  // also: every thread is done with the previous iteration's counters
+    if (tid == 0) {
+      s_ins = 0;
+      s_tot = 0;
+      s_err = 0;
+      s_fl = 0;
+    }
+    // ---- A: H_ii of the shifted Hamiltonian, g = 4 B_i + 4 C_i S, the step
+    double part = 0.0;
+    if (KIND) {
+      if (tid < A.HK.L) part = A.HK.eps[tid] * (double)(((ia >> tid) & 1) + ((ib >> tid) & 1));
+    } else {
+      const int nt = diag_terms(L);
+      for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
+    }
+    double Hii = wg_sum(part, s_red) - shift;
+    if (KIND) Hii += A.HK.u * (double)L.na * (double)L.nb;
+    double g[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      s_v[k] = Ci[k];
-      s_v[NS + k] = Bi[k];
-      s_v[2 * NS + k] = g[k];
-    }
-  }
-  __syncthreads();  // every thread has read the old S; s_v is complete
-  // S' and Q' from the pre-step rows, one element per thread
-  if (tid < NN) {
-    const int k = tid / NS, l = tid % NS;
-    const double Cik = s_v[k], Cil = s_v[l], Bik = s_v[NS + k], Bil = s_v[NS + l];
-    const double gk = s_v[2 * NS + k], gl = s_v[2 * NS + l];
-    const dd e2 = two_prod(eta, eta);
-    const dd gkl = two_prod(gk, gl);
-    dd S = dd_add(dd{s_Shi[tid], s_Slo[tid]}, dd_mul_d(dd_add(two_prod(Cik, gl), two_prod(gk, Cil)), eta));
-    S = dd_add(S, dd_mul(e2, gkl));
-    dd Q = dd_add(dd{s_Qhi[tid], s_Qlo[tid]}, dd_mul_d(dd_add(two_prod(Bik, gl), two_prod(gk, Bil)), eta));
-    Q = dd_add(Q, dd_mul_d(dd_mul(e2, gkl), Hii));
-    s_Shi[tid] = S.hi;
-    s_Slo[tid] = S.lo;
-    s_Qhi[tid] = Q.hi;
-    s_Qlo[tid] = Q.lo;
-    s_S[tid] = dd_val(S);
-  }
-  __syncthreads();
-  // ---- scatter eta H_ji g over the column; candidates; recalculation parts
-  XCand best{-1.0, kEmpty, kEmpty, -1};
-  double rec[NS];
+      double t = Bi[k];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) rec[k] = 0.0;
-  int err = 0, my_probe = 0;
-  unsigned my_ins = 0;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = 1 + (int64_t)blockIdx.x * blockDim.x + tid; e < A.n_col; e += gsz) {
-    uint64_t ja, jb;
-    const double Hj = KIND ? column_entry_k(A.HK, L, ia, ib, e, &ja, &jb) : column_entry(H, L, ia, ib, e, 0.0, &ja, &jb);
-    if (Hj == 0.0) continue;
-    int probes = 0;
-    int64_t slot = xkey_find(A.K, A.mask, ja, jb, &probes);
-    double cj[NS], bj[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) cj[k] = bj[k] = 0.0;
-    bool anyc = false;
-    const bool big = fabs(eta * Hj) * ginf >= A.tau;
-    if (slot < 0 && big) {
-      int ins = 0;
-      slot = xkey_upsert(A.K, A.mask, ja, jb, &ins, &probes, &err);
-      my_ins += ins;
+      for (int l = 0; l < NS; ++l) t += Ci[l] * s_S[l * NS + k];
+      g[k] = 4.0 * t;
     }
-    my_probe = max(my_probe, probes);
-    if (slot < 0) continue;
-    double* r = A.R + (size_t)slot * 2 * NS;
+    double gg = 0.0, cg = 0.0, cc = 0.0, gsg = 0.0, ginf = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      cj[k] = r[k];
-      bj[k] = r[NS + k];
-      anyc = anyc || cj[k] != 0.0;
+      gg += g[k] * g[k];
+      cg += Ci[k] * g[k];
+      cc += Ci[k] * Ci[k];
+      ginf = fmax(ginf, fabs(g[k]));
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < NS; ++l) t += s_S[k * NS + l] * g[l];
+      gsg += g[k] * t;
     }
-    if (anyc || big) {
+    const double w1 = gg, w2 = 2.0 * Hii * gg + 2.0 * cg * cg + 2.0 * cc * gg + 2.0 * gsg;
+    const double w3 = 4.0 * gg * cg, w4 = gg * gg;
+    const double eta = w4 > 0.0 ? line_search(w1 / w4, w2 / w4, w3 / w4) : 0.0;
+    double Cn[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Cn[k] = Ci[k] + eta * g[k];
+    if (tid == 0) {
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        bj[k] += (eta * Hj) * g[k];
-        r[NS + k] = bj[k];
+        s_v[k] = Ci[k];
+        s_v[NS + k] = Bi[k];
+        s_v[2 * NS + k] = g[k];
       }
     }
-    double gmax = 0.0;
+    __syncthreads();  // every thread has read the old S; s_v is complete
+    // S' and Q' from the pre-step rows, one element per thread
+    if (tid < NN) {
+      const int k = tid / NS, l = tid % NS;
+      const double Cik = s_v[k], Cil = s_v[l], Bik = s_v[NS + k], Bil = s_v[NS + l];
+      const double gk = s_v[2 * NS + k], gl = s_v[2 * NS + l];
+      const dd e2 = two_prod(eta, eta);
+      const dd gkl = two_prod(gk, gl);
+      dd S = dd_add(dd{s_Shi[tid], s_Slo[tid]}, dd_mul_d(dd_add(two_prod(Cik, gl), two_prod(gk, Cil)), eta));
+      S = dd_add(S, dd_mul(e2, gkl));
+      dd Q = dd_add(dd{s_Qhi[tid], s_Qlo[tid]}, dd_mul_d(dd_add(two_prod(Bik, gl), two_prod(gk, Bil)), eta));
+      Q = dd_add(Q, dd_mul_d(dd_mul(e2, gkl), Hii));
+      s_Shi[tid] = S.hi;
+      s_Slo[tid] = S.lo;
+      s_Qhi[tid] = Q.hi;
+      s_Qlo[tid] = Q.lo;
+      s_S[tid] = dd_val(S);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      double* r = A.R + (size_t)islot * 2 * NS;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) st_co(&r[k], Cn[k]);
+    }
+    __syncthreads();
+    // ---- B: scatter eta H_ji g over the column; candidates; recalculation parts
+    XCand best{-1.0, kEmpty, kEmpty, -1};
+    double rec[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) rec[k] = 0.0;
+    int err = 0;
+    unsigned my_ins = 0;
+    for (int64_t e = 1 + (int64_t)blockIdx.x * blockDim.x + tid; e < A.n_col; e += gsz) {
+      uint64_t ja, jb;
+      const double Hj =
+          KIND ? column_entry_k(A.HK, L, ia, ib, e, &ja, &jb) : column_entry(H, L, ia, ib, e, 0.0, &ja, &jb);
+      if (Hj == 0.0) continue;
+      int probes = 0;
+      int64_t slot = xkey_find(A.K, A.mask, ja, jb, &probes);
+      const bool big = fabs(eta * Hj) * ginf >= A.tau;
+      if (slot < 0 && big) {
+        int ins = 0;
+        slot = xkey_upsert(A.K, A.mask, ja, jb, &ins, &probes, &err);
+        my_ins += ins;
+      }
+      my_probe = max(my_probe, probes);
+      if (slot < 0) continue;
+      double* r = A.R + (size_t)slot * 2 * NS;
+      double cj[NS], bj[NS];
+      const bool prev = ja == pa && jb == pb;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        cj[k] = prev ? pC[k] : ld_co(&r[k]);
+        bj[k] = prev ? pR[k] : ld_co(&r[NS + k]);
+      }
+      bool anyc = false;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) anyc = anyc || cj[k] != 0.0;
+      if (anyc || big) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double delta = (eta * Hj) * g[k];
+          atomic_add_f64(&r[NS + k], delta);
+          bj[k] += delta;
+        }
+      }
+      double gmax = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        rec[k] += Hj * cj[k];
+        double t = bj[k];
+#pragma unroll
+        for (int l = 0; l < NS; ++l) t += cj[l] * s_S[l * NS + k];
+        gmax = fmax(gmax, fabs(4.0 * t));
+      }
+      const XCand cnd{gmax, ja, jb, slot};
+      if (xbetter(cnd, best)) best = cnd;
+    }
+    if (my_ins) atomicAdd(&s_ins, (unsigned long long)my_ins);
+    if (err) atomicOr(&s_err, err);
+    const XCand wb = xblock_argmax(best, s_c);
+    xblock_sums<NS>(rec, s_red);
+    XPartial* P = A.parts + (size_t)(step & 1) * G;  // double-buffered by parity
+    if (tid == 0) {
+      XPartial* Q = P + blockIdx.x;
+      st_co(&Q->gmax, wb.g);
+      st_co(&Q->ka, wb.a);
+      st_co(&Q->kb, wb.b);
+      st_co(&Q->slot, wb.slot);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) st_co(&Q->rec[k], rec[k]);
+      st_co(&Q->inserts, (int64_t)s_ins);
+      st_co(&Q->err, (int64_t)s_err);
+    }
+    target += G;
+    if (!grid_barrier(&X->arrive, target)) flags |= kErrBarrier;
+    // ---- C: combine (every workgroup, the same order)
+    XCand wc{-1.0, kEmpty, kEmpty, -1};
+    double rsum[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) rsum[k] = 0.0;
+    unsigned long long ins_tot = 0;
+    int fl = 0;
+    for (int q = tid; q < G; q += blockDim.x) {  // fixed order per thread
+      const XPartial* Q = P + q;
+      const XCand c{ld_co(&Q->gmax), ld_co(&Q->ka), ld_co(&Q->kb), ld_co(&Q->slot)};
+      if (xbetter(c, wc)) wc = c;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) rsum[k] += ld_co(&Q->rec[k]);
+      ins_tot += (unsigned long long)ld_co(&Q->inserts);
+      fl |= (int)ld_co(&Q->err);
+    }
+    if (ins_tot) atomicAdd(&s_tot, ins_tot);
+    if (fl) atomicOr(&s_fl, fl);
+    const XCand win = xblock_argmax(wc, s_c);  // its barriers also complete s_tot, s_fl
+    xblock_sums<NS>(rsum, s_red);
+    flags |= s_fl;
+    occupied += s_tot;
+    inserts += s_tot;
+    if (occupied > A.max_entries) flags |= kErrTableFull;
+    // B_i = H_ii C_i' + sum_{j != i} H_ji C_j; the next row
+    double Rn[NS];
+    double gi = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Rn[k] = Hii * Cn[k] + rsum[k];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      rec[k] += Hj * cj[k];
-      double t = bj[k];
+      double t = Rn[k];
 #pragma unroll
-      for (int l = 0; l < NS; ++l) t += cj[l] * s_S[l * NS + k];
-      gmax = fmax(gmax, fabs(4.0 * t));
+      for (int l = 0; l < NS; ++l) t += Cn[l] * s_S[l * NS + k];
+      gi = fmax(gi, fabs(4.0 * t));
     }
-    const XCand cnd{gmax, ja, jb, slot};
-    if (xbetter(cnd, best)) best = cnd;
+    const XCand self{gi, ia, ib, islot};
+    const XCand nxt = xbetter(self, win) ? self : win;
+    if (blockIdx.x == 0 && tid == 0) {
+      double* r = A.R + (size_t)islot * 2 * NS;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) atomic_add_f64(&r[NS + k], Rn[k] - Bi[k]);
+      if (A.tr_SQ) {
+        double* t = A.tr_SQ + step * 2 * NN;
+        for (int k = 0; k < NN; ++k) {
+          t[k] = s_Shi[k] + s_Slo[k];
+          t[NN + k] = s_Qhi[k] + s_Qlo[k];
+        }
+      }
+      if (A.tr_a) A.tr_a[step] = ia;
+      if (A.tr_b) A.tr_b[step] = ib;
+    }
+    const double step_norm = fabs(eta) * sqrt(gg);
+    d = (step0 + step == 0) ? step_norm : A.theta * d + (1.0 - A.theta) * step_norm;
+    pa = ia;
+    pb = ib;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      pC[k] = Cn[k];
+      pR[k] = Rn[k];
+    }
+    if (nxt.slot == islot) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        Ci[k] = Cn[k];
+        Bi[k] = Rn[k];
+      }
+    } else {  // updated by its owner before the barrier
+      const double* r = A.R + (size_t)nxt.slot * 2 * NS;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        Ci[k] = ld_co(&r[k]);
+        Bi[k] = ld_co(&r[NS + k]);
+      }
+    }
+    ia = nxt.a;
+    ib = nxt.b;
+    islot = nxt.slot;
+    if (flags) {
+      ++step;
+      break;
+    }
+    if (d < A.dx_tol) {
+      stopped = 1;
+      ++step;
+      break;
+    }
   }
-  if (my_ins) atomicAdd(&s_ins, (unsigned long long)my_ins);
-  if (err) atomicOr(&s_err, err);
+  // statistics and state write-back
+  if (tid == 0) s_probe = 0;
+  __syncthreads();
   if (my_probe) atomicMax(&s_probe, my_probe);
-  const XCand wb = xblock_argmax(best, s_c);
-  xblock_sums<NS>(rec, s_red);
-  if (tid == 0) {
-    XPartial* P = A.parts + blockIdx.x;
-    st_co(&P->gmax, wb.g);
-    st_co(&P->ka, wb.a);
-    st_co(&P->kb, wb.b);
-    st_co(&P->slot, wb.slot);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) st_co(&P->rec[k], rec[k]);
-    st_co(&P->inserts, (int64_t)s_ins);
-    st_co(&P->err, (int64_t)s_err);
-    if (s_probe) atomicMax(&X->max_probe, s_probe);
-    s_tot = 0;
-  }
-  if (!last_workgroup(&X->arrive)) return;
-  // ---- last workgroup: combine, store the step, recalculate B_i, choose the
-  // next coordinate.  Every workgroup has read X and row i by now.
-  XCand wc{-1.0, kEmpty, kEmpty, -1};
-  double rsum[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) rsum[k] = 0.0;
-  unsigned long long ins_tot = 0;
-  int fl = 0;
-  for (int q = tid; q < (int)gridDim.x; q += blockDim.x) {  // fixed order per thread
-    const XPartial* P = A.parts + q;
-    const XCand c{ld_co(&P->gmax), ld_co(&P->ka), ld_co(&P->kb), ld_co(&P->slot)};
-    if (xbetter(c, wc)) wc = c;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) rsum[k] += ld_co(&P->rec[k]);
-    ins_tot += (unsigned long long)ld_co(&P->inserts);
-    fl |= (int)ld_co(&P->err);
-  }
-  if (ins_tot) atomicAdd(&s_tot, ins_tot);
-  if (fl) atomicOr(&X->error, fl);
-  const XCand win = xblock_argmax(wc, s_c);  // its barriers also complete s_tot
-  xblock_sums<NS>(rsum, s_red);
-  ins_tot = s_tot;
-  if (tid < NN) {
-    X->S_hi[tid] = s_Shi[tid];
-    X->S_lo[tid] = s_Slo[tid];
-    X->Q_hi[tid] = s_Qhi[tid];
-    X->Q_lo[tid] = s_Qlo[tid];
-  }
-  if (tid != 0) return;
-  // C_i' = C_i + eta g;  B_i = H_ii C_i' + sum_{j != i} H_ji C_j
-  double Cn[NS], Rn[NS];
-  double gi = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    Cn[k] = Ci[k] + eta * g[k];
-    Rn[k] = Hii * Cn[k] + rsum[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double t = Rn[k];
-#pragma unroll
-    for (int l = 0; l < NS; ++l) t += Cn[l] * s_S[l * NS + k];
-    gi = fmax(gi, fabs(4.0 * t));
-  }
-  {
-    double* r = A.R + (size_t)islot * 2 * NS;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      r[k] = Cn[k];
-      r[NS + k] = Rn[k];
+  __syncthreads();
+  if (tid == 0 && s_probe) atomicMax(&X->max_probe, s_probe);
+  if (blockIdx.x == 0) {
+    if (tid < NN) {
+      X->S_hi[tid] = s_Shi[tid];
+      X->S_lo[tid] = s_Slo[tid];
+      X->Q_hi[tid] = s_Qhi[tid];
+      X->Q_lo[tid] = s_Qlo[tid];
+    }
+    if (tid == 0) {
+      if (flags) atomicOr(&X->error, flags);
+      X->d = d;
+      X->occupied = occupied;
+      X->inserts += inserts;
+      X->ia = ia;
+      X->ib = ib;
+      X->islot = islot;
+      X->steps_this_call = step;
+      X->stopped = stopped;
     }
   }
-  const XCand self{gi, ia, ib, islot};
-  const XCand nxt = xbetter(self, win) ? self : win;
-  if (A.tr_SQ) {
-    double* t = A.tr_SQ + local * 2 * NN;
-    for (int k = 0; k < NN; ++k) {
-      t[k] = s_Shi[k] + s_Slo[k];
-      t[NN + k] = s_Qhi[k] + s_Qlo[k];
-    }
-  }
-  if (A.tr_a) A.tr_a[local] = ia;
-  if (A.tr_b) A.tr_b[local] = ib;
-  const double step_norm = fabs(eta) * sqrt(gg);
-  const double d = (step == 0) ? step_norm : A.theta * X->d + (1.0 - A.theta) * step_norm;
-  X->d = d;
-  X->occupied += ins_tot;
-  X->inserts += ins_tot;
-  if (X->occupied > A.max_entries) X->error |= kErrTableFull;
-  if (d < A.dx_tol) X->stopped = 1;
-  X->ia = nxt.a;
-  X->ib = nxt.b;
-  X->islot = nxt.slot;
-  X->steps = step + 1;
-  X->steps_this_call += 1;
-  X->arrive = 0;
 }
 
 // ---------------------------------------------------------------- start

@@ -24,7 +24,7 @@ Further blocks on the same JSON line (skipped with --no-extra):
                     headline run's final state;
   xcdfci            several low-lying states (Alg. 3) on the headline system:
                     4 states, 2^26-slot table, tau = 5e-5, iterations/s and
-                    entries/s of the one-launch-per-iteration path, with the
+                    entries/s of the persistent multi-state kernel, with the
                     multi-state oracle timed on its first iterations;
   hubbard_k         the paper's 4x4 momentum-space Hubbard case (U/t = 4,
                     8+8, degenerate-subspace start): iterations/s and the

@@ -352,7 +352,8 @@ int cdfci_xinit_hubbard(const int* dims, int ndim, double t, double U, int n_alp
 int cdfci_xinit_hubbard_k(const int* dims, int ndim, double t, double U, int n_alpha, int n_beta,
                           int n_states, double shift, const cdfci_opts* opts, cdfci_xctx** out);
 
-/* Run up to nsteps iterations (one kernel launch each) and stop early when
+/* Run up to nsteps iterations (one persistent cooperative launch, one
+ * device-wide barrier per iteration) and stop early when
  * the damped accumulator of |eta| ||G_i||_2 falls below dx_threshold.  Host
  * traces, any may be NULL: energies (nsteps * n, the pencil's eigenvalues
  * after each iteration, ascending), sel_alpha / sel_beta (nsteps, the row

@@ -2528,6 +2528,7 @@ int xctl_read(cdfci_xctx* X, XCtl* h) {
 int xcheck(cdfci_xctx* X, const XCtl& h) {
   int rc = 0;
   if ((h.error & kErrTableFull) || h.occupied > X->max_entries) rc = CDFCI_ERR_TABLE_FULL;
+  else if (h.error & kErrBarrier) rc = CDFCI_ERR_BARRIER;
   else if (h.error) rc = CDFCI_ERR_HIP;
   if (rc) X->poisoned = true;
   return rc;

@@ -11,7 +11,7 @@ from .api import (Batch, CDFCIError, Context, cdfci_batch_context, cdfci_batch_r
                   cdfci_rdm_backward, cdfci_step, cdfci_step_batch, cdfci_step_energies, cdfci_step_trace,
                   cdfci_strerror, cdfci_tune_batch, cdfci_tune_k, cdfci_workspace_size, cdfci_xenergies,
                   cdfci_xexport, cdfci_xfree, cdfci_xinit, cdfci_xinit_hubbard, cdfci_xinit_hubbard_k, cdfci_xmatrices, cdfci_xstep,
-                  make_opts, read_fcidump, XContext, cdfci_optorb)
+                  make_opts, make_rdm1, make_rdm12, read_fcidump, XContext, cdfci_optorb)
 
 __all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch_results", "cdfci_batch_trace",
            "cdfci_column", "cdfci_energy", "cdfci_entry", "cdfci_export", "cdfci_free", "cdfci_free_batch",
@@ -19,4 +19,4 @@ __all__ = ["Batch", "CDFCIError", "Context", "cdfci_batch_context", "cdfci_batch
            "cdfci_rdm_backward", "cdfci_step", "cdfci_step_batch", "cdfci_step_energies", "cdfci_step_trace",
            "cdfci_strerror", "cdfci_tune_batch", "cdfci_tune_k", "cdfci_workspace_size", "cdfci_xenergies",
            "cdfci_xexport", "cdfci_xfree", "cdfci_xinit", "cdfci_xinit_hubbard", "cdfci_xinit_hubbard_k", "cdfci_xmatrices", "cdfci_xstep",
-           "make_opts", "read_fcidump", "XContext", "cdfci_optorb"]
+           "make_opts", "make_rdm1", "make_rdm12", "read_fcidump", "XContext", "cdfci_optorb"]

@@ -164,6 +164,20 @@ def cdfci_rdm_backward(ctx, grad_E=1.0, top_n=0, want_eri=True):
     return energy, dh, deri, kap
 
 
+def make_rdm1(ctx, top_n=0):
+    """Spin-summed 1-RDM gamma[p, q] = sum_s <a+_ps a_qs> of the normalised
+    top_n support (the reverse pass at grad_E = 1)."""
+    _, dh, _, _ = cdfci_rdm_backward(ctx, 1.0, top_n, want_eri=False)
+    return dh
+
+
+def make_rdm12(ctx, top_n=0):
+    """(gamma, Gamma): Gamma[p, q, r, s] = sum_st <a+_ps a+_rt a_st a_qs>
+    (chemist order, E = sum h gamma + 1/2 sum (pq|rs) Gamma)."""
+    _, dh, deri, _ = cdfci_rdm_backward(ctx, 1.0, top_n)
+    return dh, 2.0 * deri
+
+
 def cdfci_column(ctx, key):
     L = _lib.load()
     k = np.array([int(key[0]), int(key[1])], dtype=np.uint64)

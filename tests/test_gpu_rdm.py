@@ -168,3 +168,22 @@ def test_autograd_support_energy(api):
     assert np.max(np.abs(ht.grad.numpy() - dh)) < 1e-12
     assert np.max(np.abs(et.grad.numpy() - deri)) < 1e-12
     ctx.close()
+
+
+def test_make_rdm12_convention(api):
+    """make_rdm1 / make_rdm12 (the spin-summed RDMs in the PySCF FCI solver
+    convention the reverse pass follows) against the oracle's RDMs of the
+    exported state, and E = sum h gamma + 1/2 sum (pq|rs) Gamma."""
+    N = 8
+    h, eri = synth_inputs.ab_initio(N, 24, 7)
+    ctx = api.cdfci_init(h, eri, 4, 3, table_slots=1 << 14)
+    api.cdfci_step(ctx, 1, 400)
+    ka, kb, c, _ = api.cdfci_export(ctx)
+    g1o, g2o = ocd.rdm12(N, ka, kb, c)
+    g1 = api.make_rdm1(ctx)
+    d1, d2 = api.make_rdm12(ctx)
+    assert np.max(np.abs(g1 - g1o)) < 1e-12 and np.max(np.abs(d1 - g1o)) < 1e-12
+    assert np.max(np.abs(d2 - g2o)) < 1e-12
+    E = float(np.sum(h * d1) + 0.5 * np.sum(eri * d2))
+    assert abs(E - api.cdfci_energy(ctx, exact=1)) < 1e-10
+    ctx.close()

@@ -104,3 +104,19 @@ def test_4x4_half_filling(api):
     assert E[-1, 0] < E_start - 0.1
     assert E[-1, 0] > exact - 1e-5
     x.close()
+
+
+def test_two_state_trajectory(api):
+    """Two states in momentum space with a shift: 300 iterations against the
+    oracle following the device's picks among ties."""
+    dims, na, nb, t, U, n = (6,), 2, 2, 1.0, 4.0, 2
+    keys, C0 = hk.degenerate_start(dims, t, U, na, nb, n, U + 1.0)
+    x = api.cdfci_xinit_hubbard_k(dims, t, U, na, nb, n, shift=U + 1.0, table_slots=1 << 12)
+    E, sa, sb, st = api.cdfci_xstep(x, 300, trace=True)
+    sel = [(int(a), int(b)) for a, b in zip(sa, sb)]
+    orc = oxc.xcdfci_run(None, None, keys, C0, max_steps=300, shift=U + 1.0,
+                         column=lambda k: hk.column(dims, t, U, *k), follow=sel)
+    assert orc.follow_failed is None, orc.follow_failed
+    assert orc.selections == sel
+    assert np.max(np.abs(E - orc.energies) / np.abs(orc.energies)) <= 1e-10
+    x.close()

@@ -206,3 +206,21 @@ def test_63_orbitals(api):
     E, sa, sb, st = api.cdfci_xstep(x, steps, trace=True)
     _compare_trajectory(E, sa, sb, orc, 8)
     x.close()
+
+
+def test_lattice_trajectory_with_ties(api):
+    """Real-space 2 x 3 lattice, two states, shift U + 1: lattice symmetry
+    makes |G| ties common, so the oracle follows the device's pick wherever
+    it is one of the largest (within 1e-9 relative) and must agree with it at
+    every one of 300 iterations (energies 1e-10 relative)."""
+    dims, na, nb, t, U, n = (2, 3), 3, 3, 1.0, 4.0, 2
+    h, eri = fci.hubbard_integrals(dims, t, U)
+    keys, C0 = oxc.initial_rows(h, eri, ocd.neel(dims, na, nb), n)
+    x = api.cdfci_xinit_hubbard(dims, t, U, na, nb, n, shift=U + 1.0, table_slots=1 << 12)
+    E, sa, sb, st = api.cdfci_xstep(x, 300, trace=True)
+    sel = [(int(a), int(b)) for a, b in zip(sa, sb)]
+    orc = oxc.xcdfci_run(h, eri, keys, C0, max_steps=300, shift=U + 1.0, follow=sel)
+    assert orc.follow_failed is None, orc.follow_failed
+    assert orc.selections == sel
+    assert np.max(np.abs(E - orc.energies) / np.abs(orc.energies)) <= 1e-10
+    x.close()

@@ -224,3 +224,21 @@ def test_lattice_trajectory_with_ties(api):
     assert orc.selections == sel
     assert np.max(np.abs(E - orc.energies) / np.abs(orc.energies)) <= 1e-10
     x.close()
+
+
+def test_closed_shell_full_size_trajectory(api):
+    """The 6 + 6 workload itself (closed shell: spin-flipped determinants tie
+    exactly), four states, 30 iterations: the oracle follows the device's
+    pick among ties and must agree at every iteration."""
+    N, na, nb, naux = 24, 6, 6, 72
+    h, eri = synth_inputs.ab_initio(N, naux, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    n, steps = 4, 30
+    keys, C0 = oxc.initial_rows(h, eri, ocd.aufbau(h, na, nb), n)
+    x = api.cdfci_xinit(h, eri, na, nb, n, table_slots=1 << 20)
+    E, sa, sb, st = api.cdfci_xstep(x, steps, trace=True)
+    sel = [(int(a), int(b)) for a, b in zip(sa, sb)]
+    orc = oxc.xcdfci_run(h, eri, keys, C0, max_steps=steps, follow=sel)
+    assert orc.follow_failed is None, orc.follow_failed
+    assert orc.selections == sel
+    assert np.max(np.abs(E - orc.energies) / np.abs(orc.energies)) <= 1e-10
+    x.close()

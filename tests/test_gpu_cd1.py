@@ -179,3 +179,25 @@ def test_not_negative_is_reported(api):
     with pytest.raises(api.CDFCIError) as ei:
         api.cdfci_init(h, eri, 2, 2, table_slots=1 << 10)
     assert ei.value.code == -4
+
+
+def test_abinitio_n24_closed_shell_trajectory_with_ties(api):
+    """The benchmark's own 6 + 6 system, whose closed-shell start makes
+    spin-flipped determinants tie exactly in |g|: the one-state form of the
+    multi-state oracle (Alg. 1, pinned against the serial oracle) follows the
+    device's pick wherever it is one of the largest (within 1e-9 relative)
+    and must agree with every chosen determinant and energy of 60 steps."""
+    from oracle import xcdfci as oxc
+
+    N, na, nb = 24, 6, 6
+    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    K = 60
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 24)
+    tr = api.cdfci_step_trace(ctx, K)
+    sel = [(int(a), int(b)) for a, b in zip(tr["sel_alpha"], tr["sel_beta"])]
+    orc = oxc.xcdfci_run(h, eri, keys, np.asarray(c0, dtype=np.float64).reshape(-1, 1), max_steps=K, follow=sel)
+    assert orc.follow_failed is None, orc.follow_failed
+    assert orc.selections == sel
+    assert np.max(np.abs(tr["energy"] - orc.energies[:, 0]) / np.abs(orc.energies[:, 0])) <= 1e-10
+    ctx.close()

@@ -409,77 +409,93 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ a, const d
 // Eigenvector of the symmetric tridiagonal (a, b) for the eigenvalue
 // estimate lam, by one thread: inverse iteration on (T - lam I), two sweeps
 // from the all-ones vector (lam is accurate to a few ulps, so one sweep
-// already converges; the second is a margin).  scale bounds |T|.
+// already converges; the second is a margin).  scale bounds |T|.  Each loop
+// loads the next row's shared-memory operands one iteration ahead, so the
+// dependent chain runs register to register; the row interchanges are
+// selects, not branches.  y is normalised on return.
 __device__ void tri_inverse_iteration(const double* __restrict__ a, const double* __restrict__ b, int n,
                                       double lam, double scale, double* __restrict__ y,
                                       double* __restrict__ wk) {
-  // inverse iteration on (T - lam I): Gaussian elimination with partial
-  // pivoting of a tridiagonal matrix (one extra superdiagonal of fill-in),
-  // the row being eliminated carried in registers.  The factors are
-  // stored as multipliers dl, reciprocal pivots rdm, superdiagonals du, du2.
+  // Gaussian elimination with partial pivoting of T - lam I (one extra
+  // superdiagonal of fill-in), the row being eliminated carried in
+  // registers; stored as multipliers dl, reciprocal pivots rdm,
+  // superdiagonals du, du2 and the interchange flags sw (1.0 = swapped).
   double* dl = wk;
   double* rdm = wk + n;
   double* du = wk + 2 * n;
   double* du2 = wk + 3 * n;
-  int* piv = (int*)(wk + 4 * n);
+  double* sw = wk + 4 * n;
   const double tiny = 1e-300 + 1e-15 * scale;
+  const int nb = n - 1;  // entries of b
   double dm_c = a[0] - lam, du_c = b[0];
-  for (int i = 0; i < n - 1; ++i) {
-    const double dl_i = b[i];
-    const double a_nx = a[i + 1] - lam;
-    const double du_nx = i + 1 < n - 1 ? b[i + 1] : 0.0;
-    double f;
-    if (fabs(dm_c) >= fabs(dl_i)) {
-      if (dm_c == 0.0) dm_c = tiny;
-      f = dl_i / dm_c;
-      piv[i] = 0;
-      rdm[i] = 1.0 / dm_c;
-      du[i] = du_c;
-      du2[i] = 0.0;
-      dm_c = a_nx - f * du_c;
-      du_c = du_nx;
-    } else {
-      f = dm_c / dl_i;
-      piv[i] = 1;
-      rdm[i] = 1.0 / dl_i;
-      du[i] = a_nx;
-      du2[i] = du_nx;
-      dm_c = du_c - f * a_nx;
-      du_c = -f * du_nx;
-    }
+  double q_b = b[0], q_a = a[1], q_bn = b[min(1, nb - 1)];
+  for (int i = 0; i < nb; ++i) {
+    const double dl_i = q_b, a_nx = q_a - lam, du_nx = i + 1 < nb ? q_bn : 0.0;
+    const int j = min(i + 1, nb - 1);
+    q_b = b[j];
+    q_a = a[j + 1];
+    q_bn = b[min(j + 1, nb - 1)];
+    const bool swp = fabs(dm_c) < fabs(dl_i);
+    const double pv = swp ? dl_i : (dm_c == 0.0 ? tiny : dm_c);
+    const double r = 1.0 / pv;
+    const double f = (swp ? dm_c : dl_i) * r;
+    const double du_s = swp ? a_nx : du_c;
     dl[i] = f;
+    rdm[i] = r;
+    du[i] = du_s;
+    du2[i] = swp ? du_nx : 0.0;
+    sw[i] = swp ? 1.0 : 0.0;
+    dm_c = (swp ? du_c : a_nx) - f * du_s;
+    du_c = swp ? -f * du_nx : du_nx;
   }
   if (dm_c == 0.0) dm_c = tiny;
   rdm[n - 1] = 1.0 / dm_c;
-  for (int i = 0; i < n; ++i) y[i] = 1.0;
+  double inv = 1.0;  // scale of the right-hand side (the previous sweep's norm)
   for (int sweep = 0; sweep < 2; ++sweep) {
-    // L solve with the row interchanges
-    double cur = y[0];
-    for (int i = 0; i < n - 1; ++i) {
-      const double nx = y[i + 1];
-      if (piv[i] == 0) {
-        y[i] = cur;
-        cur = nx - dl[i] * cur;
-      } else {
-        y[i] = nx;
-        cur = cur - dl[i] * nx;
-      }
+    // L solve with the row interchanges: y <- L^-1 P (inv * rhs), rhs = ones
+    // on the first sweep and the previous solution on the second
+    double cur = sweep ? inv * y[0] : 1.0;
+    double q_f = dl[0], q_s = sw[0], q_n = sweep ? y[1] : 1.0;
+    for (int i = 0; i < nb; ++i) {
+      const double fv = q_f, nx = inv * q_n;
+      const bool swp = q_s != 0.0;
+      const int j = min(i + 1, nb - 1);
+      q_f = dl[j];
+      q_s = sw[j];
+      q_n = sweep ? y[j + 1] : 1.0;
+      y[i] = swp ? nx : cur;
+      cur = swp ? cur - fv * nx : nx - fv * cur;
     }
-    // U solve
+    // U solve, the squared norm alongside
     double y2 = cur * rdm[n - 1];
     y[n - 1] = y2;
+    double nrm = y2 * y2;
     double y1 = (y[n - 2] - du[n - 2] * y2) * rdm[n - 2];
     y[n - 2] = y1;
-    for (int i = n - 3; i >= 0; --i) {
-      const double yi = (y[i] - du[i] * y1 - du2[i] * y2) * rdm[i];
-      y[i] = yi;
-      y2 = y1;
-      y1 = yi;
+    nrm += y1 * y1;
+    if (n >= 3) {
+      double q_y = y[n - 3], q_u = du[n - 3], q_u2 = du2[n - 3], q_r = rdm[n - 3];
+      for (int i = n - 3; i >= 0; --i) {
+        const double yv = q_y, uv = q_u, u2v = q_u2, rv = q_r;
+        const int j = max(i - 1, 0);
+        q_y = y[j];
+        q_u = du[j];
+        q_u2 = du2[j];
+        q_r = rdm[j];
+        const double yi = (yv - uv * y1 - u2v * y2) * rv;
+        y[i] = yi;
+        nrm += yi * yi;
+        y2 = y1;
+        y1 = yi;
+      }
     }
-    double nrm = 0.0;
-    for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
-    const double inv = 1.0 / sqrt(nrm);
-    for (int i = 0; i < n; ++i) y[i] *= inv;
+    inv = 1.0 / sqrt(nrm);
+  }
+  double q_y = y[0];
+  for (int i = 0; i < n; ++i) {
+    const double yv = q_y;
+    q_y = y[min(i + 1, n - 1)];
+    y[i] = inv * yv;
   }
 }
 
@@ -526,6 +542,7 @@ __device__ double tri_lowest_wg(const double* __restrict__ a, const double* __re
     __syncthreads();
     const double nhi = f < npts ? lo + (hi - lo) * ((double)(f + 1) * inv_seg) : hi;
     const double nlo = f > 0 ? lo + (hi - lo) * ((double)f * inv_seg) : lo;
+    if (nlo == lo && nhi == hi) break;  // the points no longer split the interval
     lo = nlo;
     hi = nhi;
   }
@@ -912,29 +929,40 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 constexpr int kLdA = kEigSmall + 1;  // leading dimension of the reduced matrix in shared memory
 constexpr int kEigWaves = 8;        // waves of the small eigen kernel
 
+// a - v qc - q vc: the rank-2 update of one element, one expression for the
+// stored matrix and for the next column every wave forms in registers
+__device__ __forceinline__ double rank2_update(double a, double v, double qc, double q, double vc) {
+  return a - v * qc - q * vc;
+}
+
 // Householder reduction of the symmetric n x n matrix sA (column-major,
 // leading dimension kLdA, n <= 65) to tridiagonal form T = Q^T A Q by the W
 // waves of the workgroup.  Step i reflects rows/columns i+1..n-1: lane l of
 // every wave owns row i+1+l of the trailing block (at most 64 rows) and every
-// wave forms the same reflector v; wave w takes the columns w, w+W, ... of the
-// product p = tau A' v (partial sums combined in shared memory, fixed order)
-// and of the symmetric rank-2 update A' -= v q^T + q v^T, with the other
-// lanes' values of v and q broadcast through scalar registers.  Reflector i
-// goes to sR[64 i ..], its factor to tau[i]; d[0..n) and e[0..n-1) receive T.
+// wave forms the same reflector v from the column it holds in registers;
+// wave w takes the columns w, w+W, ... of the product p = tau A' v (partial
+// sums combined in shared memory, fixed order) and of the symmetric rank-2
+// update A' -= v q^T + q v^T, with the other lanes' values of v and q
+// broadcast through scalar registers.  Every wave also applies the update to
+// its own copy of column i+1 (read before anyone writes it), which is the
+// next step's column: the next reflector is formed before the barrier that
+// publishes the update.  Reflector i goes to sR[64 i ..], its factor to
+// tau[i]; d[0..n) and e[0..n-1) receive T.
 template <int W>
 __device__ void tridiagonalize_wg(double* __restrict__ sA, int n, double* __restrict__ sR,
                                   double* __restrict__ d, double* __restrict__ e,
                                   double* __restrict__ tau, double* __restrict__ s_p) {
   constexpr int U = 64 / W;  // columns per wave at most
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // column 0, rows 1..n-1, lane l holding row 1+l
+  double x = n > 2 && lane < n - 1 ? sA[1 + lane] : 0.0;
+  double d_cur = sA[0];  // diagonal element of the current column
   for (int i = 0; i + 2 < n; ++i) {
     const int t = n - 1 - i;  // trailing order
     const bool act = lane < t;
     const int r = act ? i + 1 + lane : n - 1;  // rows past the end read a valid row
-    const double* col = sA + i * kLdA;
-    const double x = act ? col[r] : 0.0;
-    // identical in every wave (same values, same order): the branch below is
-    // uniform over the workgroup
+    // identical in every wave (same values, same order): every branch below
+    // is uniform over the workgroup
     const double s2 = wave_sum_dpp(x * x);
     const double x0 = lane_value(x, 0);
     const double sigma = s2 - x0 * x0;
@@ -943,42 +971,50 @@ __device__ void tridiagonalize_wg(double* __restrict__ sA, int n, double* __rest
       alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
       v = lane == 0 ? x0 - alpha : x;
       tf = 1.0 / (s2 - x0 * alpha);  // 2 / (v.v)
-      double pp = 0.0;
+    }
+    __syncthreads();  // the previous step's update is visible
+    double av[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = w + u * W;
-        const int cc = min(c, t - 1);
-        const double vc = c < t ? lane_value(v, cc) : 0.0;
-        pp += sA[(i + 1 + cc) * kLdA + r] * vc;
-      }
-      s_p[w * 64 + lane] = act ? pp : 0.0;
-      __syncthreads();
-      double p = 0.0;
+    for (int u = 0; u < U; ++u) av[u] = sA[(i + 1 + min(w + u * W, t - 1)) * kLdA + r];
+    const double x1 = sA[(i + 1) * kLdA + r];  // column i+1 before this step's update
+    double pp = 0.0;
 #pragma unroll
-      for (int q = 0; q < W; ++q) p += s_p[q * 64 + lane];
-      p *= tf;
-      const double K = 0.5 * tf * wave_sum_dpp(v * p);
-      const double q = p - K * v;
-      double av[U];
+    for (int u = 0; u < U; ++u) {
+      const int c = w + u * W;
+      const double vc = c < t ? lane_value(v, min(c, t - 1)) : 0.0;
+      pp += av[u] * vc;
+    }
+    s_p[w * 64 + lane] = act ? pp : 0.0;
+    __syncthreads();
+    double p = 0.0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) av[u] = sA[(i + 1 + min(w + u * W, t - 1)) * kLdA + r];
+    for (int q = 0; q < W; ++q) p += s_p[q * 64 + lane];
+    p *= tf;
+    const double K = 0.5 * tf * wave_sum_dpp(v * p);
+    const double q = p - K * v;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = w + u * W;
-        if (c < t) {
-          const double vc = lane_value(v, c), qc = lane_value(q, c);
-          if (act) sA[(i + 1 + c) * kLdA + r] = av[u] - v * qc - q * vc;
-        }
+    for (int u = 0; u < U; ++u) {
+      const int c = w + u * W;
+      if (c < t) {
+        const double vc = lane_value(v, c), qc = lane_value(q, c);
+        if (act) sA[(i + 1 + c) * kLdA + r] = rank2_update(av[u], v, qc, q, vc);
       }
     }
+    // the next column: rows i+1.. of updated column i+1; row i+1 is its
+    // diagonal element, rows i+2.. move down one lane
+    const double xn = act ? rank2_update(x1, v, lane_value(q, 0), q, lane_value(v, 0)) : 0.0;
+    const double d_next = lane_value(xn, 0);
+    const double xs = __shfl_down(xn, 1);
+    x = lane + 1 < t ? xs : 0.0;
     if (threadIdx.x == 0) {
-      d[i] = col[i];
+      d[i] = d_cur;
       e[i] = alpha;
       tau[i] = tf;
     }
+    d_cur = d_next;
     if (w == 0) sR[i * 64 + lane] = v;
-    __syncthreads();
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     if (n >= 2) {
       d[n - 2] = sA[(n - 2) * kLdA + n - 2];

@@ -413,9 +413,9 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ a, const d
 // loads the next row's shared-memory operands one iteration ahead, so the
 // dependent chain runs register to register; the row interchanges are
 // selects, not branches.  y is normalised on return.
-__device__ void tri_inverse_iteration(const double* __restrict__ a, const double* __restrict__ b, int n,
-                                      double lam, double scale, double* __restrict__ y,
-                                      double* __restrict__ wk) {
+__device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int n, double lam, double scale, double* __restrict__ y,
+                                                     double* __restrict__ wk) {
   // Gaussian elimination with partial pivoting of T - lam I (one extra
   // superdiagonal of fill-in), the row being eliminated carried in
   // registers; stored as multipliers dl, reciprocal pivots rdm,
@@ -504,9 +504,9 @@ __device__ void tri_inverse_iteration(const double* __restrict__ a, const double
 // subintervals per round, the first point above the eigenvalue found from
 // the waves' ballots), then inverse iteration by thread 0.  Every thread
 // gets the eigenvalue; y (n doubles) is complete when it returns.
-__device__ double tri_lowest_wg(const double* __restrict__ a, const double* __restrict__ b, int n,
-                                double* __restrict__ y, double* __restrict__ wk,
-                                unsigned long long* s_bal) {
+__device__ __forceinline__ double tri_lowest_wg(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                                double* __restrict__ y, double* __restrict__ wk,
+                                                unsigned long long* s_bal) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
   const int npts = blockDim.x;
   if (n == 1) {

@@ -246,26 +246,37 @@ __global__ void __launch_bounds__(256) k_cd1(Cd1Args A) {
     t_last = t_now;                              \
   }
   for (; step < A.nsteps; ++step) {
-    // ---- phase A: lists of D, then (overlapped) this lane's first column
-    // entry and its probe, H_DD and the line search
+    // ---- phase A: lists of D; every lane forms its first column entry and
+    // issues the first probe load of it; while those loads are in flight,
+    // wave 0 forms H_DD (its integrals loaded before the entry's, summed by a
+    // fixed-order wave sum with no workgroup barrier) and takes the line
+    // search; then the probes complete
     make_lists_block(sa, sb, H.N, L);
     __syncthreads();
+    const int nt = diag_terms(L);
+    DiagLoad dg0{0.0, 0.0, 0.0}, dg1{0.0, 0.0, 0.0};
+    if (tid < 64) {
+      if (tid < nt) dg0 = diag_term_load(H, L, tid);
+      if (tid + 64 < nt) dg1 = diag_term_load(H, L, tid + 64);
+    }
     const int64_t e0 = 1 + gtid;
     uint64_t ja0 = 0, jb0 = 0;
     double H0 = 0.0;
     SlotVal sv0{0, 0, 0.0, 0.0};
+    SlotVal first{kEmpty, 0, 0.0, 0.0};
     int64_t slot0 = -1;
     int probes0 = 0;
     if (e0 < A.n_col) {
       H0 = column_entry(H, L, sa, sb, e0, 0.0, &ja0, &jb0);
-      slot0 = table_find(A.T, A.mask, ja0, jb0, &probes0, &sv0);
+      first = slot_load(&A.T[hash_key(ja0, jb0) & A.mask]);
     }
-    {
-      double part = 0.0;
-      const int nt = diag_terms(L);
-      for (int t = tid; t < nt; t += blockDim.x) part += diag_term(H, L, t);
-      Cand dummy{0.0, 0, 0, 0, 0.0, 0.0};
-      block_reduce<kMaxWaves>(dummy, part, s_cand, s_sum);
+    if (tid < 64) {
+      double part = dg0.f * (dg0.x - dg0.y) + dg1.f * (dg1.x - dg1.y);
+      for (int t = tid + 128; t < nt; t += 64) part += diag_term(H, L, t);
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(part, off);
+        part = (tid & off) ? (o + part) : (part + o);
+      }
       if (tid == 0) {
         const double Hii = part;
         const double mud = dd_val(mu);
@@ -286,6 +297,7 @@ __global__ void __launch_bounds__(256) k_cd1(Cd1Args A) {
         s_flags = 0;
       }
     }
+    if (e0 < A.n_col) slot0 = table_find_from(A.T, A.mask, ja0, jb0, first, &probes0, &sv0);
     __syncthreads();
     const double eta = s_bc[0], Hii = s_bc[1];
     mu = dd{s_bc[2], s_bc[3]};

@@ -157,6 +157,38 @@ __device__ inline int64_t table_find(const Slot* __restrict__ T, uint64_t mask, 
   return -1;
 }
 
+// table_find with the first probe's slot already loaded (issued early by the
+// caller, so its latency runs under other work); same result as table_find
+__device__ inline int64_t table_find_from(const Slot* __restrict__ T, uint64_t mask, uint64_t a, uint64_t b,
+                                          SlotVal first, int* probes, SlotVal* val) {
+  uint64_t idx = hash_key(a, b) & mask;
+  for (int n = 0; n < kMaxProbe; ++n) {
+    SlotVal v = n == 0 ? first : slot_load(&T[idx]);
+    if (v.ka == kEmpty) {
+      *probes = n + 1;
+      return -1;
+    }
+    if (v.ka == a) {
+      if (v.kb == kPending) {
+        int spin = 0;
+        do {
+          v.kb = ld_co(&T[idx].kb);
+        } while (v.kb == kPending && ++spin < (1 << 20));
+        v.c = ld_co(&T[idx].c);
+        v.b = ld_co(&T[idx].b);
+      }
+      if (v.kb == b) {
+        *probes = n + 1;
+        *val = v;
+        return (int64_t)idx;
+      }
+    }
+    idx = (idx + 1) & mask;
+  }
+  *probes = kMaxProbe;
+  return -1;
+}
+
 // Find or insert; returns slot, or -1 on probe overflow / publish timeout
 // (*err gets the flag).  *inserted = 1 if this call claimed the slot.  The
 // slot's c and b are returned in *val (zeros for a fresh slot).
@@ -444,6 +476,31 @@ __device__ inline double diag_term(const Ham& H, const Lists& L, int t) {
   }
   t -= L.nb * L.nb;
   return ERI(H, L.oa[t / L.nb], L.oa[t / L.nb], L.ob[t % L.nb], L.ob[t % L.nb]);
+}
+
+// diag_term(t) as f (x - y) with its integrals loaded and the arithmetic left
+// to the caller (y = 0 and f = 1 where diag_term has no exchange part: the
+// same value bit for bit)
+struct DiagLoad {
+  double x, y, f;
+};
+
+__device__ inline DiagLoad diag_term_load(const Ham& H, const Lists& L, int t) {
+  if (t < L.na) return DiagLoad{H.h[L.oa[t] * H.N + L.oa[t]], 0.0, 1.0};
+  t -= L.na;
+  if (t < L.nb) return DiagLoad{H.h[L.ob[t] * H.N + L.ob[t]], 0.0, 1.0};
+  t -= L.nb;
+  if (t < L.na * L.na) {
+    int p = L.oa[t / L.na], q = L.oa[t % L.na];
+    return DiagLoad{ERI(H, p, p, q, q), ERI(H, p, q, q, p), 0.5};
+  }
+  t -= L.na * L.na;
+  if (t < L.nb * L.nb) {
+    int p = L.ob[t / L.nb], q = L.ob[t % L.nb];
+    return DiagLoad{ERI(H, p, p, q, q), ERI(H, p, q, q, p), 0.5};
+  }
+  t -= L.nb * L.nb;
+  return DiagLoad{ERI(H, L.oa[t / L.nb], L.oa[t / L.nb], L.ob[t % L.nb], L.ob[t % L.nb]), 0.0, 1.0};
 }
 
 // single p -> r within spin sigma (same: occupied list of that spin, other:

@@ -58,7 +58,9 @@ typedef struct {
                             2 = Neel determinant + sqrt(-lambda) times the lowest eigenvector
                             of H on it and the nonzero entries of its column */
   int grid_blocks;       /* workgroups of the single-coordinate persistent kernel; 0 = auto */
-  int block_threads;     /* threads per workgroup (64..256, multiple of 64); 0 = 256 */
+  int block_threads;     /* threads per workgroup of the single-coordinate kernel (64..256,
+                            multiple of 64); 0 = 128 when the column gives every lane one
+                            entry with one workgroup per compute unit, else 256 */
   int reserved0;
   void* workspace;          /* optional caller-owned device memory for the hash table and
                                buffers (e.g. a torch tensor); NULL = library allocates */

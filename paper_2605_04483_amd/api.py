@@ -32,7 +32,7 @@ def _up(a):
 
 
 def make_opts(table_slots=1 << 22, load_factor=0.79, z_threshold=0.0, dx_damping=0.9,
-              dx_threshold=0.0, init_kind=0, grid_blocks=0, block_threads=256, workspace=None,
+              dx_threshold=0.0, init_kind=0, grid_blocks=0, block_threads=0, workspace=None,
               stream=None):
     o = cdfci_opts()
     o.table_slots = int(table_slots)

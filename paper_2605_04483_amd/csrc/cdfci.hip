@@ -1130,7 +1130,7 @@ void fill_defaults(cdfci_opts& o) {
   if (o.table_slots == 0) o.table_slots = 1ull << 22;
   if (o.load_factor <= 0.0) o.load_factor = 0.79;
   if (o.dx_damping <= 0.0) o.dx_damping = 0.9;
-  if (o.block_threads <= 0) o.block_threads = 256;
+  if (o.block_threads < 0) o.block_threads = 0;  // 0: chosen from the column size at set-up
 }
 
 int ensure_list(cdfci_ctx* c, int64_t n) {
@@ -1169,6 +1169,10 @@ int setup_and_init(cdfci_ctx* c, int init_kind, uint64_t neel_a, uint64_t neel_b
   // persistent grid: enough lanes for one column entry each, bounded by residency
   int dev_cus = 0;
   HIP_TRY(hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  // automatic workgroup size: 128 threads while the column still gives every
+  // lane one entry within one workgroup per compute unit (a shorter tail of
+  // slow probes per workgroup), else 256
+  if (c->block == 0) c->block = (c->n_col + 127) / 128 <= dev_cus ? 128 : 256;
   int per_cu = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cd1, c->block, 0));
   int max_grid = std::max(1, per_cu) * dev_cus;

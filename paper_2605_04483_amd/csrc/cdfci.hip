@@ -2520,7 +2520,7 @@ struct cdfci_xctx {
   XCtl* x = nullptr;
   XPartial* parts = nullptr;
   double* dE = nullptr;
-  int grid = 0, max_parts = 0;
+  int grid = 0, block = 256, max_parts = 0;
   int64_t n_col = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool poisoned = false;
@@ -2586,12 +2586,12 @@ int x_launch(cdfci_xctx* X, XArgs& A) {
   if (!X->grid_fixed) {
     int cus = 0, per_cu = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, X->base->device));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, X->block, 0));
     X->grid = std::max(1, std::min(X->grid, std::min(std::max(1, per_cu) * cus, X->max_parts / 2)));
     X->grid_fixed = true;
   }
   void* args[] = {&A};
-  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(X->grid), dim3(256), args, 0, s));
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(X->grid), dim3(X->block), args, 0, s));
   return 0;
 }
 
@@ -2605,7 +2605,13 @@ int x_alloc(cdfci_xctx* X) {
   X->mask = X->nslots - 1;
   X->max_entries = (uint64_t)(o.load_factor * (double)X->nslots);
   X->n_col = X->kind ? column_count_k(c->N, c->na, c->nb) : column_count(c->N, c->na, c->nb);
-  X->grid = (int)std::max<int64_t>(1, (X->n_col - 1 + 255) / 256);
+  // workgroup size: 128 threads while the column (diagonal excluded) still
+  // gives every lane one entry with one workgroup per compute unit (a shorter
+  // tail of slow probes per workgroup), else 256
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  X->block = (X->n_col - 1 + 127) / 128 <= cus ? 128 : 256;
+  X->grid = (int)std::max<int64_t>(1, (X->n_col - 1 + X->block - 1) / X->block);
   X->max_parts = std::max(X->grid, kXSelParts);
   HIP_TRY(hipMalloc(&X->K, X->nslots * sizeof(XKey)));
   HIP_TRY(hipMalloc(&X->R, X->nslots * 2 * n * sizeof(double)));

@@ -135,6 +135,23 @@ def test_abinitio_n24_spin_polarised_trajectory(api):
     ctx.close()
 
 
+@pytest.mark.parametrize("block", [64, 256])
+def test_abinitio_n24_trajectory_other_workgroup_sizes(api, block):
+    """The spin-polarised trajectory with workgroups of 64 lanes (the grid is
+    capped at one workgroup per compute unit, so lanes take two or more column
+    entries each) and of 256 lanes (the size for larger columns); the default
+    for this column is 128."""
+    N, na, nb = 24, 6, 5
+    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    K = 300
+    orc = ocd.cd_run(h, eri, keys, c0, max_steps=K)
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 22, block_threads=block)
+    tr = api.cdfci_step_trace(ctx, K)
+    _compare_traj(tr, orc, K)
+    ctx.close()
+
+
 def test_abinitio_n24_full_size(api):
     """24 orbitals, 6+6 electrons, naux 72, 2^28 slots (the benchmark's
     configuration): trajectory parity over the first steps, the maintained

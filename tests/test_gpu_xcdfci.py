@@ -195,6 +195,36 @@ def test_table_full_and_empty_calls(api):
     x.close()
 
 
+def test_n36_sampled_rows_256_lane_workgroups(api):
+    """N = 36, 8 + 8 (a 71,793-entry column: the kernel runs 256-lane
+    workgroups there, 128 below 32,768 entries), 2 states, 100 iterations at
+    tau = 0: S and Q against C^T C and C^T B over the exported rows, and B on
+    sampled determinants against (H C)_j over the oracle's column of j."""
+    N, na, nb, naux = 36, 8, 8, 108
+    h, eri = synth_inputs.ab_initio(N, naux, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
+    n = 2
+    x = api.cdfci_xinit(h, eri, na, nb, n, table_slots=1 << 24)
+    st = api.cdfci_xstep(x, 100)
+    assert st["steps"] == 100
+    ka, kb, C, B = api.cdfci_xexport(x)
+    S, Q = api.cdfci_xmatrices(x)
+    assert np.max(np.abs(S - C.T @ C)) <= 1e-10 * np.max(np.abs(S))
+    assert np.max(np.abs(Q - C.T @ B)) <= 1e-10 * np.max(np.abs(Q))
+    rows = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(ka, kb))}
+    rng = np.random.default_rng(36)
+    nz = np.flatnonzero(np.any(C != 0.0, axis=1))
+    pick = list(rng.choice(nz, 4, replace=False)) + list(rng.choice(len(ka), 4, replace=False))
+    for r in pick:
+        cka, ckb, cv = ocd.column(h, eri, int(ka[r]), int(kb[r]))
+        ref = np.zeros(n)
+        for a, b, v in zip(cka, ckb, cv):
+            j = rows.get((int(a), int(b)))
+            if j is not None:
+                ref += v * C[j]
+        assert np.max(np.abs(B[r] - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref))), r
+    x.close()
+
+
 def test_63_orbitals(api):
     """Keys using bit 62: the first iterations against the oracle."""
     N, na, nb = 63, 2, 1

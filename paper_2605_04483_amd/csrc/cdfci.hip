@@ -345,8 +345,13 @@ __global__ void __launch_bounds__(256) k_cd1(Cd1Args A) {
           bnew += delta;
         }
       } else if (fabs(delta) >= A.tau) {
+        // the find ended at an empty slot (probes - 1 occupied ones before
+        // it) unless it ran out of probes: the insert starts there
         int ins = 0;
-        slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
+        slot = probes < kMaxProbe
+                   ? table_upsert_at(A.T, A.mask, ja, jb, (hash_key(ja, jb) + (uint64_t)(probes - 1)) & A.mask,
+                                     probes - 1, &ins, &probes, &err, &sv)
+                   : table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
         if (slot >= 0) {
           atomic_add_f64(&A.T[slot].b, delta);
           cj = sv.c;

@@ -243,6 +243,68 @@ __device__ inline int64_t table_upsert(Slot* __restrict__ T, uint64_t mask, uint
   return -1;
 }
 
+// table_upsert for a key whose find has just ended at the empty slot idx0
+// after nprev occupied slots: the claim is tried there at once, with no reload
+// and no second walk of the chain before it (those slots held other keys, and
+// within an iteration no other lane inserts this key).  If another key took
+// idx0 meanwhile, the walk continues from there as in table_upsert.
+__device__ inline int64_t table_upsert_at(Slot* __restrict__ T, uint64_t mask, uint64_t a, uint64_t b,
+                                          uint64_t idx0, int nprev, int* inserted, int* probes, int* err,
+                                          SlotVal* val) {
+  uint64_t idx = idx0;
+  *inserted = 0;
+  for (int n = nprev; n < kMaxProbe; ++n) {
+    SlotVal v;
+    if (n == nprev) {
+      v = SlotVal{kEmpty, 0, 0.0, 0.0};
+    } else {
+      v = slot_load(&T[idx]);
+    }
+    uint64_t ka = v.ka;
+    if (ka == kEmpty) {
+      uint64_t old = atomicCAS((unsigned long long*)&T[idx].ka, (unsigned long long)kEmpty,
+                               (unsigned long long)a);
+      if (old == kEmpty) {
+        st_co(&T[idx].kb, b);
+        *inserted = 1;
+        *probes = n + 1;
+        *val = SlotVal{a, b, 0.0, 0.0};
+        return (int64_t)idx;
+      }
+      ka = old;
+      v.kb = ld_co(&T[idx].kb);
+      v.c = ld_co(&T[idx].c);
+      v.b = ld_co(&T[idx].b);
+    }
+    if (ka == a) {
+      uint64_t kb = v.kb;
+      if (kb == kPending) {
+        int spin = 0;
+        do {
+          kb = ld_co(&T[idx].kb);
+        } while (kb == kPending && ++spin < (1 << 20));
+        if (kb == kPending) {
+          *err |= kErrPublish;
+          return -1;
+        }
+        v.c = ld_co(&T[idx].c);
+        v.b = ld_co(&T[idx].b);
+      }
+      if (kb == b) {
+        *probes = n + 1;
+        v.ka = a;
+        v.kb = b;
+        *val = v;
+        return (int64_t)idx;
+      }
+    }
+    idx = (idx + 1) & mask;
+  }
+  *probes = kMaxProbe;
+  *err |= kErrTableFull;
+  return -1;
+}
+
 // ---------------------------------------------------------------- double-double
 
 struct dd {

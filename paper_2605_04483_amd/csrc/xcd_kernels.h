@@ -188,6 +188,48 @@ __device__ inline int64_t xkey_upsert(XKey* __restrict__ K, uint64_t mask, uint6
   return -1;
 }
 
+// xkey_upsert for a key whose find has just ended at the empty slot idx0
+// after nprev occupied slots: the claim is tried there at once (within an
+// iteration no other lane inserts this key and nothing is deleted, so the
+// slots before it hold other keys); if another key took idx0 meanwhile, the
+// walk continues from there as in xkey_upsert.
+__device__ inline int64_t xkey_upsert_at(XKey* __restrict__ K, uint64_t mask, uint64_t a, uint64_t b, uint64_t idx0,
+                                         int nprev, int* inserted, int* probes, int* err) {
+  uint64_t idx = idx0;
+  *inserted = 0;
+  for (int n = nprev; n < kMaxProbe; ++n) {
+    uint64_t ka = n == nprev ? kEmpty : ld_co(&K[idx].ka);
+    if (ka == kEmpty) {
+      const uint64_t old = atomicCAS((unsigned long long*)&K[idx].ka, (unsigned long long)kEmpty,
+                                     (unsigned long long)a);
+      if (old == kEmpty) {
+        st_co(&K[idx].kb, b);
+        *inserted = 1;
+        *probes = n + 1;
+        return (int64_t)idx;
+      }
+      ka = old;
+    }
+    if (ka == a) {
+      uint64_t kb = ld_co(&K[idx].kb);
+      int spin = 0;
+      while (kb == kPending && ++spin < (1 << 20)) kb = ld_co(&K[idx].kb);
+      if (kb == kPending) {
+        *err |= kErrPublish;
+        return -1;
+      }
+      if (kb == b) {
+        *probes = n + 1;
+        return (int64_t)idx;
+      }
+    }
+    idx = (idx + 1) & mask;
+  }
+  *probes = kMaxProbe;
+  *err |= kErrTableFull;
+  return -1;
+}
+
 // ---------------------------------------------------------------- small dense algebra
 
 // Ascending generalised eigenvalues of the pencil (Q, S), n <= kXMax, by one
@@ -472,8 +514,13 @@ __global__ void __launch_bounds__(256) k_xiter(XArgs A) {
       int64_t slot = xkey_find(A.K, A.mask, ja, jb, &probes);
       const bool big = fabs(eta * Hj) * ginf >= A.tau;
       if (slot < 0 && big) {
+        // the find ended at an empty slot unless it ran out of probes: the
+        // insert starts there
         int ins = 0;
-        slot = xkey_upsert(A.K, A.mask, ja, jb, &ins, &probes, &err);
+        slot = probes < kMaxProbe
+                   ? xkey_upsert_at(A.K, A.mask, ja, jb, (hash_key(ja, jb) + (uint64_t)(probes - 1)) & A.mask,
+                                    probes - 1, &ins, &probes, &err)
+                   : xkey_upsert(A.K, A.mask, ja, jb, &ins, &probes, &err);
         my_ins += ins;
       }
       my_probe = max(my_probe, probes);

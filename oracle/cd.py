@@ -23,6 +23,27 @@ from . import fci
 _lib = None
 
 
+def bind(path):
+    """Load a build of cd_serial.cpp from `path` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    L.oracle_line_search.restype = ctypes.c_double
+    L.oracle_line_search.argtypes = [ctypes.c_double] * 3
+    L.oracle_entry.restype = ctypes.c_double
+    L.oracle_entry.argtypes = [ctypes.c_int, dp, dp] + [ctypes.c_uint64] * 4
+    L.oracle_column.restype = ctypes.c_int64
+    L.oracle_column.argtypes = [ctypes.c_int, dp, dp, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.c_int64, up, up, dp]
+    L.oracle_cd_run.restype = ctypes.c_int
+    L.oracle_cd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, up, up, dp,
+                                ctypes.c_double, ctypes.c_int64, ctypes.c_double,
+                                ctypes.c_double, dp, up, up, dp, dp, ip, dp, dp, ip, ip,
+                                ctypes.c_int64, up, up, dp, dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -30,23 +51,7 @@ def lib():
 
         if not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        up = ctypes.POINTER(ctypes.c_uint64)
-        ip = ctypes.POINTER(ctypes.c_int64)
-        L.oracle_line_search.restype = ctypes.c_double
-        L.oracle_line_search.argtypes = [ctypes.c_double] * 3
-        L.oracle_entry.restype = ctypes.c_double
-        L.oracle_entry.argtypes = [ctypes.c_int, dp, dp] + [ctypes.c_uint64] * 4
-        L.oracle_column.restype = ctypes.c_int64
-        L.oracle_column.argtypes = [ctypes.c_int, dp, dp, ctypes.c_uint64, ctypes.c_uint64,
-                                    ctypes.c_int64, up, up, dp]
-        L.oracle_cd_run.restype = ctypes.c_int
-        L.oracle_cd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, up, up, dp,
-                                    ctypes.c_double, ctypes.c_int64, ctypes.c_double,
-                                    ctypes.c_double, dp, up, up, dp, dp, ip, dp, dp, ip, ip,
-                                    ctypes.c_int64, up, up, dp, dp]
-        _lib = L
+        _lib = bind(LIB)
     return _lib
 
 
@@ -142,7 +147,9 @@ class CDResult:
 
 
 def cd_run(h, eri, init_keys, init_c, tau=0.0, max_steps=1000, theta=0.9, dx_tol=0.0,
-           trajectory=True, export=False):
+           trajectory=True, export=False, library=None):
+    """Algorithm 1 from c^(0) = sum init_c[t] e_{init_keys[t]}.  `library` is
+    a build bound by bind() (default: the oracle's own build)."""
     N = h.shape[0]
     h = np.ascontiguousarray(h, dtype=np.float64)
     eri = np.ascontiguousarray(eri, dtype=np.float64)
@@ -162,7 +169,7 @@ def cd_run(h, eri, init_keys, init_c, tau=0.0, max_steps=1000, theta=0.9, dx_tol
     nel = np.zeros(1, np.int64)
     cap = 0
     oa = ob = oc = ov = None
-    L = lib()
+    L = library if library is not None else lib()
 
     def call(cap, oa, ob, oc, ov):
         return L.oracle_cd_run(N, _p(h, ctypes.c_double), _p(eri, ctypes.c_double), len(ia),

@@ -65,6 +65,8 @@ def mcdfci_run(h, eri, init_keys, init_c, m, tau=0.0, max_steps=100, theta=0.9, 
     energies = []
     selections = []
     gaps = []
+    etas = []
+    gammas = []
     for step in range(max_steps):
         g = {j: abs(4.0 * b.get(j, 0.0) + 4.0 * mu * c.get(j, 0.0)) for j in cand}
         order = sorted(cand, key=lambda j: (-g[j], _order_key(j)))
@@ -126,6 +128,8 @@ def mcdfci_run(h, eri, init_keys, init_c, m, tau=0.0, max_steps=100, theta=0.9, 
         d = nrm if step == 0 else theta * d + (1.0 - theta) * nrm
         energies.append(alpha / mu)
         selections.append(list(I))
+        etas.append(np.array(eta, dtype=np.float64))
+        gammas.append(float(gamma))
         cand = newcand
         if d < dx_tol:
             break
@@ -134,5 +138,7 @@ def mcdfci_run(h, eri, init_keys, init_c, m, tau=0.0, max_steps=100, theta=0.9, 
     st.energies = np.array(energies)
     st.selections = selections
     st.gaps = np.array(gaps)
+    st.etas = etas        # per step: eta (aligned with selections)
+    st.gammas = gammas    # per step: gamma
     st.energy = alpha / mu
     return st

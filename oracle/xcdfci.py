@@ -48,6 +48,10 @@ from . import cd as cdmod
 from . import fci
 
 
+# relative window within which a followed pick counts as tying the maximum
+FOLLOW_REL = 1e-13
+
+
 def _order_key(k):
     return (k[1], k[0])
 
@@ -91,7 +95,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
     """column (optional): key -> (alpha keys, beta keys, values) with the
     diagonal first, for Hamiltonians not given by integrals (h, eri unused).
     follow (optional): selections to take where the argmax is tied, i.e.
-    where follow[step] has ||G||_inf within a relative 1e-9 of the largest
+    where follow[step] has ||G||_inf within a relative FOLLOW_REL of the largest
     (another run's choice among equals); the first step where it is not is
     recorded in follow_failed."""
     n = C0.shape[1]
@@ -132,7 +136,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
     S64 = np.array(S, dtype=np.float64)
     # first coordinate: argmax over every stored entry
     cand = set(C.keys())
-    energies, selections, gaps, etas = [], [], [], []
+    energies, selections, gaps, etas, ginfs = [], [], [], [], []
     d = 0.0
     follow_failed = None
     for step in range(max_steps):
@@ -141,8 +145,12 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
         order = sorted(cand, key=lambda j: (-gn[j], _order_key(j)))
         i = order[0]
         if follow is not None and step < len(follow) and follow_failed is None:
+            # a pick of the device's is followed only where it ties the
+            # maximum up to rounding (the values of both sides may differ in
+            # their last bits): spin-flip images and lattice symmetries give
+            # exact ties, anything farther apart is a different selection
             f = follow[step]
-            if f in gn and gn[f] >= gn[i] * (1.0 - 1e-9):
+            if f in gn and gn[f] >= gn[i] * (1.0 - FOLLOW_REL):
                 i = f
             else:
                 follow_failed = step
@@ -175,6 +183,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
         energies.append(shift + pencil_energies(np.array(Q, dtype=np.float64), np.array(S, dtype=np.float64)))
         selections.append(i)
         etas.append(eta)
+        ginfs.append(ginf)
         cand = newcand
         if d < dx_tol:
             break
@@ -184,6 +193,7 @@ def xcdfci_run(h, eri, init_keys, C0, tau=0.0, max_steps=100, theta=0.9, dx_tol=
     r.selections = selections
     r.gaps = np.array(gaps)
     r.eta = np.array(etas)
+    r.ginf = np.array(ginfs)  # ||g||_inf of each step's row update
     r.S = np.array(S, dtype=np.float64)
     r.Q = np.array(Q, dtype=np.float64)
     r.C = C

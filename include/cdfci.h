@@ -53,6 +53,10 @@ typedef struct {
   double z_threshold;    /* compression threshold tau on b updates (Sec. 3.1); default 0 */
   double dx_damping;     /* theta of the damped step accumulator (Sec. 4.1.3); 0 = 0.9 */
   double dx_threshold;   /* stop when the accumulator falls below this; 0 = never */
+  double energy_shift;   /* sigma: the solver minimises f for H - sigma I, which needs a
+                            negative lowest eigenvalue (Sec. 2.3, eq. (optimization)); every
+                            reported energy adds sigma back, the stored b is (H - sigma I) c
+                            and alpha = c^T (H - sigma I) c; 0 = no shift */
   int init_kind;         /* c^(0): 0 = model default (1 for integrals, 2 for lattices);
                             1 = lowest-h_pp (aufbau) determinant with c = sqrt(-H_00);
                             2 = Neel determinant + sqrt(-lambda) times the lowest eigenvector
@@ -89,8 +93,12 @@ int cdfci_workspace_size(int n_orb, int n_alpha, int n_beta, const cdfci_opts* o
 /* Create a context for an integral Hamiltonian (Sec. 2.2 eq. (general-ham),
  * Sec. 4.1.1 HamiltonianMolecule).  h: n_orb*n_orb row-major, symmetric.
  * eri: n_orb^4 row-major chemist (pq|rs), eri[((p*N+q)*N+r)*N+s], with the
- * 8-fold permutational symmetry.  Both host pointers, copied to the device.
- * Builds c^(0) per opts->init_kind and b^(0) = H c^(0) exactly (Alg. 1). */
+ * 8-fold permutational symmetry.  Each may be a host or a device pointer (an
+ * exception to the host-pointer convention); both are copied, the caller
+ * keeps ownership.  Builds c^(0) per opts->init_kind and b^(0) = H c^(0)
+ * exactly (Alg. 1).  opts->energy_shift sigma is applied as h - (sigma / n) I
+ * with n = n_alpha + n_beta, which on the n-electron space is H - sigma I;
+ * CDFCI_ERR_NOT_NEGATIVE if the start still has no negative energy. */
 int cdfci_init(const double* h, const double* eri, int n_orb, int n_alpha, int n_beta,
                const cdfci_opts* opts, cdfci_ctx** out);
 
@@ -170,8 +178,30 @@ int cdfci_export(cdfci_ctx* ctx, int64_t top_n, uint64_t* keys, double* c, doubl
 /* Profiling aid: device seconds that workgroup 0 of the single-coordinate
  * kernel has spent, since init, in its four phases: [0] choose-and-step
  * (H_DD, line search), [1] column scatter, [2] waiting at the device-wide
- * barrier, [3] combining the partial results.  seconds: 4 doubles. */
+ * barrier, [3] combining the partial results.  seconds: 4 doubles.  The
+ * timers are compiled into the kernel only with -DCDFCI_PHASE_TIMING;
+ * otherwise CDFCI_ERR_UNSUPPORTED. */
 int cdfci_phase_times(cdfci_ctx* ctx, double* seconds);
+
+/* Inspection of the multicoordinate step (Alg. 2, eq. (choose-I)), for
+ * parity tests.  Both need the context to be in the multicoordinate state
+ * (its last step had k > 1), else CDFCI_ERR_INVALID_ARG.
+ *
+ * cdfci_mc_candidates: the candidates the next k > 1 step chooses from (the
+ * stored determinants of the last step's columns and its chosen set, each
+ * once), in no particular order.  keys 2*cap uint64 (alpha, beta); g, cv, bv
+ * cap doubles each: the selection key |4 b^ + 4 mu c^| exactly as the
+ * selection forms it, and the stored c^ and b^, where c = s c^ and b = s b^
+ * with the lazy scale s of the multicoordinate state; mu_scale[0] = mu,
+ * mu_scale[1] = s.  Any output may be NULL; *count = candidates, at most cap
+ * written.  The state is not changed.
+ *
+ * cdfci_mc_selection: the chosen set of the last k > 1 step (in the
+ * selection's internal order) and its step eta (true scale): keys 2*cap
+ * uint64, eta cap doubles (may be NULL); *count = its size. */
+int cdfci_mc_candidates(cdfci_ctx* ctx, uint64_t* keys, double* g, double* cv, double* bv, int64_t cap,
+                        int64_t* count, double* mu_scale);
+int cdfci_mc_selection(cdfci_ctx* ctx, uint64_t* keys, double* eta, int64_t cap, int64_t* count);
 
 /* Restart (Sec. 4.1.3: checkpoints for termination and restart from stored
  * wavefunctions).  Replaces the context's state by the wavefunction

@@ -23,6 +23,7 @@ class cdfci_opts(ctypes.Structure):
         ("z_threshold", ctypes.c_double),
         ("dx_damping", ctypes.c_double),
         ("dx_threshold", ctypes.c_double),
+        ("energy_shift", ctypes.c_double),
         ("init_kind", ctypes.c_int),
         ("grid_blocks", ctypes.c_int),
         ("block_threads", ctypes.c_int),
@@ -141,6 +142,8 @@ SIGNATURES = [
     ("cdfci_export", ctypes.c_int, [_P, ctypes.c_int64, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_phase_times", ctypes.c_int, [_P, _DP]),
     ("cdfci_load", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64]),
+    ("cdfci_mc_candidates", ctypes.c_int, [_P, _UP, _DP, _DP, _DP, ctypes.c_int64, _I64P, _DP]),
+    ("cdfci_mc_selection", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_set_threshold", ctypes.c_int, [_P, ctypes.c_double]),
     ("cdfci_step_search", ctypes.c_int,
      [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _DP, _STP]),

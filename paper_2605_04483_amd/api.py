@@ -32,14 +32,15 @@ def _up(a):
 
 
 def make_opts(table_slots=1 << 22, load_factor=0.79, z_threshold=0.0, dx_damping=0.9,
-              dx_threshold=0.0, init_kind=0, grid_blocks=0, block_threads=0, workspace=None,
-              stream=None):
+              dx_threshold=0.0, energy_shift=0.0, init_kind=0, grid_blocks=0, block_threads=0,
+              workspace=None, stream=None):
     o = cdfci_opts()
     o.table_slots = int(table_slots)
     o.load_factor = float(load_factor)
     o.z_threshold = float(z_threshold)
     o.dx_damping = float(dx_damping)
     o.dx_threshold = float(dx_threshold)
+    o.energy_shift = float(energy_shift)
     o.init_kind = int(init_kind)
     o.grid_blocks = int(grid_blocks)
     o.block_threads = int(block_threads)
@@ -78,6 +79,7 @@ class Context:
         self.handle = handle
         self.workspace = workspace
         self.N, self.na, self.nb = N, na, nb
+        self.integrals = None
 
     def __del__(self):
         try:
@@ -92,18 +94,36 @@ class Context:
             self.workspace = None
 
 
+def _integral_arg(x):
+    """(pointer, keep-alive, host copy) of an integral array: a float64 torch
+    tensor on the GPU is passed as a device pointer, anything else as a
+    contiguous float64 host array."""
+    if type(x).__module__.startswith("torch"):
+        import torch
+
+        if x.is_cuda:
+            t = x.detach().to(torch.float64).contiguous()
+            return ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctypes.POINTER(ctypes.c_double)), t, t
+        x = x.detach().numpy()
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    return _dp(a), a, a
+
+
 def cdfci_init(h, eri, n_alpha, n_beta, use_torch_workspace=True, **kw):
+    """Context for integrals h (N x N) and eri (N^4, chemist): numpy arrays,
+    CPU tensors or float64 tensors on the GPU (passed as device pointers)."""
     L = _lib.load()
-    h = np.ascontiguousarray(h, dtype=np.float64)
-    eri = np.ascontiguousarray(eri, dtype=np.float64)
-    N = h.shape[0]
-    assert h.shape == (N, N) and eri.shape == (N, N, N, N)
+    hp, hk, href = _integral_arg(h)
+    ep, ek, eref = _integral_arg(eri)
+    N = int(hk.shape[0])
+    assert tuple(hk.shape) == (N, N) and tuple(ek.shape) == (N, N, N, N)
     opts = make_opts(**kw)
     ws = _torch_workspace(N, n_alpha, n_beta, opts) if use_torch_workspace else None
     ctx = ctypes.c_void_p()
-    _check(L.cdfci_init(_dp(h), _dp(eri), N, n_alpha, n_beta, ctypes.byref(opts), ctypes.byref(ctx)),
-           "cdfci_init")
-    return Context(ctx, ws, N, n_alpha, n_beta)
+    _check(L.cdfci_init(hp, ep, N, n_alpha, n_beta, ctypes.byref(opts), ctypes.byref(ctx)), "cdfci_init")
+    c = Context(ctx, ws, N, n_alpha, n_beta)
+    c.integrals = (href, eref)  # what the context was created from (checked by autograd)
+    return c
 
 
 def cdfci_init_hubbard(dims, t, U, n_alpha, n_beta, use_torch_workspace=True, **kw):
@@ -213,6 +233,37 @@ def cdfci_export(ctx, top_n=0):
     _check(L.cdfci_export(ctx.handle, int(top_n), _up(keys), _dp(c), _dp(b), n, ctypes.byref(cnt)),
            "cdfci_export")
     return keys[0:2 * n:2].copy(), keys[1:2 * n:2].copy(), c[:n], b[:n]
+
+
+def cdfci_mc_candidates(ctx):
+    """Candidates of the coming multicoordinate selection: dict with keys_alpha,
+    keys_beta, g (the selection key as the device forms it), c_hat, b_hat,
+    mu and the lazy scale s (c = s c_hat)."""
+    L = _lib.load()
+    cnt = ctypes.c_int64(0)
+    _check(L.cdfci_mc_candidates(ctx.handle, None, None, None, None, 0, ctypes.byref(cnt), None),
+           "cdfci_mc_candidates")
+    n = cnt.value
+    m = max(n, 1)
+    keys = np.zeros(2 * m, np.uint64)
+    g, c, b = np.zeros(m), np.zeros(m), np.zeros(m)
+    ms = np.zeros(2)
+    _check(L.cdfci_mc_candidates(ctx.handle, _up(keys), _dp(g), _dp(c), _dp(b), n, ctypes.byref(cnt),
+                                 _dp(ms)), "cdfci_mc_candidates")
+    return {"keys_alpha": keys[0:2 * n:2].copy(), "keys_beta": keys[1:2 * n:2].copy(), "g": g[:n],
+            "c_hat": c[:n], "b_hat": b[:n], "mu": float(ms[0]), "scale": float(ms[1])}
+
+
+def cdfci_mc_selection(ctx):
+    """Chosen set of the last multicoordinate step: (keys_alpha, keys_beta, eta)."""
+    L = _lib.load()
+    cnt = ctypes.c_int64(0)
+    _check(L.cdfci_mc_selection(ctx.handle, None, None, 0, ctypes.byref(cnt)), "cdfci_mc_selection")
+    n = cnt.value
+    keys = np.zeros(2 * max(n, 1), np.uint64)
+    eta = np.zeros(max(n, 1))
+    _check(L.cdfci_mc_selection(ctx.handle, _up(keys), _dp(eta), n, ctypes.byref(cnt)), "cdfci_mc_selection")
+    return keys[0:2 * n:2].copy(), keys[1:2 * n:2].copy(), eta[:n]
 
 
 def cdfci_load(ctx, keys_alpha, keys_beta, c):

@@ -237,14 +237,20 @@ __global__ void __launch_bounds__(256) k_cd1(Cd1Args A) {
   int stopped = 0, flags = 0;
   int my_probe = 0;
 
-  // phase timers of workgroup 0 (wall-clock ticks)
-  unsigned long long tp0 = 0, tp1 = 0, tp2 = 0, tp3 = 0, t_last = wall_clock64();
+  // phase timers of workgroup 0 (wall-clock ticks), compiled in only for
+  // profiling builds (-DCDFCI_PHASE_TIMING)
+  unsigned long long tp0 = 0, tp1 = 0, tp2 = 0, tp3 = 0;
+#ifdef CDFCI_PHASE_TIMING
+  unsigned long long t_last = wall_clock64();
 #define CDFCI_TICK(acc)                          \
   if (blockIdx.x == 0 && tid == 0) {             \
     unsigned long long t_now = wall_clock64();   \
     acc += t_now - t_last;                       \
     t_last = t_now;                              \
   }
+#else
+#define CDFCI_TICK(acc)
+#endif
   for (; step < A.nsteps; ++step) {
     // ---- phase A: lists of D; every lane forms its first column entry and
     // issues the first probe load of it; while those loads are in flight,
@@ -504,6 +510,10 @@ __global__ void __launch_bounds__(256) k_build_jk(const double* eri, int N, doub
 
 // ---------------------------------------------------------------------------
 // Table maintenance.
+
+__global__ void k_shift_diag(double* h, int N, double delta) {
+  for (int p = threadIdx.x; p < N; p += blockDim.x) h[p * N + p] -= delta;
+}
 
 __global__ void __launch_bounds__(256) k_clear_table(Slot* T, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1053,6 +1063,7 @@ struct cdfci_ctx {
   int max_parts = 0;
   int64_t n_col = 0;
   cdfci_opts opts;
+  double shift = 0.0;  // sigma of opts.energy_shift: the device holds H - sigma I
   int grid = 0, block = 256;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool poisoned = false;
@@ -1245,7 +1256,9 @@ int make_ctx(int N, int na, int nb, const cdfci_opts* opts, cdfci_ctx** out) {
   if ((o.table_slots & (o.table_slots - 1)) != 0 || o.table_slots < 64) return CDFCI_ERR_INVALID_ARG;
   if (o.block_threads % 64 != 0 || o.block_threads > 256) return CDFCI_ERR_INVALID_ARG;
   if (o.load_factor > 0.95) return CDFCI_ERR_INVALID_ARG;
+  if (!std::isfinite(o.energy_shift)) return CDFCI_ERR_INVALID_ARG;
   cdfci_ctx* c = new cdfci_ctx();
+  c->shift = o.energy_shift;
   c->N = N;
   c->na = na;
   c->nb = nb;
@@ -1264,9 +1277,12 @@ int upload(cdfci_ctx* c, const double* h, const double* eri) {
   size_t N = c->N;
   HIP_TRY(hipMalloc(&c->d_h, N * N * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_eri, N * N * N * N * sizeof(double)));
-  HIP_TRY(hipMemcpyAsync(c->d_h, h, N * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->d_eri, eri, N * N * N * N * sizeof(double), hipMemcpyHostToDevice,
-                         c->stream));
+  // host or device sources (unified addressing picks the direction)
+  HIP_TRY(hipMemcpyAsync(c->d_h, h, N * N * sizeof(double), hipMemcpyDefault, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_eri, eri, N * N * N * N * sizeof(double), hipMemcpyDefault, c->stream));
+  // energy shift: h - (sigma / n) I is H - sigma I on the n-electron space
+  if (c->shift != 0.0)
+    k_shift_diag<<<1, 64, 0, c->stream>>>(c->d_h, c->N, c->shift / (double)(c->na + c->nb));
   HIP_TRY(hipMalloc(&c->d_jk, 2 * N * N * N * sizeof(double)));
   const int64_t njk = (int64_t)N * N * N;
   k_build_jk<<<(int)((njk + 255) / 256), 256, 0, c->stream>>>(c->d_eri, c->N, c->d_jk);
@@ -1530,7 +1546,10 @@ static int run_cd1(cdfci_ctx* c, int64_t nsteps, double* trE, uint64_t* tra, uin
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (tracing) {
     int64_t done = h.steps - before.steps;
-    if (trE) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+    if (trE) {
+      HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < done; ++i) trE[i] += c->shift;
+    }
     if (tra) HIP_TRY(hipMemcpy(tra, da + before.steps, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
     if (trb) HIP_TRY(hipMemcpy(trb, db + before.steps, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
     if (treta) HIP_TRY(hipMemcpy(treta, deta + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
@@ -1547,7 +1566,7 @@ static int run_cd1(cdfci_ctx* c, int64_t nsteps, double* trE, uint64_t* tra, uin
     out->occupied = h.occupied;
     out->max_probe = h.max_probe;
     out->stopped = h.stopped;
-    out->energy = h.energy;
+    out->energy = h.energy + c->shift;
     out->dx = h.d;
     out->mu = h.mu_hi + h.mu_lo;
     out->alpha = h.al_hi + h.al_lo;
@@ -1695,6 +1714,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   const int64_t done = h.steps - before.steps;
   if (trE) {
     if (done > 0) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < done; ++i) trE[i] += c->shift;
     (void)hipFree(dE);
   }
   if (out) {
@@ -1705,7 +1725,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     out->occupied = h.occupied;
     out->max_probe = h.max_probe;
     out->stopped = h.stopped;
-    out->energy = h.energy;
+    out->energy = h.energy + c->shift;
     out->dx = h.d;
     out->mu = h.mu_hi + h.mu_lo;
     out->alpha = h.al_hi + h.al_lo;
@@ -1754,7 +1774,7 @@ int cdfci_energy(cdfci_ctx* c, int exact, double* energy) {
   int rc = ctl_read(c, &h);
   if (rc) return rc;
   if (!exact) {
-    *energy = (h.al_hi + h.al_lo) / (h.mu_hi + h.mu_lo);
+    *energy = (h.al_hi + h.al_lo) / (h.mu_hi + h.mu_lo) + c->shift;
     return 0;
   }
   hipStream_t s = c->stream;
@@ -1775,7 +1795,7 @@ int cdfci_energy(cdfci_ctx* c, int exact, double* energy) {
   double r[2];
   HIP_TRY(hipMemcpyAsync(r, c->dscratch + 2 * 4096, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *energy = r[0] / r[1];
+  *energy = r[0] / r[1] + c->shift;
   return 0;
 }
 
@@ -1847,8 +1867,8 @@ int cdfci_rdm_backward(cdfci_ctx* c, double grad_E, int64_t top_n, double* energ
   HIP_TRY(hipStreamSynchronize(s));
   if (herr) return CDFCI_ERR_TABLE_FULL;
   if (energy) {
-    energy[0] = he[4];
-    energy[1] = he[2];
+    energy[0] = he[4] + c->shift;
+    energy[1] = he[2] + c->shift;
   }
   return 0;
 }
@@ -1873,6 +1893,7 @@ int cdfci_column(cdfci_ctx* c, const uint64_t key[2], uint64_t* keys, double* va
   HIP_TRY(hipStreamSynchronize(c->stream));
   (void)hipFree(dk);
   (void)hipFree(dv);
+  vals[0] += c->shift;  // entries of H: the diagonal comes first
   return 0;
 }
 
@@ -1885,6 +1906,7 @@ int cdfci_entry(cdfci_ctx* c, const uint64_t k1[2], const uint64_t k2[2], double
   HIP_TRY(hipMemcpyAsync(value, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   (void)hipFree(d);
+  if (k1[0] == k2[0] && k1[1] == k2[1]) *value += c->shift;  // entries of H
   return 0;
 }
 
@@ -1947,6 +1969,74 @@ int cdfci_export(cdfci_ctx* c, int64_t top_n, uint64_t* keys, double* cv, double
     (void)hipFree(dk);
     (void)hipFree(dc);
     (void)hipFree(db);
+  }
+  return 0;
+}
+
+int cdfci_mc_candidates(cdfci_ctx* c, uint64_t* keys, double* g, double* cv, double* bv, int64_t cap,
+                        int64_t* count, double* mu_scale) {
+  if (!c || !count || cap < 0) return CDFCI_ERR_INVALID_ARG;
+  if (c->mode != 1 || !c->mst) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = c->stream;
+  McState st;
+  HIP_TRY(hipMemcpyAsync(&st, c->mst, sizeof(st), hipMemcpyDeviceToHost, s));
+  Ctl h;
+  int rc = ctl_read(c, &h);
+  if (rc) return rc;
+  CallBufs bufs;
+  const uint64_t m = std::max<uint64_t>((uint64_t)cap, 1);
+  uint64_t* dk;
+  double *dg, *dc, *db;
+  unsigned long long* dn;
+  HIP_TRY(bufs.alloc(&dk, 2 * m));
+  HIP_TRY(bufs.alloc(&dg, m));
+  HIP_TRY(bufs.alloc(&dc, m));
+  HIP_TRY(bufs.alloc(&db, m));
+  HIP_TRY(bufs.alloc(&dn, 1));
+  HIP_TRY(hipMemsetAsync(dn, 0, sizeof(unsigned long long), s));
+  k_mc_export_cands<<<1024, 256, 0, s>>>(c->T, c->cand, c->cnt, c->mst, c->ctl, dk, dg, dc, db,
+                                         (unsigned long long)cap, dn);
+  HIP_TRY(hipGetLastError());
+  unsigned long long n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, dn, sizeof(n), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *count = (int64_t)n;
+  const int64_t w = std::min<int64_t>((int64_t)n, cap);
+  if (w > 0) {
+    if (keys) HIP_TRY(hipMemcpyAsync(keys, dk, 2 * w * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    if (g) HIP_TRY(hipMemcpyAsync(g, dg, w * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (cv) HIP_TRY(hipMemcpyAsync(cv, dc, w * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (bv) HIP_TRY(hipMemcpyAsync(bv, db, w * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (mu_scale) {
+    mu_scale[0] = h.mu_hi + h.mu_lo;
+    mu_scale[1] = st.scale;
+  }
+  return 0;
+}
+
+int cdfci_mc_selection(cdfci_ctx* c, uint64_t* keys, double* eta, int64_t cap, int64_t* count) {
+  if (!c || !count || cap < 0) return CDFCI_ERR_INVALID_ARG;
+  if (!c->mst || !c->sel_a) return CDFCI_ERR_INVALID_ARG;
+  hipStream_t s = c->stream;
+  McState st;
+  HIP_TRY(hipMemcpyAsync(&st, c->mst, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t n = (int64_t)st.last_sel;
+  *count = n;
+  const int64_t w = std::min<int64_t>(n, cap);
+  if (w > 0) {
+    std::vector<uint64_t> a((size_t)w), b((size_t)w);
+    HIP_TRY(hipMemcpyAsync(a.data(), c->sel_a, w * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b.data(), c->sel_b, w * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    if (eta) HIP_TRY(hipMemcpyAsync(eta, c->eta, w * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (keys)
+      for (int64_t i = 0; i < w; ++i) {
+        keys[2 * i] = a[(size_t)i];
+        keys[2 * i + 1] = b[(size_t)i];
+      }
   }
   return 0;
 }
@@ -2501,6 +2591,9 @@ const char* cdfci_last_error(void) { return g_last_error.c_str(); }
 
 int cdfci_phase_times(cdfci_ctx* c, double* seconds) {
   if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
+#ifndef CDFCI_PHASE_TIMING
+  return CDFCI_ERR_UNSUPPORTED;  // timers compiled out of the kernel
+#endif
   Ctl h;
   int rc = ctl_read(c, &h);
   if (rc) return rc;

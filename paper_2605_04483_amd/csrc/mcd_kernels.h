@@ -38,6 +38,7 @@ struct McState {
   int skip;  // this step does nothing (an error is pending or the run stopped)
   unsigned arrive;                   // workgroups done with the current selection kernel
   unsigned long long n_total;        // candidates of the coming selection
+  unsigned long long last_sel;       // size of the last completed step's chosen set
 };
 
 constexpr int kPage = 256;
@@ -1310,6 +1311,7 @@ __global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_
   for (unsigned p = threadIdx.x; p < npg; p += blockDim.x)
     cnt[page0 + p] = s_n > p * kPage ? min((unsigned)kPage, s_n - p * kPage) : 0u;
   if (threadIdx.x == 0) {
+    st->last_sel = (unsigned long long)m;
     st->n_sel = 0;
     st->n_pages = (unsigned long long)page0 + npg;
     if (ctl->occupied > max_entries) ctl->error |= kErrTableFull;
@@ -1334,5 +1336,29 @@ __global__ void k_mc_rescale_done(McState* st, int force) {
     st->scale = 1.0;
     st->inv_scale = 1.0;
     st->rescale = 0;
+  }
+}
+
+// Inspection: the candidates of the coming selection, compacted, with the
+// selection key |4 b_hat + 4 mu c_hat| exactly as the radix select forms it
+// (g_key) and the stored c_hat, b_hat.
+__global__ void __launch_bounds__(256) k_mc_export_cands(const Slot* T, const unsigned* cand, const unsigned* cnt,
+                                                         const McState* st, const Ctl* ctl, uint64_t* keys,
+                                                         double* g, double* cv, double* bv, unsigned long long cap,
+                                                         unsigned long long* count) {
+  const unsigned long long n = st->n_pages * kPage;
+  const double mu = ctl->mu_hi + ctl->mu_lo;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
+    const Slot v = T[cand[i]];
+    const unsigned long long q = atomicAdd(count, 1ull);
+    if (q < cap) {
+      keys[2 * q] = v.ka;
+      keys[2 * q + 1] = v.kb;
+      g[q] = __longlong_as_double((long long)g_key(v, mu));
+      cv[q] = v.c;
+      bv[q] = v.b;
+    }
   }
 }

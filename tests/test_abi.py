@@ -30,13 +30,35 @@ def test_library_exports_every_declared_symbol():
     assert bound == set(declared_symbols())
 
 
-def test_struct_layouts():
-    # cdfci_opts: 5 8-byte scalars, 4 ints, 3 pointer-size fields
-    assert ctypes.sizeof(_lib.cdfci_opts) == 5 * 8 + 4 * 4 + 3 * 8
-    assert ctypes.sizeof(_lib.cdfci_stats) == 5 * 8 + 2 * 4 + 5 * 8
-    assert ctypes.sizeof(_lib.cdfci_hubbard_spec) == 7 * 4 + 4 + 2 * 8
-    assert ctypes.sizeof(_lib.cdfci_batch_opts) == 7 * 8 + 2 * 4 + 8
-    assert ctypes.sizeof(_lib.cdfci_batch_stats) == 2 * 8 + 4 * 4 + 8
+def test_struct_layouts(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler
+    gives it in include/cdfci.h."""
+    import subprocess
+
+    structs = {"cdfci_opts": _lib.cdfci_opts, "cdfci_stats": _lib.cdfci_stats,
+               "cdfci_hubbard_spec": _lib.cdfci_hubbard_spec, "cdfci_batch_opts": _lib.cdfci_batch_opts,
+               "cdfci_batch_stats": _lib.cdfci_batch_stats, "cdfci_optorb_opts": _lib.cdfci_optorb_opts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cdfci.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        name, field, value = line.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), (name, field, got, value)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())
 
 
 def test_strerror_without_gpu():

@@ -1,0 +1,145 @@
+"""GPU parity of the multicoordinate step (Alg. 2, eq. (choose-I) and
+eq. (def-z)) at the sizes the benchmark runs, called through the C ABI.
+
+* 12 orbitals, 5+4 electrons (1,566-entry columns, no spin-flip ties),
+  k = 64, 256 and 1024: the chosen set and the energy of every step against
+  the oracle's Alg. 2 (LAPACK for the reduced problem) while the oracle's
+  selection boundary has no near-tie.
+* 36 orbitals, 8+8 electrons, naux 108, tau = 5e-5, 2^28 slots, k = 256:
+  the candidates the device exports are exactly the stored determinants of
+  the previous step's columns plus its chosen set (oracle columns), their
+  selection keys equal |4 b + 4 mu c|, and the next step chooses exactly the
+  256 largest keys with ties to the smaller (beta, alpha) key.
+* the same system at k = 256 and 1024: the energy after a step equals the
+  lowest eigenvalue of A = Q^T H Q formed on the host (LAPACK) from the state
+  before it, with H_II from oracle entries: the device's Householder /
+  Lanczos eigenpair against LAPACK at (k+1) = 257 and 1025."""
+import numpy as np
+import pytest
+
+import synth_inputs
+from oracle import cd as ocd
+from oracle import mcdfci as omc
+
+pytestmark = pytest.mark.gpu
+
+KEY = [("b", "<u8"), ("a", "<u8")]  # sorts as the (beta, alpha) key order
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2605_04483_amd as api
+
+    return api
+
+
+def _keys(a, b):
+    k = np.zeros(len(a), dtype=KEY)
+    k["a"] = a
+    k["b"] = b
+    return k
+
+
+def _member(sorted_keys, q):
+    i = np.searchsorted(sorted_keys, q)
+    i = np.minimum(i, len(sorted_keys) - 1)
+    return sorted_keys[i] == q
+
+
+@pytest.mark.parametrize("k", [64, 256, 1024])
+def test_mc_large_k_steps_match_oracle(api, k):
+    N, na, nb = 12, 5, 4
+    h, eri = synth_inputs.ab_initio(N, 36, 1)
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    K = 4
+    orc = omc.mcdfci_run(h, eri, keys, c0, k, max_steps=K)
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 22)
+    checked = 0
+    for s in range(K):
+        E, _ = api.cdfci_step_energies(ctx, k, 1)
+        sa, sb, _ = api.cdfci_mc_selection(ctx)
+        assert len(sa) == len(orc.selections[s])
+        assert {(int(x), int(y)) for x, y in zip(sa, sb)} == set(orc.selections[s]), s
+        assert abs(E[0] - orc.energies[s]) <= 1e-9 * abs(orc.energies[s]), (s, E[0], orc.energies[s])
+        checked += 1
+        if orc.gaps[s] < 1e-9:
+            break
+    assert checked >= 2, checked
+    ctx.close()
+
+
+def _n36():
+    N, na, nb = 36, 8, 8
+    h, eri = synth_inputs.ab_initio(N, 108, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
+    return N, na, nb, h, eri
+
+
+def test_mc_topk_exact_at_full_size(api):
+    N, na, nb, h, eri = _n36()
+    k, tau = 256, 5e-5
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 28, z_threshold=tau)
+    api.cdfci_step(ctx, k, 2)
+    pa, pb, _ = api.cdfci_mc_selection(ctx)
+    assert len(pa) == k
+    ka, kb, c, b = api.cdfci_export(ctx)  # folds the lazy scale: s = 1 below
+    cand = api.cdfci_mc_candidates(ctx)
+    assert cand["scale"] == 1.0
+    ck = _keys(cand["keys_alpha"], cand["keys_beta"])
+    # each candidate once
+    assert len(np.unique(ck)) == len(ck)
+    # candidates = stored entries of the previous columns (H_ji != 0) plus the chosen set
+    stored = np.sort(_keys(ka, kb))
+    cols = []
+    for x, y in zip(pa.tolist(), pb.tolist()):
+        oa, ob, v = ocd.column(h, eri, x, y)
+        nz = v != 0.0
+        cols.append(_keys(oa[nz], ob[nz]))
+    touched = np.unique(np.concatenate(cols + [_keys(pa, pb)]))
+    expect = touched[_member(stored, touched)]
+    assert len(expect) == len(ck)
+    assert np.array_equal(expect, np.sort(ck))
+    # selection keys are |4 b + 4 mu c| of the stored values (the device may fuse the product)
+    gref = np.abs(4.0 * cand["b_hat"] + 4.0 * cand["mu"] * cand["c_hat"])
+    assert np.all(np.abs(cand["g"] - gref) <= 1e-14 * np.maximum(gref, 1e-300) + 1e-300)
+    # the next step takes exactly the k largest, ties to the smaller (beta, alpha) key
+    api.cdfci_step(ctx, k, 1)
+    sa, sb, _ = api.cdfci_mc_selection(ctx)
+    order = np.lexsort((ck["a"], ck["b"], -cand["g"]))
+    top = np.sort(ck[order[:k]])
+    assert np.array_equal(np.sort(_keys(sa, sb)), top)
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [256, 1024])
+def test_mc_step_energy_is_lowest_eigenvalue_full_size(api, k):
+    N, na, nb, h, eri = _n36()
+    tau = 5e-5
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 28, z_threshold=tau)
+    st = api.cdfci_step(ctx, k, 2)
+    ka, kb, c, b = api.cdfci_export(ctx)
+    st = api.cdfci_step(ctx, k, 0)  # maintained mu, alpha of the folded state
+    mu, alpha = st["mu"], st["alpha"]
+    E1, st1 = api.cdfci_step_energies(ctx, k, 1)
+    sa, sb, _ = api.cdfci_mc_selection(ctx)
+    I = [(int(x), int(y)) for x, y in zip(sa, sb)]
+    where = {(int(x), int(y)): i for i, (x, y) in enumerate(zip(ka, kb))}
+    cI = np.array([c[where[i]] if i in where else 0.0 for i in I])
+    bI = np.array([b[where[i]] if i in where else 0.0 for i in I])
+    m = len(I)
+    HII = np.zeros((m, m))
+    for p in range(m):
+        for q in range(p, m):
+            HII[p, q] = HII[q, p] = ocd.entry(h, eri, I[p], I[q])
+    nu2 = mu - cI @ cI
+    assert nu2 > 1e-10 * mu
+    nu = np.sqrt(nu2)
+    A = np.zeros((m + 1, m + 1))
+    A[0, 0] = (alpha - 2.0 * cI @ bI + cI @ HII @ cI) / nu2
+    A[0, 1:] = A[1:, 0] = (bI - HII @ cI) / nu
+    A[1:, 1:] = HII
+    lam = np.linalg.eigvalsh(A)[0]
+    assert abs(E1[0] - lam) <= 1e-9 * abs(lam), (E1[0], lam)
+    ctx.close()

@@ -8,7 +8,7 @@ LIB = os.path.join(HERE, "liboracle_cd.so")
 
 def build(verbose=False):
     src = os.path.join(HERE, "cd_serial.cpp")
-    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-o", LIB, src, "-lquadmath"]
+    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", LIB, src, "-lquadmath"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -36,6 +36,10 @@ def bind(path):
     L.oracle_column.restype = ctypes.c_int64
     L.oracle_column.argtypes = [ctypes.c_int, dp, dp, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_int64, up, up, dp]
+    L.oracle_cd_run_mt.restype = ctypes.c_int
+    L.oracle_cd_run_mt.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, up, up, dp, ctypes.c_double,
+                                   ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, up,
+                                   up, dp, ip, dp, dp, ip, ip]
     L.oracle_cd_run.restype = ctypes.c_int
     L.oracle_cd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, up, up, dp,
                                 ctypes.c_double, ctypes.c_int64, ctypes.c_double,
@@ -210,6 +214,47 @@ def cd_run(h, eri, init_keys, init_c, tau=0.0, max_steps=1000, theta=0.9, dx_tol
         r.gap = tg[:n]
     if export:
         r.keys_a, r.keys_b, r.c, r.b = oa, ob, oc, ov
+    return r
+
+
+def cd_run_mt(h, eri, init_keys, init_c, threads, tau=0.0, max_steps=1000, theta=0.9, dx_tol=0.0,
+              trajectory=True):
+    """Algorithm 1 on `threads` host threads (OpenMP); the same trajectory as
+    cd_run, bit for bit.  For the CPU timing baseline."""
+    N = h.shape[0]
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    ia = np.array([k[0] for k in init_keys], np.uint64)
+    ib = np.array([k[1] for k in init_keys], np.uint64)
+    ic = np.ascontiguousarray(init_c, dtype=np.float64)
+    T = max_steps if trajectory else 0
+    tE = np.zeros(T) if trajectory else None
+    ta = np.zeros(T, np.uint64) if trajectory else None
+    tb = np.zeros(T, np.uint64) if trajectory else None
+    te = np.zeros(T) if trajectory else None
+    steps = np.zeros(1, np.int64)
+    mu = np.zeros(1)
+    al = np.zeros(1)
+    nst = np.zeros(1, np.int64)
+    nel = np.zeros(1, np.int64)
+    rc = lib().oracle_cd_run_mt(N, _p(h, ctypes.c_double), _p(eri, ctypes.c_double), len(ia),
+                                _p(ia, ctypes.c_uint64), _p(ib, ctypes.c_uint64), _p(ic, ctypes.c_double),
+                                tau, max_steps, theta, dx_tol, int(threads), _p(tE, ctypes.c_double),
+                                _p(ta, ctypes.c_uint64), _p(tb, ctypes.c_uint64), _p(te, ctypes.c_double),
+                                _p(steps, ctypes.c_int64), _p(mu, ctypes.c_double), _p(al, ctypes.c_double),
+                                _p(nst, ctypes.c_int64), _p(nel, ctypes.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_cd_run_mt failed: {rc}")
+    r = CDResult()
+    n = int(steps[0])
+    r.steps = n
+    r.mu = float(mu[0])
+    r.alpha = float(al[0])
+    r.energy = r.alpha / r.mu
+    r.nstored = int(nst[0])
+    r.elements = int(nel[0])
+    if trajectory:
+        r.E, r.sel_a, r.sel_b, r.eta = tE[:n], ta[:n], tb[:n], te[:n]
     return r
 
 

@@ -437,4 +437,189 @@ int oracle_cd_run(int N, const double* h, const double* eri, int ninit, const ui
   return 0;
 }
 
+// The same Algorithm 1 on several host threads (OpenMP), for the CPU timing
+// baseline: the column of the chosen coordinate is generated in independent
+// pieces (one per occupied orbital for singles, one per occupied pair for
+// doubles) and joined in the serial order, the lookups and the b updates of
+// the column's entries run in parallel (the entries of one column are
+// distinct determinants, so each stored value has one writer; new entries are
+// inserted afterwards in column order), the recalculation sum and the
+// selection are reduced in the serial order.  Every value, and so the whole
+// trajectory, is bit for bit that of oracle_cd_run.
+static void column_mt(const Ham& H, Key key, std::vector<Elem>& out, int threads) {
+  const int N = H.N;
+  Occ x{{key.a, key.b}};
+  std::vector<int> oc = occ_list(x, N), vi;
+  for (int P = 0; P < 2 * N; ++P)
+    if (!is_set(x, P, N)) vi.push_back(P);
+  const int no = (int)oc.size();
+  std::vector<std::pair<int, int>> pairs;
+  for (int i = 0; i < no; ++i)
+    for (int j = i + 1; j < no; ++j) pairs.push_back({i, j});
+  // piece 0..no-1: singles of oc[i]; piece no + t: doubles of pair t
+  const int npieces = no + (int)pairs.size();
+  std::vector<std::vector<Elem>> piece(npieces);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+  for (int t = 0; t < npieces; ++t) {
+    std::vector<Elem>& o = piece[t];
+    if (t < no) {
+      const int p = oc[t];
+      for (int r : vi) {
+        if ((p >= N) != (r >= N)) continue;
+        Occ y = x;
+        const char kd[2] = {'c', 'a'};
+        const int ix[2] = {r, p};
+        int sg = apply_ops(y, 2, kd, ix, N);
+        double val = H.one(r, p);
+        for (int k : oc) val += H.v(r, k, p, k) - H.v(r, k, k, p);
+        o.push_back({Key{y.w[0], y.w[1]}, sg * val});
+      }
+    } else {
+      const int p = oc[pairs[t - no].first], q = oc[pairs[t - no].second];
+      for (size_t u = 0; u < vi.size(); ++u)
+        for (size_t w = u + 1; w < vi.size(); ++w) {
+          int r = vi[u], s2 = vi[w];
+          int sp = (p >= N) + (q >= N), sr = (r >= N) + (s2 >= N);
+          if (sp != sr) continue;
+          Occ y = x;
+          const char kd[4] = {'c', 'c', 'a', 'a'};
+          const int ix[4] = {r, s2, q, p};
+          int sg = apply_ops(y, 4, kd, ix, N);
+          double val = H.v(r, s2, p, q) - H.v(r, s2, q, p);
+          o.push_back({Key{y.w[0], y.w[1]}, sg * val});
+        }
+    }
+  }
+  out.clear();
+  out.push_back({key, diag_entry(H, x)});
+  for (auto& v : piece) out.insert(out.end(), v.begin(), v.end());
+}
+
+int oracle_cd_run_mt(int N, const double* h, const double* eri, int ninit, const uint64_t* init_a,
+                     const uint64_t* init_b, const double* init_c, double tau, int64_t max_steps,
+                     double theta, double dx_tol, int threads, double* traj_E, uint64_t* traj_a,
+                     uint64_t* traj_b, double* traj_eta, int64_t* steps_done, double* mu_out,
+                     double* alpha_out, int64_t* nstored, int64_t* elements) {
+  if (N < 1 || N > 64 || ninit < 1 || threads < 1) return -1;
+  Ham H{N, h, eri};
+  std::unordered_map<Key, Val, KeyHash> wf;
+  wf.reserve(1 << 16);
+  std::vector<Elem> col;
+  std::vector<Key> cand;
+  int64_t nelem = 0;
+  for (int t = 0; t < ninit; ++t) wf[Key{init_a[t], init_b[t]}].c += init_c[t];
+  for (int t = 0; t < ninit; ++t) {
+    Key D{init_a[t], init_b[t]};
+    column(H, D, col);
+    for (const Elem& e : col) {
+      if (e.v == 0.0) continue;
+      wf[e.k].b += init_c[t] * e.v;
+      cand.push_back(e.k);
+    }
+  }
+  std::sort(cand.begin(), cand.end(), key_less);
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  __float128 mu = 0, alpha = 0;
+  for (auto& kv : wf) {
+    mu += (__float128)kv.second.c * kv.second.c;
+    alpha += (__float128)kv.second.c * kv.second.b;
+  }
+  std::vector<double> prod, delta;
+  std::vector<Val*> node;
+  std::vector<char> insert;
+  double d = 0.0;
+  int64_t step = 0;
+  for (; step < max_steps; ++step) {
+    const double mud = (double)mu;
+    // selection: per-thread best under the total order (g desc, key asc), then joined
+    Key best{0, 0};
+    double gbest = -1.0;
+#pragma omp parallel num_threads(threads)
+    {
+      Key lb{0, 0};
+      double lg = -1.0;
+#pragma omp for schedule(static)
+      for (int64_t t = 0; t < (int64_t)cand.size(); ++t) {
+        const Key& k = cand[t];
+        auto it = wf.find(k);
+        double c = it == wf.end() ? 0.0 : it->second.c;
+        double b = it == wf.end() ? 0.0 : it->second.b;
+        double g = fabs(4.0 * b + 4.0 * mud * c);
+        if (g > lg || (g == lg && key_less(k, lb))) {
+          lb = k;
+          lg = g;
+        }
+      }
+#pragma omp critical
+      {
+        if (lg > gbest || (lg == gbest && key_less(lb, best))) {
+          best = lb;
+          gbest = lg;
+        }
+      }
+    }
+    Key I = best;
+    Val& vi = wf[I];
+    double ci = vi.c, bi = vi.b;
+    double Hii = diag_entry(H, Occ{{I.a, I.b}});
+    double eta = line_search(4.0 * bi + 4.0 * mud * ci, 2.0 * Hii + 4.0 * ci * ci + 2.0 * mud, 4.0 * ci);
+    vi.c = ci + eta;
+    column_mt(H, I, col, threads);
+    nelem += (int64_t)col.size();
+    const int64_t n = (int64_t)col.size();
+    prod.assign(n, 0.0);
+    delta.assign(n, 0.0);
+    node.assign(n, nullptr);
+    insert.assign(n, 0);
+    // lookups and updates of existing entries (one writer per entry)
+#pragma omp parallel for schedule(static) num_threads(threads)
+    for (int64_t t = 1; t < n; ++t) {
+      const Elem& e = col[t];
+      if (e.v == 0.0) continue;
+      const double dl = eta * e.v;
+      auto it = wf.find(e.k);
+      const double cj = it == wf.end() ? 0.0 : it->second.c;
+      if (cj != 0.0 || fabs(dl) >= tau) {
+        if (it == wf.end()) {
+          insert[t] = 1;
+          delta[t] = dl;
+        } else {
+          it->second.b += dl;
+        }
+      }
+      prod[t] = e.v * cj;
+    }
+    cand.clear();
+    double recalc = col[0].v * (ci + eta);
+    cand.push_back(I);
+    for (int64_t t = 1; t < n; ++t) {
+      const Elem& e = col[t];
+      if (e.v == 0.0) continue;
+      cand.push_back(e.k);
+      if (insert[t]) wf.emplace(e.k, Val{}).first->second.b += delta[t];
+      recalc += prod[t];
+    }
+    Val& vi2 = wf[I];
+    vi2.b = recalc;
+    mu += 2 * (__float128)eta * ci + (__float128)eta * eta;
+    alpha += 2 * (__float128)eta * bi + (__float128)eta * eta * Hii;
+    if (mu <= 0) return -2;
+    d = step == 0 ? fabs(eta) : theta * d + (1.0 - theta) * fabs(eta);
+    if (traj_E) traj_E[step] = (double)(alpha / mu);
+    if (traj_a) traj_a[step] = I.a;
+    if (traj_b) traj_b[step] = I.b;
+    if (traj_eta) traj_eta[step] = eta;
+    if (d < dx_tol) {
+      ++step;
+      break;
+    }
+  }
+  *steps_done = step;
+  *mu_out = (double)mu;
+  *alpha_out = (double)alpha;
+  *nstored = (int64_t)wf.size();
+  *elements = nelem;
+  return 0;
+}
+
 }  // extern "C"

@@ -199,3 +199,18 @@ def test_mcdfci_converges_to_dense(m):
     st = omc.mcdfci_run(h, eri, keys, c0, m, max_steps=10000 // m, dx_tol=1e-12)
     assert abs(st.energy - E0) < 1e-8
     assert np.all(np.array(st.energies) >= E0 - 1e-12)  # variational
+
+
+@pytest.mark.parametrize("na,nb,tau", [(4, 3, 0.0), (4, 4, 1e-3)])
+def test_cd_multithreaded_equals_serial(na, nb, tau):
+    """The OpenMP form of Algorithm 1 (the all-core CPU baseline) follows the
+    serial oracle bit for bit: same choices, steps, energies and stored set."""
+    N = 10
+    h, eri = synth_inputs.ab_initio(N, 30, 5)
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    a = ocd.cd_run(h, eri, keys, c0, tau=tau, max_steps=400)
+    for threads in (1, 3, 8):
+        b = ocd.cd_run_mt(h, eri, keys, c0, threads, tau=tau, max_steps=400)
+        assert np.array_equal(a.E, b.E) and np.array_equal(a.eta, b.eta)
+        assert np.array_equal(a.sel_a, b.sel_a) and np.array_equal(a.sel_b, b.sel_b)
+        assert (a.nstored, a.elements, a.mu, a.alpha) == (b.nstored, b.elements, b.mu, b.alpha)

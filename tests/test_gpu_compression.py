@@ -71,11 +71,13 @@ def test_mc_tau_steps_match_oracle(api, k, tau):
     for s in range(K):
         E, _ = api.cdfci_step_energies(ctx, k, 1)
         sa, sb, _ = api.cdfci_mc_selection(ctx)
-        assert {(int(x), int(y)) for x, y in zip(sa, sb)} == set(orc.selections[s]), s
+        dev = {(int(x), int(y)) for x, y in zip(sa, sb)}
+        if dev != set(orc.selections[s]):
+            # only a near-tie at the selection boundary may resolve differently
+            assert orc.gaps[s] < 1e-9, (s, orc.gaps[s])
+            break
         assert abs(E[0] - orc.energies[s]) <= 1e-9 * abs(orc.energies[s]), (s, E[0], orc.energies[s])
         checked += 1
-        if orc.gaps[s] < 1e-9:
-            break
     assert checked >= 3, checked
     # the stored determinants with c != 0 are the oracle's
     ka, kb, c, _ = api.cdfci_export(ctx)

@@ -61,13 +61,15 @@ def test_mc_large_k_steps_match_oracle(api, k):
     for s in range(K):
         E, _ = api.cdfci_step_energies(ctx, k, 1)
         sa, sb, _ = api.cdfci_mc_selection(ctx)
-        assert len(sa) == len(orc.selections[s])
-        assert {(int(x), int(y)) for x, y in zip(sa, sb)} == set(orc.selections[s]), s
+        assert len(sa) == len(orc.selections[s]), (s, len(sa), len(orc.selections[s]))
+        dev = {(int(x), int(y)) for x, y in zip(sa, sb)}
+        if dev != set(orc.selections[s]):
+            # only a near-tie at the selection boundary may resolve differently
+            assert orc.gaps[s] < 1e-9, (s, len(dev - set(orc.selections[s])), orc.gaps[s])
+            break
         assert abs(E[0] - orc.energies[s]) <= 1e-9 * abs(orc.energies[s]), (s, E[0], orc.energies[s])
         checked += 1
-        if orc.gaps[s] < 1e-9:
-            break
-    assert checked >= 2, checked
+    assert checked >= 3, checked
     ctx.close()
 
 
@@ -99,17 +101,24 @@ def test_mc_topk_exact_at_full_size(api):
         cols.append(_keys(oa[nz], ob[nz]))
     touched = np.unique(np.concatenate(cols + [_keys(pa, pb)]))
     expect = touched[_member(stored, touched)]
-    assert len(expect) == len(ck)
-    assert np.array_equal(expect, np.sort(ck))
+    got = np.sort(ck)
+    missing = expect[~_member(got, expect)]
+    extra = got[~_member(expect, got)]
+    assert len(missing) == 0 and len(extra) == 0, (len(expect), len(got), missing[:5], extra[:5])
     # selection keys are |4 b + 4 mu c| of the stored values (the device may fuse the product)
-    gref = np.abs(4.0 * cand["b_hat"] + 4.0 * cand["mu"] * cand["c_hat"])
-    assert np.all(np.abs(cand["g"] - gref) <= 1e-14 * np.maximum(gref, 1e-300) + 1e-300)
+    # (to the rounding of one product and one sum)
+    t1, t2 = 4.0 * cand["b_hat"], 4.0 * cand["mu"] * cand["c_hat"]
+    gref = np.abs(t1 + t2)
+    assert np.all(np.abs(cand["g"] - gref) <= 4.5e-16 * (np.abs(t1) + np.abs(t2)))
     # the next step takes exactly the k largest, ties to the smaller (beta, alpha) key
     api.cdfci_step(ctx, k, 1)
     sa, sb, _ = api.cdfci_mc_selection(ctx)
     order = np.lexsort((ck["a"], ck["b"], -cand["g"]))
     top = np.sort(ck[order[:k]])
-    assert np.array_equal(np.sort(_keys(sa, sb)), top)
+    chosen = np.sort(_keys(sa, sb))
+    assert len(chosen) == k
+    bad = chosen[~_member(top, chosen)]
+    assert len(bad) == 0, (len(bad), cand["g"][order[k - 1]], cand["g"][order[k]], bad[:4])
     ctx.close()
 
 
@@ -129,10 +138,18 @@ def test_mc_step_energy_is_lowest_eigenvalue_full_size(api, k):
     cI = np.array([c[where[i]] if i in where else 0.0 for i in I])
     bI = np.array([b[where[i]] if i in where else 0.0 for i in I])
     m = len(I)
+    # H_II from the oracle's columns of the chosen determinants
+    Ik = _keys(np.array([x for x, _ in I], np.uint64), np.array([y for _, y in I], np.uint64))
     HII = np.zeros((m, m))
-    for p in range(m):
-        for q in range(p, m):
-            HII[p, q] = HII[q, p] = ocd.entry(h, eri, I[p], I[q])
+    for q in range(m):
+        oa, ob, v = ocd.column(h, eri, *I[q])
+        ck = _keys(oa, ob)
+        order = np.argsort(ck)
+        ck, v = ck[order], v[order]
+        pos = np.minimum(np.searchsorted(ck, Ik), len(ck) - 1)
+        HII[:, q] = np.where(ck[pos] == Ik, v[pos], 0.0)
+    assert np.max(np.abs(HII - HII.T)) <= 1e-12
+    HII = 0.5 * (HII + HII.T)
     nu2 = mu - cI @ cI
     assert nu2 > 1e-10 * mu
     nu = np.sqrt(nu2)

@@ -164,6 +164,19 @@ int cdfci_rdm_backward(cdfci_ctx* ctx, double grad_E, int64_t top_n, double* ene
 int cdfci_column(cdfci_ctx* ctx, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
                  int64_t* count);
 
+/* get_column for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result as cdfci_column, staged through a fixed device array of the
+ * library instead of per-call buffers, so the call makes no hipMalloc,
+ * hipFree or other allocating call.  keys (2*cap uint64) and vals (cap
+ * doubles) may be host or device pointers.  Limit: columns of at most
+ * 262144 entries (6 MiB of staging per GPU, held until the process ends);
+ * a larger column gives CDFCI_ERR_UNSUPPORTED with *count set.  Every call on
+ * one GPU shares that staging array: calls that overlap on one GPU (other
+ * contexts or threads) race and must be serialised by the caller. */
+int cdfci_column_noalloc(cdfci_ctx* ctx, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
+                         int64_t* count);
+
 /* get_entry (Sec. 4.1.1): H_{k1,k2} by the Slater-Condon rules, eq. (entry). */
 int cdfci_entry(cdfci_ctx* ctx, const uint64_t k1[2], const uint64_t k2[2], double* value);
 

@@ -138,6 +138,7 @@ SIGNATURES = [
     ("cdfci_energy", ctypes.c_int, [_P, ctypes.c_int, _DP]),
     ("cdfci_rdm_backward", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64, _DP, _DP, _DP, _DP]),
     ("cdfci_column", ctypes.c_int, [_P, _UP, _UP, _DP, ctypes.c_int64, _I64P]),
+    ("cdfci_column_noalloc", ctypes.c_int, [_P, _UP, _UP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_entry", ctypes.c_int, [_P, _UP, _UP, _DP]),
     ("cdfci_export", ctypes.c_int, [_P, ctypes.c_int64, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_phase_times", ctypes.c_int, [_P, _DP]),

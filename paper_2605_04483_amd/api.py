@@ -213,6 +213,37 @@ def cdfci_column(ctx, key):
     return keys[0::2].copy(), keys[1::2].copy(), vals
 
 
+def cdfci_column_noalloc(ctx, key, keys_out=None, vals_out=None):
+    """get_column through the no-allocation entry point.  keys_out (uint64,
+    2*n) and vals_out (float64, n) may be given (numpy arrays or contiguous
+    device tensors); else host arrays are made here.  Returns
+    (keys_alpha, keys_beta, vals) for host outputs, else the count."""
+    L = _lib.load()
+    k = np.array([int(key[0]), int(key[1])], dtype=np.uint64)
+    cnt = ctypes.c_int64(0)
+    if keys_out is None:
+        rc = L.cdfci_column_noalloc(ctx.handle, _up(k), None, None, 0, ctypes.byref(cnt))
+        n = cnt.value
+        if n <= 0 or rc not in (0, -1):
+            _check(rc, "cdfci_column_noalloc")
+        keys = np.zeros(2 * n, np.uint64)
+        vals = np.zeros(n)
+        _check(L.cdfci_column_noalloc(ctx.handle, _up(k), _up(keys), _dp(vals), n, ctypes.byref(cnt)),
+               "cdfci_column_noalloc")
+        return keys[0::2].copy(), keys[1::2].copy(), vals
+
+    def ptr(x, t):
+        if isinstance(x, np.ndarray):
+            return x.ctypes.data_as(ctypes.POINTER(t)), x.size
+        return ctypes.cast(ctypes.c_void_p(int(x.data_ptr())), ctypes.POINTER(t)), x.numel()
+
+    kp, nk = ptr(keys_out, ctypes.c_uint64)
+    vp, nv = ptr(vals_out, ctypes.c_double)
+    _check(L.cdfci_column_noalloc(ctx.handle, _up(k), kp, vp, min(nk // 2, nv), ctypes.byref(cnt)),
+           "cdfci_column_noalloc")
+    return cnt.value
+
+
 def cdfci_entry(ctx, bra, ket):
     k1 = np.array([int(bra[0]), int(bra[1])], dtype=np.uint64)
     k2 = np.array([int(ket[0]), int(ket[1])], dtype=np.uint64)

@@ -37,6 +37,35 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Staging memory of cdfci_column_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code uses only the device
+// address resolved per device at context set-up.
+constexpr int64_t kNoAllocMaxEntries = 1 << 18;  // column entries (keys 16 B + value 8 B each): 6 MiB
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocMaxEntries * (2 * sizeof(uint64_t) + sizeof(double))];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// resolve this device's address of `scratch` once (the device must be current)
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[device] = p;
+  return e;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(_e);                 \
+      return CDFCI_ERR_HIP;                                                             \
+    }                                                                                   \
+  } while (0)
+
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
     hipError_t _e = (expr);                                                             \
@@ -912,12 +941,15 @@ __global__ void k_aufbau_init(Ham H, InitTask* out, int* status) {
 // ---------------------------------------------------------------------------
 // Inspection kernels.
 
-__global__ void __launch_bounds__(256) k_column(Ham H, uint64_t a, uint64_t b, int64_t n_col, uint64_t* keys, double* vals) {
+// diag_shift is added to the diagonal entry (the context holds H - sigma I;
+// get_column reports H)
+__global__ void __launch_bounds__(256) k_column(Ham H, uint64_t a, uint64_t b, int64_t n_col, double diag_shift,
+                                                uint64_t* keys, double* vals) {
   __shared__ Lists L;
   __shared__ double s_diag;
   if (threadIdx.x == 0) {
     make_lists_serial(a, b, H.N, L);
-    s_diag = diag_serial(H, L);
+    s_diag = diag_serial(H, L) + diag_shift;
   }
   __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_col;
@@ -1268,6 +1300,14 @@ int make_ctx(int N, int na, int nb, const cdfci_opts* opts, cdfci_ctx** out) {
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return CDFCI_ERR_HIP;
+  }
+  {
+    hipError_t e = resolve_scratch(c->device);
+    if (e != hipSuccess) {
+      g_last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      delete c;
+      return CDFCI_ERR_HIP;
+    }
   }
   *out = c;
   return 0;
@@ -1886,14 +1926,37 @@ int cdfci_column(cdfci_ctx* c, const uint64_t key[2], uint64_t* keys, double* va
   HIP_TRY(hipMalloc(&dk, 2 * c->n_col * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&dv, c->n_col * sizeof(double)));
   int blocks = (int)std::min<int64_t>((c->n_col + 255) / 256, 4096);
-  k_column<<<blocks, 256, 0, c->stream>>>(ham_of(c), key[0], key[1], c->n_col, dk, dv);
+  k_column<<<blocks, 256, 0, c->stream>>>(ham_of(c), key[0], key[1], c->n_col, c->shift, dk, dv);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(keys, dk, 2 * c->n_col * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(vals, dv, c->n_col * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   (void)hipFree(dk);
   (void)hipFree(dv);
-  vals[0] += c->shift;  // entries of H: the diagonal comes first
+  return 0;
+}
+
+int cdfci_column_noalloc(cdfci_ctx* c, const uint64_t key[2], uint64_t* keys, double* vals, int64_t cap,
+                         int64_t* count) {
+  if (!c || !key || !count) return CDFCI_ERR_INVALID_ARG;
+  if (__builtin_popcountll(key[0]) != c->na || __builtin_popcountll(key[1]) != c->nb ||
+      (c->N < 64 && ((key[0] | key[1]) >> c->N)))
+    return CDFCI_ERR_INVALID_ARG;
+  *count = c->n_col;
+  if (c->n_col > kNoAllocMaxEntries) return CDFCI_ERR_UNSUPPORTED;
+  if (cap < c->n_col || !keys || !vals) return CDFCI_ERR_INVALID_ARG;
+  if (c->device < 0 || c->device >= kMaxDevices || !g_scratch_ptr[c->device]) return CDFCI_ERR_HIP;
+  // the staging buffer is this device's copy of `scratch`, by the address
+  // resolved at set-up (never the host-side name of the array)
+  unsigned char* base = (unsigned char*)g_scratch_ptr[c->device];
+  uint64_t* dk = (uint64_t*)base;
+  double* dv = (double*)(base + kNoAllocMaxEntries * 2 * sizeof(uint64_t));
+  int blocks = (int)std::min<int64_t>((c->n_col + 255) / 256, 4096);
+  k_column<<<blocks, 256, 0, c->stream>>>(ham_of(c), key[0], key[1], c->n_col, c->shift, dk, dv);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(keys, dk, 2 * c->n_col * sizeof(uint64_t), hipMemcpyDefault, c->stream));
+  HIP_TRY(hipMemcpyAsync(vals, dv, c->n_col * sizeof(double), hipMemcpyDefault, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return 0;
 }
 

@@ -211,9 +211,10 @@ def mcd_n36(api, synth_inputs, args):
 def hubbard_batch(api, synth_inputs, args):
     specs = synth_inputs.hubbard_batch_specs(256, synth_inputs.CONFIG_SEEDS["hubbard_batch"])
     t0 = time.perf_counter()
-    B = api.cdfci_init_hubbard_batch(specs, max_table_slots=1 << 22, dx_threshold=1e-10)
+    B = api.cdfci_init_hubbard_batch(specs, dx_threshold=1e-10)
     t_init = time.perf_counter() - t0
-    chunk, launches = api.cdfci_tune_batch(B, chunks=(512, 2048), launches=(2, 8), steps_per_trial=4000)
+    chunk, launches, lf = api.cdfci_tune_batch(B, chunks=(512, 2048), launches=(2, 8), load_factors=(0.5, 0.79),
+                                               steps_per_trial=4000)
     t0 = time.perf_counter()
     st = api.cdfci_step_batch(B, args.batch_steps)
     wall = time.perf_counter() - t0

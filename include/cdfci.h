@@ -78,6 +78,8 @@ typedef struct {
   int64_t total_steps;    /* iterations since init */
   int64_t elements;       /* Hamiltonian entries enumerated (zeros included) */
   int64_t inserts;        /* new determinants stored */
+  int64_t probes;         /* table slots inspected by the column scatters of k > 1 steps */
+  int64_t atomics;        /* FP64 atomic b updates issued by those scatters */
   uint64_t occupied;      /* determinants in the table */
   int32_t max_probe;      /* longest probe sequence seen */
   int32_t stopped;        /* 1 if the damped accumulator fell below dx_threshold */
@@ -216,6 +218,17 @@ int cdfci_mc_candidates(cdfci_ctx* ctx, uint64_t* keys, double* g, double* cv, d
                         int64_t* count, double* mu_scale);
 int cdfci_mc_selection(cdfci_ctx* ctx, uint64_t* keys, double* eta, int64_t cap, int64_t* count);
 
+/* Measurement aid: the rates of the memory operations a column scatter is
+ * made of, each alone over uniformly random slots of a table of table_slots
+ * 32-byte slots (allocated for the call, on the current device), n_ops
+ * operations per run, best of three timed runs: rates[0] 16-byte key
+ * gathers/s, rates[1] gather + plain 8-byte read-modify-write/s, rates[2]
+ * gather + agent-scope FP64 atomic add/s, rates[3] returning 32-bit atomic
+ * ORs into a one-bit-per-slot bitmap/s, rates[4] bytes/s of a 1 GiB device
+ * copy (read + write).  These are the ceilings the hash probes and atomics
+ * of the solver are compared with. */
+int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates);
+
 /* Restart (Sec. 4.1.3: checkpoints for termination and restart from stored
  * wavefunctions).  Replaces the context's state by the wavefunction
  * c = sum_i cv[i] e_{key i}: keys 2*count uint64 (alpha, beta) and cv count
@@ -259,10 +272,22 @@ int cdfci_free(cdfci_ctx* ctx);
  * persistent kernel: one wavefront holds one instance at a time (a Hubbard
  * column has at most 1 + 2 * bonds entries) and waves take instances from a
  * queue; the host replays a captured HIP graph of such launches until every
- * instance has stopped or used its step budget.  Each instance is an ordinary
- * context created as by cdfci_init_hubbard (Neel determinant plus subspace
- * start), so it can be inspected with cdfci_energy, cdfci_export and the like
- * through cdfci_batch_context. */
+ * instance of the current wave has stopped or used its step budget.
+ *
+ * Memory: each instance gets a table sized to its FCI dimension (the smallest
+ * power of two >= dimension / load_factor, at least 2^10, capped by
+ * max_table_slots if that is set and by the memory budget), so no instance
+ * can fill its table below the budget.  A scheduler keeps the tables of the
+ * resident instances within memory_budget: a call runs the instances that
+ * still have work in waves, admitting instances in index order while their
+ * tables fit and evicting instances that have no work left in the call
+ * (stopped or failed ones are released with their results kept; running ones
+ * are checkpointed to host memory as their (key, c) list and restarted later
+ * by the rule of cdfci_load: b rebuilt exactly, the step accumulator reset).
+ * Each instance is an ordinary context created as by cdfci_init_hubbard
+ * (Neel determinant plus subspace start); while it is resident it can be
+ * inspected with cdfci_energy, cdfci_export and the like through
+ * cdfci_batch_context. */
 typedef struct {
   int dims[3];   /* sites per direction (row-major site index); entries past ndim ignored */
   int ndim;      /* 1..3; at most 63 sites and 64 distinct bonds */
@@ -274,10 +299,11 @@ typedef struct {
 typedef struct cdfci_batch cdfci_batch; /* opaque, library-owned */
 
 typedef struct {
-  uint64_t table_slots;      /* per instance (power of two); 0 = the smallest power of two
-                                >= FCI dimension / load_factor, at least 2^10, at most
-                                max_table_slots */
-  uint64_t max_table_slots;  /* 0 = 2^22 */
+  uint64_t table_slots;      /* per instance (power of two); 0 = sized from the FCI dimension
+                                (see above) */
+  uint64_t max_table_slots;  /* cap of the automatic size; 0 = none (only the budget) */
+  uint64_t memory_budget;    /* bytes of instance tables resident at once; 0 = 85% of the
+                                device memory free at creation */
   double load_factor;        /* 0 = 0.79 */
   double z_threshold;        /* tau, as in cdfci_opts */
   double dx_damping;         /* 0 = 0.9 */
@@ -295,11 +321,16 @@ typedef struct {
   int32_t stopped;         /* instances stopped by dx_threshold (now or before) */
   int32_t failed;          /* instances with an error (table full) */
   int32_t graph_replays;
+  int32_t rounds;          /* waves of resident instances the scheduler ran */
+  int32_t restarts;        /* instances restored from a checkpoint in this call */
   double seconds;          /* device time of the call */
+  double peak_bytes;       /* largest table bytes resident at once in this call */
 } cdfci_batch_stats;
 
-/* Create count instances (count >= 1).  Errors of one instance's creation
- * abort the whole call (nothing is kept). */
+/* Create count instances (count >= 1).  Specs are checked and table sizes
+ * planned here; instances are created when the scheduler first admits them,
+ * and an instance whose start fails (e.g. CDFCI_ERR_NOT_NEGATIVE) is marked
+ * failed with that code. */
 int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const cdfci_batch_opts* opts,
                              cdfci_batch** out);
 
@@ -314,13 +345,18 @@ int cdfci_batch_results(cdfci_batch* batch, double* energy, int64_t* steps, int*
 
 /* Advance only `instance` by up to nsteps iterations, recording per iteration
  * the energy and the chosen determinant (host arrays of length nsteps, any may
- * be NULL).  For parity tests. */
+ * be NULL).  The instance is admitted if it is not resident (evicting others
+ * as a call of cdfci_step_batch would).  For parity tests. */
 int cdfci_batch_trace(cdfci_batch* batch, int instance, int64_t nsteps, double* energy,
                       uint64_t* sel_alpha, uint64_t* sel_beta);
 
-/* Borrow the context of one instance (owned by the batch: do not free it, do
- * not step it while the batch runs). */
+/* Borrow the context of one resident instance (owned by the batch: do not
+ * free it, do not step it while the batch runs; a later batch call may evict
+ * it).  CDFCI_ERR_INVALID_ARG if the instance is not resident. */
 int cdfci_batch_context(cdfci_batch* batch, int instance, cdfci_ctx** ctx);
+
+/* Table slots planned for each instance (host array of length count). */
+int cdfci_batch_tables(cdfci_batch* batch, uint64_t* slots);
 
 int cdfci_free_batch(cdfci_batch* batch);
 
@@ -336,12 +372,17 @@ int cdfci_free_batch(cdfci_batch* batch);
 int cdfci_tune_k(cdfci_ctx* ctx, const int* ks, int nk, double seconds_per_trial, int rounds, int* best_k,
                  double* rates);
 
-/* Pick a batch's chunk_steps and launches_per_graph among the candidate lists
- * by aggregate iterations per device-second over steps_per_trial iterations
- * per instance each; the winners become the batch's settings.  best_chunk and
- * best_launches may be NULL. */
+/* Pick a batch's hash load factor, chunk_steps and launches_per_graph among
+ * the candidate lists by aggregate iterations per second of wall time over
+ * steps_per_trial iterations per instance each (the whole batch, so the
+ * trade of a lower load factor, shorter probes against larger tables and
+ * fewer resident instances per wave, is measured as it is paid).  A new load
+ * factor re-plans every table: resident instances are checkpointed and
+ * restarted at their new size.  The winners become the batch's settings.
+ * lfs may be NULL (nlf = 0: the load factor is kept); best_* may be NULL. */
 int cdfci_tune_batch(cdfci_batch* batch, const int64_t* chunks, int nc, const int* launches, int nl,
-                     int64_t steps_per_trial, int64_t* best_chunk, int* best_launches);
+                     const double* lfs, int nlf, int64_t steps_per_trial, int64_t* best_chunk,
+                     int* best_launches, double* best_lf);
 
 /* ---- Several low-lying states: xCDFCI (Sec. 3.3, Alg. 3) ---------------------
  * Minimises f(C) = ||H - sigma I + C C^T||_F^2 over C with n = K + 1 columns

@@ -40,6 +40,8 @@ class cdfci_stats(ctypes.Structure):
         ("total_steps", ctypes.c_int64),
         ("elements", ctypes.c_int64),
         ("inserts", ctypes.c_int64),
+        ("probes", ctypes.c_int64),
+        ("atomics", ctypes.c_int64),
         ("occupied", ctypes.c_uint64),
         ("max_probe", ctypes.c_int32),
         ("stopped", ctypes.c_int32),
@@ -70,6 +72,7 @@ class cdfci_batch_opts(ctypes.Structure):
     _fields_ = [
         ("table_slots", ctypes.c_uint64),
         ("max_table_slots", ctypes.c_uint64),
+        ("memory_budget", ctypes.c_uint64),
         ("load_factor", ctypes.c_double),
         ("z_threshold", ctypes.c_double),
         ("dx_damping", ctypes.c_double),
@@ -89,7 +92,10 @@ class cdfci_batch_stats(ctypes.Structure):
         ("stopped", ctypes.c_int32),
         ("failed", ctypes.c_int32),
         ("graph_replays", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
         ("seconds", ctypes.c_double),
+        ("peak_bytes", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -143,6 +149,7 @@ SIGNATURES = [
     ("cdfci_export", ctypes.c_int, [_P, ctypes.c_int64, _UP, _DP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_phase_times", ctypes.c_int, [_P, _DP]),
     ("cdfci_load", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64]),
+    ("cdfci_random_access_rates", ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _DP]),
     ("cdfci_mc_candidates", ctypes.c_int, [_P, _UP, _DP, _DP, _DP, ctypes.c_int64, _I64P, _DP]),
     ("cdfci_mc_selection", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_set_threshold", ctypes.c_int, [_P, ctypes.c_double]),
@@ -160,8 +167,9 @@ SIGNATURES = [
      [_P, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_int,
       ctypes.POINTER(ctypes.c_int), _DP]),
     ("cdfci_tune_batch", ctypes.c_int,
-     [_P, _I64P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64, _I64P,
-      ctypes.POINTER(ctypes.c_int)]),
+     [_P, _I64P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _DP, ctypes.c_int, ctypes.c_int64,
+      _I64P, ctypes.POINTER(ctypes.c_int), _DP]),
+    ("cdfci_batch_tables", ctypes.c_int, [_P, _UP]),
     ("cdfci_xinit", ctypes.c_int,
      [_DP, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _OPTP, _CTXP]),
     ("cdfci_xinit_hubbard", ctypes.c_int,

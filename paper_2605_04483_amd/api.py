@@ -297,6 +297,15 @@ def cdfci_mc_selection(ctx):
     return keys[0:2 * n:2].copy(), keys[1:2 * n:2].copy(), eta[:n]
 
 
+def cdfci_random_access_rates(table_slots=1 << 28, n_ops=18_379_008):
+    """Ceilings of the scatter's memory operations on random slots (see include/cdfci.h)."""
+    r = np.zeros(5)
+    _check(_lib.load().cdfci_random_access_rates(int(table_slots), int(n_ops), _dp(r)), "cdfci_random_access_rates")
+    return {"gather16_per_s": r[0], "gather_rmw8_per_s": r[1], "gather_atomic_f64_per_s": r[2],
+            "bitmap_or_ret_per_s": r[3], "copy_bytes_per_s": r[4], "table_slots": int(table_slots),
+            "n_ops": int(n_ops)}
+
+
 def cdfci_load(ctx, keys_alpha, keys_beta, c):
     """Restart from a stored wavefunction (keys and c as cdfci_export returns)."""
     ka = np.asarray(keys_alpha, dtype=np.uint64)
@@ -363,9 +372,9 @@ class Batch:
             self.handle = None
 
 
-def cdfci_init_hubbard_batch(specs, table_slots=0, max_table_slots=0, load_factor=0.0, z_threshold=0.0,
-                             dx_damping=0.0, dx_threshold=0.0, chunk_steps=0, launches_per_graph=0,
-                             waves=0):
+def cdfci_init_hubbard_batch(specs, table_slots=0, max_table_slots=0, memory_budget=0, load_factor=0.0,
+                             z_threshold=0.0, dx_damping=0.0, dx_threshold=0.0, chunk_steps=0,
+                             launches_per_graph=0, waves=0):
     """specs: sequence of dicts {dims, t, U, n_alpha, n_beta}."""
     L = _lib.load()
     arr = (cdfci_hubbard_spec * len(specs))()
@@ -381,6 +390,7 @@ def cdfci_init_hubbard_batch(specs, table_slots=0, max_table_slots=0, load_facto
     o = cdfci_batch_opts()
     o.table_slots = int(table_slots)
     o.max_table_slots = int(max_table_slots)
+    o.memory_budget = int(memory_budget)
     o.load_factor = float(load_factor)
     o.z_threshold = float(z_threshold)
     o.dx_damping = float(dx_damping)
@@ -445,15 +455,27 @@ def cdfci_tune_k(ctx, ks=(64, 256, 1024), seconds_per_trial=0.05, rounds=2):
     return best.value, dict(zip((int(k) for k in ks), rates.tolist()))
 
 
-def cdfci_tune_batch(batch, chunks=(256, 1024, 4096), launches=(1, 4, 16), steps_per_trial=20000):
-    """Returns (best_chunk, best_launches)."""
+def cdfci_tune_batch(batch, chunks=(256, 1024, 4096), launches=(1, 4, 16), load_factors=(),
+                     steps_per_trial=20000):
+    """Returns (best_chunk, best_launches, best_load_factor)."""
     ca = (ctypes.c_int64 * len(chunks))(*[int(c) for c in chunks])
     la = (ctypes.c_int * len(launches))(*[int(x) for x in launches])
+    lf = np.ascontiguousarray(load_factors, dtype=np.float64)
     bc = ctypes.c_int64(0)
     bl = ctypes.c_int(0)
-    _check(_lib.load().cdfci_tune_batch(batch.handle, ca, len(chunks), la, len(launches), int(steps_per_trial),
-                                        ctypes.byref(bc), ctypes.byref(bl)), "cdfci_tune_batch")
-    return bc.value, bl.value
+    blf = ctypes.c_double(0.0)
+    _check(_lib.load().cdfci_tune_batch(batch.handle, ca, len(chunks), la, len(launches),
+                                        _dp(lf) if len(lf) else None, len(lf), int(steps_per_trial),
+                                        ctypes.byref(bc), ctypes.byref(bl), ctypes.byref(blf)),
+           "cdfci_tune_batch")
+    return bc.value, bl.value, blf.value
+
+
+def cdfci_batch_tables(batch):
+    """Table slots planned for each instance."""
+    out = np.zeros(batch.count, np.uint64)
+    _check(_lib.load().cdfci_batch_tables(batch.handle, _up(out)), "cdfci_batch_tables")
+    return out
 
 
 # ---------------------------------------------------------------- several states (xCDFCI)

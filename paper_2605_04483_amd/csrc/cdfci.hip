@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -66,15 +67,6 @@ hipError_t resolve_scratch(int device) {
     }                                                                                   \
   } while (0)
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t _e = (expr);                                                             \
-    if (_e != hipSuccess) {                                                             \
-      g_last_error = std::string(#expr) + ": " + hipGetErrorString(_e);                 \
-      return CDFCI_ERR_HIP;                                                             \
-    }                                                                                   \
-  } while (0)
-
 // Control block in device memory: the solver's scalar state between launches.
 struct Ctl {
   double mu_hi, mu_lo, al_hi, al_lo;  // mu = c.c, alpha = c.Hc (double-double)
@@ -86,6 +78,8 @@ struct Ctl {
   int64_t steps;                      // iterations since init
   unsigned long long occupied;        // stored determinants
   unsigned long long inserts;
+  unsigned long long probes;          // slots inspected by multicoordinate scatters
+  unsigned long long atomics;         // FP64 atomic b updates of multicoordinate scatters
   int error;
   int stopped;
   int max_probe;
@@ -970,6 +964,42 @@ __global__ void k_entry(Ham H, uint64_t a1, uint64_t b1, uint64_t a2, uint64_t b
   *out = sc_entry(H, a1, b1, a2, b2, L, d);
 }
 
+// Random-access calibration (cdfci_random_access_rates): the memory
+// operations the column scatter is made of, each on its own over uniformly
+// random slots of a table as large as the solver's.  Only the timing matters;
+// the values written are meaningless.
+__global__ void __launch_bounds__(256) k_ra_fill(Slot* T, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    T[i].ka = hash_key(i, 1);
+    T[i].kb = hash_key(i, 2);
+    T[i].c = 0.0;
+    T[i].b = 0.0;
+  }
+}
+// kind 0: 16-byte key gather; 1: gather and plain read-modify-write of b;
+// 2: gather and agent-scope FP64 atomic add to b; 3: returning atomic OR into
+// a bitmap of one bit per slot
+__global__ void __launch_bounds__(256) k_ra(Slot* T, unsigned* bitmap, uint64_t mask, uint64_t n, uint64_t salt,
+                                            int kind, unsigned long long* sink) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t idx = hash_key(i, salt) & mask;
+  uint64_t acc = 0;
+  if (kind == 3) {
+    acc = atomicOr(&bitmap[idx >> 5], 1u << (idx & 31));
+  } else {
+    const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&T[idx]);
+    acc = kk.x ^ kk.y;
+    if (kind == 1 && acc != 1) T[idx].b = T[idx].b + 1.0;
+    if (kind == 2 && acc != 1) atomic_add_f64(&T[idx].b, 1.0);
+  }
+  if (acc == 1) *sink = acc;  // keeps the loads
+}
+__global__ void __launch_bounds__(256) k_ra_copy(const double4* a, double4* b, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 // compact occupied slots (c != 0 if nonzero_c) into a list of slot ids
 __global__ void __launch_bounds__(256) k_compact(const Slot* T, uint64_t nslots, int nonzero_c, int64_t* list,
                           unsigned long long* count, int64_t cap) {
@@ -1050,13 +1080,13 @@ __global__ void k_sum_partials(const double* num, const double* den, int n, doub
 #include "xcd_kernels.h"
 #include "orb_kernels.h"
 
-// per-instance step budget of the coming batch call (traced: only instance
-// `only` advances)
-__global__ void k_hub_limits(HubInst* inst, int n, int64_t nsteps, int only) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t s = inst[i].ctl->steps;
-  inst[i].step_limit = (only < 0 || only == i) ? s + nsteps : s;
+// per-instance step budget of the coming wave: the listed (resident)
+// instances may advance nsteps iterations
+__global__ void k_hub_limits(HubInst* inst, const unsigned* ids, int n, int64_t nsteps) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  HubInst& P = inst[ids[k]];
+  P.step_limit = P.ctl->steps + nsteps;
 }
 
 struct HubResult {
@@ -1066,11 +1096,13 @@ struct HubResult {
   int stopped, error;
 };
 
-__global__ void k_hub_results(const HubInst* inst, int n, HubResult* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Ctl* c = inst[i].ctl;
-  out[i] = HubResult{(c->al_hi + c->al_lo) / (c->mu_hi + c->mu_lo), c->steps, *inst[i].elements,
+// results of the listed (resident) instances, in list order
+__global__ void k_hub_results(const HubInst* inst, const unsigned* ids, int n, HubResult* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const HubInst& P = inst[ids[k]];
+  const Ctl* c = P.ctl;
+  out[k] = HubResult{(c->al_hi + c->al_lo) / (c->mu_hi + c->mu_lo), c->steps, *P.elements,
                      c->occupied, c->stopped, c->error};
 }
 
@@ -1125,9 +1157,19 @@ struct cdfci_ctx {
 
 struct cdfci_batch {
   int count = 0;
-  std::vector<cdfci_ctx*> ctx;
-  std::vector<HubInst> h_inst;
+  std::vector<cdfci_hubbard_spec> specs;
+  std::vector<cdfci_ctx*> ctx;              // resident instances (nullptr otherwise)
+  std::vector<uint64_t> slots;              // planned table slots per instance
+  std::vector<HubInst> h_inst;              // host copy of the per-instance kernel arguments
+  std::vector<HubResult> res;               // last known results (steps counted since init)
+  std::vector<int> init_error;              // CDFCI_ERR_* of an instance whose start failed
+  std::vector<int64_t> base_steps;          // iterations before the last restart
+  std::vector<std::vector<uint64_t>> ck_keys;  // checkpoint of an evicted running instance
+  std::vector<std::vector<double>> ck_c;
+  uint64_t budget = 0, resident = 0, peak = 0;
+  int restarts = 0;
   HubInst* d_inst = nullptr;
+  unsigned* d_active = nullptr;
   unsigned* d_queue = nullptr;
   unsigned long long* d_elems = nullptr;
   HubResult* d_res = nullptr;
@@ -1135,6 +1177,7 @@ struct cdfci_batch {
   bool own_stream = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int graph_n = -1, graph_waves = -1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   cdfci_batch_opts opts;
   int waves = 0;
@@ -1603,6 +1646,8 @@ static int run_cd1(cdfci_ctx* c, int64_t nsteps, double* trE, uint64_t* tra, uin
     out->total_steps = h.steps;
     out->elements = out->steps * c->n_col;
     out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->probes = 0;
+    out->atomics = 0;
     out->occupied = h.occupied;
     out->max_probe = h.max_probe;
     out->stopped = h.stopped;
@@ -1734,9 +1779,9 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     if (k <= kEigSmall)
       k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
     else if (k <= 256)
-      k_mc_eig<256><<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_lobpcg<256><<<kEigGrid, 1024, 0, s>>>(ea);
     else
-      k_mc_eig<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_lobpcg<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
     k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
     k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);
@@ -1762,6 +1807,8 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     out->total_steps = h.steps;
     out->elements = done * (int64_t)k * c->n_col;
     out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->probes = (int64_t)(h.probes - before.probes);
+    out->atomics = (int64_t)(h.atomics - before.atomics);
     out->occupied = h.occupied;
     out->max_probe = h.max_probe;
     out->stopped = h.stopped;
@@ -2104,6 +2151,50 @@ int cdfci_mc_selection(cdfci_ctx* c, uint64_t* keys, double* eta, int64_t cap, i
   return 0;
 }
 
+int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates) {
+  if (!rates || n_ops < 1 || table_slots < 1024 || (table_slots & (table_slots - 1))) return CDFCI_ERR_INVALID_ARG;
+  CallBufs bufs;
+  Slot* T;
+  unsigned* bm;
+  unsigned long long* sink;
+  const uint64_t ncopy = (1ull << 30) / sizeof(double4);
+  double4 *ca, *cb;
+  HIP_TRY(bufs.alloc(&T, table_slots));
+  HIP_TRY(bufs.alloc(&bm, table_slots / 32));
+  HIP_TRY(bufs.alloc(&sink, 1));
+  HIP_TRY(bufs.alloc(&ca, ncopy));
+  HIP_TRY(bufs.alloc(&cb, ncopy));
+  HIP_TRY(hipMemset(bm, 0, table_slots / 32 * sizeof(unsigned)));
+  HIP_TRY(hipMemset(ca, 0, ncopy * sizeof(double4)));
+  k_ra_fill<<<4096, 256>>>(T, table_slots);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int grid = (int)((n_ops + 255) / 256);
+  int rc = 0;
+  for (int kind = 0; kind < 5 && !rc; ++kind) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (hipEventRecord(e0) != hipSuccess) rc = CDFCI_ERR_HIP;
+      if (kind < 4)
+        k_ra<<<grid, 256>>>(T, bm, table_slots - 1, (uint64_t)n_ops, 1000003ull * (rep + 1) + kind, kind, sink);
+      else
+        k_ra_copy<<<4096, 256>>>(ca, cb, ncopy);
+      if (hipEventRecord(e1) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = CDFCI_ERR_HIP;
+      float ms = 0.0f;
+      if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = CDFCI_ERR_HIP;
+      if (rep > 0 && ms < best) best = ms;  // the first run warms up
+    }
+    rates[kind] = kind < 4 ? (double)n_ops / (best * 1e-3) : 2.0 * (double)(1ull << 30) / (best * 1e-3);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc && hipGetLastError() != hipSuccess) rc = CDFCI_ERR_HIP;
+  return rc;
+}
+
 int cdfci_load(cdfci_ctx* c, const uint64_t* keys, const double* cv, int64_t count) {
   if (!c || !keys || !cv || count < 1) return CDFCI_ERR_INVALID_ARG;
   if ((uint64_t)count > c->max_entries) return CDFCI_ERR_TABLE_FULL;
@@ -2230,6 +2321,8 @@ int cdfci_step_search(cdfci_ctx* c, int64_t nsteps, int64_t chunk, double fill, 
     out->steps = done;
     out->elements = elements;
     out->inserts = inserts;
+    out->probes = 0;
+    out->atomics = 0;
     out->seconds = seconds;
   }
   return 0;
@@ -2259,15 +2352,65 @@ int cdfci_free(cdfci_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Batches of Hubbard lattices
+// Batches of Hubbard lattices: a memory-budgeted scheduler over one
+// persistent kernel.  Instances are created when first admitted; the tables
+// of the resident ones stay within the budget.
+
+// The wavefunction of a context (stored entries with c != 0, true scale) into
+// host vectors: keys interleaved (alpha, beta) and c.  Device memory used:
+// the context's slot list, sized to that support only.
+static int export_support(cdfci_ctx* c, std::vector<uint64_t>& keys, std::vector<double>& cv) {
+  hipStream_t s = c->stream;
+  if (c->mode == 1) {  // true values: fold the multicoordinate lazy scale in
+    k_mc_rescale<<<2048, 256, 0, s>>>(c->T, c->nslots, c->mst, 1);
+    k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 1);
+  }
+  unsigned long long* d_cnt = (unsigned long long*)(c->dscratch + 2 * 4096 + 4);
+  unsigned long long n = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
+    k_compact<<<2048, 256, 0, s>>>(c->T, c->nslots, 1, c->list, d_cnt, c->list_cap);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&n, d_cnt, sizeof(n), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((int64_t)n <= c->list_cap) break;
+    const int rc = ensure_list(c, (int64_t)n);
+    if (rc) return rc;
+  }
+  keys.assign(2 * n, 0);
+  cv.assign(n, 0.0);
+  if (n == 0) return 0;
+  CallBufs bufs;
+  uint64_t* dk;
+  double *dc, *db;
+  HIP_TRY(bufs.alloc(&dk, 2 * n));
+  HIP_TRY(bufs.alloc(&dc, n));
+  HIP_TRY(bufs.alloc(&db, n));
+  k_gather<<<1024, 256, 0, s>>>(c->T, c->list, (int64_t)n, dk, dc, db);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(keys.data(), dk, 2 * n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(cv.data(), dc, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+static uint64_t batch_bytes(const cdfci_batch* B, int i) { return B->slots[i] * sizeof(Slot); }
+
+static int batch_release(cdfci_batch* B, int i) {
+  if (!B->ctx[i]) return 0;
+  cdfci_free(B->ctx[i]);
+  B->ctx[i] = nullptr;
+  B->resident -= batch_bytes(B, i);
+  return 0;
+}
 
 int cdfci_free_batch(cdfci_batch* B) {
   if (!B) return 0;
   if (B->stream) (void)hipStreamSynchronize(B->stream);
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
-  for (cdfci_ctx* c : B->ctx) cdfci_free(c);
-  void* bufs[] = {B->d_inst, B->d_queue, B->d_elems, B->d_res};
+  for (int i = 0; i < B->count; ++i) batch_release(B, i);
+  void* bufs[] = {B->d_inst, B->d_active, B->d_queue, B->d_elems, B->d_res};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (B->ev0) (void)hipEventDestroy(B->ev0);
@@ -2277,67 +2420,251 @@ int cdfci_free_batch(cdfci_batch* B) {
   return 0;
 }
 
-static int batch_create(const cdfci_hubbard_spec* specs, int count, cdfci_batch* B) {
+// table slots of every instance from the options (FCI dimension / load factor,
+// capped by max_table_slots and by the budget)
+static void batch_plan(cdfci_batch* B) {
   const cdfci_batch_opts& o = B->opts;
-  if (o.stream) {
-    B->stream = (hipStream_t)o.stream;
-  } else {
-    HIP_TRY(hipStreamCreate(&B->stream));
-    B->own_stream = true;
-  }
-  HIP_TRY(hipMalloc(&B->d_elems, count * sizeof(unsigned long long)));
-  HIP_TRY(hipMemsetAsync(B->d_elems, 0, count * sizeof(unsigned long long), B->stream));
-  for (int i = 0; i < count; ++i) {
-    const cdfci_hubbard_spec& sp = specs[i];
-    int L = 1;
-    for (int k = 0; k < sp.ndim; ++k) L *= sp.dims[k];
-    const std::vector<std::pair<int, int>> bonds = lattice_bonds(sp.dims, sp.ndim);
+  for (int i = 0; i < B->count; ++i) {
+    const cdfci_hubbard_spec& sp = B->specs[i];
     uint64_t slots = o.table_slots;
     if (!slots) {
+      int L = 1;
+      for (int k = 0; k < sp.ndim; ++k) L *= sp.dims[k];
       // FCI dimension C(L, na) C(L, nb) as a double (only its size matters)
       double dim = 1.0;
       for (int k = 0; k < sp.n_alpha; ++k) dim = dim * (L - k) / (k + 1);
       for (int k = 0; k < sp.n_beta; ++k) dim = dim * (L - k) / (k + 1);
       slots = 1024;
-      while ((double)slots * o.load_factor < dim && slots < o.max_table_slots) slots <<= 1;
+      while ((double)slots * o.load_factor < dim && slots < (1ull << 40)) slots <<= 1;
+      if (o.max_table_slots && slots > o.max_table_slots) slots = o.max_table_slots;
     }
-    cdfci_opts co;
-    memset(&co, 0, sizeof(co));
-    co.table_slots = slots;
-    co.load_factor = o.load_factor;
-    co.z_threshold = o.z_threshold;
-    co.dx_damping = o.dx_damping;
-    co.dx_threshold = o.dx_threshold;
-    co.stream = B->stream;
-    cdfci_ctx* c = nullptr;
-    int rc = cdfci_init_hubbard(sp.dims, sp.ndim, sp.t, sp.U, sp.n_alpha, sp.n_beta, &co, &c);
-    if (rc) return rc;
-    B->ctx.push_back(c);
-    HubInst hi;
-    memset(&hi, 0, sizeof(hi));
-    hi.T = c->T;
-    hi.mask = c->mask;
-    hi.max_entries = c->max_entries;
-    hi.ctl = c->ctl;
-    hi.step_limit = 0;
-    hi.elements = B->d_elems + i;
-    hi.t = sp.t;
-    hi.U = sp.U;
-    hi.nbonds = (int)bonds.size();
-    for (size_t k = 0; k < bonds.size(); ++k) {
-      hi.bi[k] = (uint8_t)bonds[k].first;
-      hi.bj[k] = (uint8_t)bonds[k].second;
-    }
-    B->h_inst.push_back(hi);
+    while (slots > 1024 && slots * sizeof(Slot) > B->budget) slots >>= 1;
+    B->slots[i] = slots;
   }
-  HIP_TRY(hipMalloc(&B->d_inst, count * sizeof(HubInst)));
-  HIP_TRY(hipMemcpyAsync(B->d_inst, B->h_inst.data(), count * sizeof(HubInst), hipMemcpyHostToDevice,
-                         B->stream));
-  HIP_TRY(hipMalloc(&B->d_queue, 2 * sizeof(unsigned)));
-  HIP_TRY(hipMalloc(&B->d_res, count * sizeof(HubResult)));
-  HIP_TRY(hipEventCreate(&B->ev0));
-  HIP_TRY(hipEventCreate(&B->ev1));
+}
+
+// results of the resident instances into B->res (steps counted since init)
+static int batch_gather(cdfci_batch* B) {
+  std::vector<unsigned> ids;
+  for (int i = 0; i < B->count; ++i)
+    if (B->ctx[i]) ids.push_back((unsigned)i);
+  if (ids.empty()) return 0;
+  const int n = (int)ids.size();
+  std::vector<HubResult> r((size_t)n);
+  HIP_TRY(hipMemcpyAsync(B->d_active, ids.data(), n * sizeof(unsigned), hipMemcpyHostToDevice, B->stream));
+  k_hub_results<<<(n + 255) / 256, 256, 0, B->stream>>>(B->d_inst, B->d_active, n, B->d_res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(r.data(), B->d_res, n * sizeof(HubResult), hipMemcpyDeviceToHost, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
+  for (int k = 0; k < n; ++k) {
+    HubResult x = r[(size_t)k];
+    x.steps += B->base_steps[ids[k]];
+    B->res[ids[k]] = x;
+  }
+  return 0;
+}
+
+// create (or restore from its checkpoint) instance i and make it resident
+static int batch_admit(cdfci_batch* B, int i) {
+  const cdfci_batch_opts& o = B->opts;
+  const cdfci_hubbard_spec& sp = B->specs[i];
+  cdfci_opts co;
+  memset(&co, 0, sizeof(co));
+  co.table_slots = B->slots[i];
+  co.load_factor = o.load_factor;
+  co.z_threshold = o.z_threshold;
+  co.dx_damping = o.dx_damping;
+  co.dx_threshold = o.dx_threshold;
+  co.stream = B->stream;
+  cdfci_ctx* c = nullptr;
+  int rc = cdfci_init_hubbard(sp.dims, sp.ndim, sp.t, sp.U, sp.n_alpha, sp.n_beta, &co, &c);
+  if (rc == 0 && !B->ck_keys[i].empty()) {
+    rc = cdfci_load(c, B->ck_keys[i].data(), B->ck_c[i].data(), (int64_t)B->ck_c[i].size());
+    if (rc == 0) ++B->restarts;
+  }
+  if (rc) {
+    if (c) cdfci_free(c);
+    if (rc == CDFCI_ERR_HIP || rc == CDFCI_ERR_INVALID_ARG) return rc;
+    B->res[i].error = rc == CDFCI_ERR_TABLE_FULL ? kErrTableFull : kErrNumeric;
+    B->init_error[i] = rc;
+    return 0;
+  }
+  B->ck_keys[i].clear();
+  B->ck_keys[i].shrink_to_fit();
+  B->ck_c[i].clear();
+  B->ck_c[i].shrink_to_fit();
+  B->ctx[i] = c;
+  B->resident += batch_bytes(B, i);
+  B->peak = std::max(B->peak, B->resident);
+  HubInst& hi = B->h_inst[i];
+  hi.T = c->T;
+  hi.mask = c->mask;
+  hi.max_entries = c->max_entries;
+  hi.ctl = c->ctl;
+  hi.step_limit = 0;
+  HIP_TRY(hipMemcpyAsync(B->d_inst + i, &hi, sizeof(HubInst), hipMemcpyHostToDevice, B->stream));
+  return 0;
+}
+
+// make room by releasing a resident instance that is not in `keep`: a
+// finished one outright, a running one after checkpointing its (key, c) list
+static int batch_evict_one(cdfci_batch* B, const std::vector<char>& keep, bool* done) {
+  *done = false;
+  int victim = -1;
+  for (int pass = 0; pass < 2 && victim < 0; ++pass)
+    for (int i = 0; i < B->count; ++i) {
+      if (!B->ctx[i] || keep[i]) continue;
+      const bool finished = B->res[i].error || B->res[i].stopped;
+      if (pass == 0 ? finished : true) {
+        victim = i;
+        break;
+      }
+    }
+  if (victim < 0) return 0;
+  const int i = victim;
+  if (!(B->res[i].error || B->res[i].stopped)) {
+    // the checkpoint is the wavefunction: the entries with c != 0
+    const int rc = export_support(B->ctx[i], B->ck_keys[i], B->ck_c[i]);
+    if (rc) return rc;
+    B->base_steps[i] = B->res[i].steps;  // a restart counts from zero again
+  }
+  batch_release(B, i);
+  *done = true;
+  return 0;
+}
+
+static HubArgs batch_args(const cdfci_batch* B, int n_active) {
+  HubArgs a;
+  a.inst = B->d_inst;
+  a.active = B->d_active;
+  a.n_inst = n_active;
+  a.queue = B->d_queue;
+  a.chunk = B->opts.chunk_steps;
+  a.tau = B->opts.z_threshold;
+  a.theta = B->opts.dx_damping;
+  a.dx_tol = B->opts.dx_threshold;
+  a.trace_inst = -1;
+  a.tr_E = nullptr;
+  a.tr_a = nullptr;
+  a.tr_b = nullptr;
+  return a;
+}
+
+// run the resident instances `ids` until each has stopped, failed or used
+// nsteps iterations; the replayed graph is captured for this wave's size
+static int batch_run_wave(cdfci_batch* B, const std::vector<unsigned>& ids, int64_t nsteps, int* replays) {
+  hipStream_t s = B->stream;
+  const int n = (int)ids.size();
+  if (n == 0 || nsteps <= 0) return 0;
+  for (unsigned i : ids)
+    if (B->ctx[i]->mode == 1) {  // stepped with k > 1 through its context: fold and reselect
+      const int e = enter_single(B->ctx[i]);
+      if (e) return e;
+    }
+  HIP_TRY(hipMemcpyAsync(B->d_active, ids.data(), n * sizeof(unsigned), hipMemcpyHostToDevice, s));
+  k_hub_limits<<<(n + 255) / 256, 256, 0, s>>>(B->d_inst, B->d_active, n, nsteps);
+  HIP_TRY(hipGetLastError());
+  const int R = B->opts.launches_per_graph;
+  const int waves = std::min(B->waves, n);
+  if (!B->exec || B->graph_n != n || B->graph_waves != waves) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    const HubArgs a = batch_args(B, n);
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < R; ++r) {
+      k_hub_reset<<<1, 1, 0, s>>>(B->d_queue);
+      k_hub_batch<<<waves, 64, 0, s>>>(a);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) {
+      g_last_error = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+      return CDFCI_ERR_HIP;
+    }
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->graph_n = n;
+    B->graph_waves = waves;
+  }
+  // every visit of a running instance advances it by min(chunk, budget left)
+  // steps, so the budget is spent within this many replays
+  const int64_t visits = (nsteps + B->opts.chunk_steps - 1) / B->opts.chunk_steps;
+  const int64_t max_replays = (visits + R - 1) / R + 1;
+  for (int64_t it = 0; it < max_replays; ++it) {
+    HIP_TRY(hipGraphLaunch(B->exec, s));
+    ++*replays;
+    unsigned active = 0;
+    HIP_TRY(hipMemcpyAsync(&active, B->d_queue + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (active == 0) break;
+  }
+  return 0;
+}
+
+// one scheduled pass: every instance in `want` (with work left) runs once
+static int batch_schedule(cdfci_batch* B, const std::vector<char>& want, int64_t nsteps, int* replays,
+                          int* rounds) {
+  std::vector<char> pending(want);
+  for (;;) {
+    std::vector<char> wave((size_t)B->count, 0);
+    std::vector<unsigned> ids;
+    bool any = false;
+    for (int i = 0; i < B->count; ++i) {
+      if (!pending[i]) continue;
+      if (B->res[i].error || B->res[i].stopped) {
+        pending[i] = 0;
+        continue;
+      }
+      any = true;
+      if (B->ctx[i]) {
+        wave[i] = 1;
+        ids.push_back((unsigned)i);
+      }
+    }
+    if (!any) break;
+    // admit in index order while the tables fit, evicting instances outside
+    // this call's remaining work (finished ones first)
+    for (int i = 0; i < B->count; ++i) {
+      if (!pending[i] || B->ctx[i] || B->res[i].error) continue;
+      const uint64_t need = batch_bytes(B, i);
+      bool fits = B->resident + need <= B->budget;
+      while (!fits) {
+        std::vector<char> keep(pending);
+        for (int j = 0; j < B->count; ++j) keep[j] |= wave[j];
+        bool done = false;
+        const int rc = batch_evict_one(B, keep, &done);
+        if (rc) return rc;
+        if (!done) break;
+        fits = B->resident + need <= B->budget;
+      }
+      if (!fits) break;  // the rest waits for the next wave
+      const int rc = batch_admit(B, i);
+      if (rc) return rc;
+      if (B->ctx[i]) {
+        wave[i] = 1;
+        ids.push_back((unsigned)i);
+      } else {
+        pending[i] = 0;  // its start failed: marked in its results
+      }
+    }
+    if (ids.empty()) {
+      // nothing resident has work and nothing fits: only pending instances
+      // hold memory, so a table larger than the budget is left
+      bool stuck = false;
+      for (int i = 0; i < B->count; ++i) stuck |= pending[i] && !B->res[i].error && !B->res[i].stopped;
+      if (stuck) return CDFCI_ERR_WORKSPACE;
+      break;
+    }
+    std::sort(ids.begin(), ids.end());
+    int rc = batch_run_wave(B, ids, nsteps, replays);
+    if (rc) return rc;
+    ++*rounds;
+    rc = batch_gather(B);
+    if (rc) return rc;
+    for (unsigned i : ids) pending[i] = 0;
+  }
   return 0;
 }
 
@@ -2349,13 +2676,13 @@ int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const c
   cdfci_batch_opts o;
   memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
-  if (o.max_table_slots == 0) o.max_table_slots = 1ull << 22;
   if (o.load_factor <= 0.0) o.load_factor = 0.79;
   if (o.dx_damping <= 0.0) o.dx_damping = 0.9;
   if (o.chunk_steps <= 0) o.chunk_steps = 1024;
   if (o.launches_per_graph <= 0) o.launches_per_graph = 4;
   if (o.waves <= 0) o.waves = std::min(count, 8192);
   if ((o.table_slots & (o.table_slots - 1)) != 0 || (o.max_table_slots & (o.max_table_slots - 1)) != 0 ||
+      (o.table_slots && o.table_slots < 64) || (o.max_table_slots && o.max_table_slots < 1024) ||
       o.load_factor > 0.95 || o.launches_per_graph > 64)
     return CDFCI_ERR_INVALID_ARG;
   // every spec is checked before any device work
@@ -2376,121 +2703,124 @@ int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const c
   B->count = count;
   B->opts = o;
   B->waves = o.waves;
-  const int rc = batch_create(specs, count, B);
-  if (rc) {
+  B->specs.assign(specs, specs + count);
+  B->ctx.assign(count, nullptr);
+  B->slots.assign(count, 0);
+  B->res.assign(count, HubResult{0.0, 0, 0, 0, 0, 0});
+  B->init_error.assign(count, 0);
+  B->base_steps.assign(count, 0);
+  B->ck_keys.resize(count);
+  B->ck_c.resize(count);
+  auto fail = [&](int rc) {
     cdfci_free_batch(B);
     return rc;
+  };
+  if (o.memory_budget) {
+    B->budget = o.memory_budget;
+  } else {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(CDFCI_ERR_HIP);
+    B->budget = (uint64_t)(0.85 * (double)fr);
   }
+  if (o.stream) {
+    B->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreate(&B->stream) != hipSuccess) return fail(CDFCI_ERR_HIP);
+    B->own_stream = true;
+  }
+  batch_plan(B);
+  B->h_inst.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const cdfci_hubbard_spec& sp = specs[i];
+    const std::vector<std::pair<int, int>> bonds = lattice_bonds(sp.dims, sp.ndim);
+    HubInst& hi = B->h_inst[i];
+    memset(&hi, 0, sizeof(hi));
+    hi.t = sp.t;
+    hi.U = sp.U;
+    hi.nbonds = (int)bonds.size();
+    for (size_t k = 0; k < bonds.size(); ++k) {
+      hi.bi[k] = (uint8_t)bonds[k].first;
+      hi.bj[k] = (uint8_t)bonds[k].second;
+    }
+  }
+  if (hipMalloc(&B->d_elems, count * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&B->d_inst, count * sizeof(HubInst)) != hipSuccess ||
+      hipMalloc(&B->d_active, count * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&B->d_queue, 2 * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&B->d_res, count * sizeof(HubResult)) != hipSuccess || hipEventCreate(&B->ev0) != hipSuccess ||
+      hipEventCreate(&B->ev1) != hipSuccess)
+    return fail(CDFCI_ERR_HIP);
+  for (int i = 0; i < count; ++i) B->h_inst[i].elements = B->d_elems + i;
+  if (hipMemsetAsync(B->d_elems, 0, count * sizeof(unsigned long long), B->stream) != hipSuccess ||
+      hipMemcpyAsync(B->d_inst, B->h_inst.data(), count * sizeof(HubInst), hipMemcpyHostToDevice, B->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(B->stream) != hipSuccess)
+    return fail(CDFCI_ERR_HIP);
+  // admit what fits now (the instances' starts), so small batches are resident at once
+  std::vector<char> none((size_t)count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (B->resident + batch_bytes(B, i) > B->budget) break;
+    const int rc = batch_admit(B, i);
+    if (rc) return fail(rc);
+  }
+  const int rc = batch_gather(B);
+  if (rc) return fail(rc);
   *out = B;
   return 0;
-}
-
-static int batch_gather(cdfci_batch* B, std::vector<HubResult>& r) {
-  r.resize(B->count);
-  k_hub_results<<<(B->count + 255) / 256, 256, 0, B->stream>>>(B->d_inst, B->count, B->d_res);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(r.data(), B->d_res, B->count * sizeof(HubResult), hipMemcpyDeviceToHost, B->stream));
-  HIP_TRY(hipStreamSynchronize(B->stream));
-  return 0;
-}
-
-static HubArgs batch_args(const cdfci_batch* B) {
-  HubArgs a;
-  a.inst = B->d_inst;
-  a.n_inst = B->count;
-  a.queue = B->d_queue;
-  a.chunk = B->opts.chunk_steps;
-  a.tau = B->opts.z_threshold;
-  a.theta = B->opts.dx_damping;
-  a.dx_tol = B->opts.dx_threshold;
-  a.trace_inst = -1;
-  a.tr_E = nullptr;
-  a.tr_a = nullptr;
-  a.tr_b = nullptr;
-  return a;
 }
 
 int cdfci_step_batch(cdfci_batch* B, int64_t max_steps, cdfci_batch_stats* out) {
   if (!B || max_steps < 0) return CDFCI_ERR_INVALID_ARG;
   hipStream_t s = B->stream;
-  // instances stepped through their own context with k > 1 hold a lazy
-  // scale: fold it and reselect as a k = 1 step would
-  for (cdfci_ctx* c : B->ctx)
-    if (c->mode == 1) {
-      const int e = enter_single(c);
-      if (e) return e;
-    }
-  std::vector<HubResult> r0, r1;
-  int rc = batch_gather(B, r0);
+  int rc = batch_gather(B);
   if (rc) return rc;
-  k_hub_limits<<<(B->count + 255) / 256, 256, 0, s>>>(B->d_inst, B->count, max_steps, -1);
-  HIP_TRY(hipGetLastError());
-  const int R = B->opts.launches_per_graph;
-  if (!B->exec) {
-    const HubArgs a = batch_args(B);
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < R; ++i) {
-      k_hub_reset<<<1, 1, 0, s>>>(B->d_queue);
-      k_hub_batch<<<B->waves, 64, 0, s>>>(a);
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess) {
-      g_last_error = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
-      return CDFCI_ERR_HIP;
-    }
-    B->graph = g;
-    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
-  }
-  // every visit of a running instance advances it by min(chunk, budget left)
-  // steps, so the budget is spent within this many replays
-  const int64_t visits = (max_steps + B->opts.chunk_steps - 1) / B->opts.chunk_steps;
-  const int64_t max_replays = (visits + R - 1) / R + 1;
-  int replays = 0;
+  const std::vector<HubResult> r0 = B->res;
+  const int restarts0 = B->restarts;
+  B->peak = B->resident;
+  int replays = 0, rounds = 0;
   HIP_TRY(hipEventRecord(B->ev0, s));
-  for (int64_t it = 0; it < max_replays && max_steps > 0; ++it) {
-    HIP_TRY(hipGraphLaunch(B->exec, s));
-    ++replays;
-    unsigned active = 0;
-    HIP_TRY(hipMemcpyAsync(&active, B->d_queue + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (active == 0) break;
-  }
+  std::vector<char> want((size_t)B->count, 1);
+  if (max_steps > 0) rc = batch_schedule(B, want, max_steps, &replays, &rounds);
+  if (rc) return rc;
   HIP_TRY(hipEventRecord(B->ev1, s));
-  rc = batch_gather(B, r1);
+  HIP_TRY(hipEventSynchronize(B->ev1));
+  rc = batch_gather(B);
   if (rc) return rc;
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, B->ev0, B->ev1));
-  int failed = 0;
-  for (int i = 0; i < B->count; ++i) failed += r1[i].error != 0;
   if (out) {
     memset(out, 0, sizeof(*out));
     for (int i = 0; i < B->count; ++i) {
-      out->steps += r1[i].steps - r0[i].steps;
-      out->elements += (int64_t)(r1[i].elements - r0[i].elements);
-      if (r1[i].error) continue;
-      if (r1[i].stopped) ++out->stopped;
+      const HubResult& a = r0[(size_t)i];
+      const HubResult& b = B->res[(size_t)i];
+      out->steps += b.steps - a.steps;
+      out->elements += (int64_t)(b.elements - a.elements);
+      if (b.error) ++out->failed;
+      else if (b.stopped) ++out->stopped;
       else ++out->running;
     }
-    out->failed = failed;
     out->graph_replays = replays;
+    out->rounds = rounds;
+    out->restarts = B->restarts - restarts0;
     out->seconds = ms * 1e-3;
+    out->peak_bytes = (double)B->peak;
   }
   return 0;
 }
 
 int cdfci_batch_results(cdfci_batch* B, double* energy, int64_t* steps, int* status) {
   if (!B) return CDFCI_ERR_INVALID_ARG;
-  std::vector<HubResult> r;
-  int rc = batch_gather(B, r);
+  int rc = batch_gather(B);
   if (rc) return rc;
   for (int i = 0; i < B->count; ++i) {
-    if (energy) energy[i] = r[i].energy;
-    if (steps) steps[i] = r[i].steps;
+    const HubResult& r = B->res[(size_t)i];
+    if (energy) energy[i] = r.energy;
+    if (steps) steps[i] = r.steps;
     if (status) {
-      int st = r[i].stopped ? 1 : 0;
-      if (r[i].error & kErrTableFull) st = CDFCI_ERR_TABLE_FULL;
-      else if (r[i].error) st = CDFCI_ERR_NUMERIC;
+      int st = r.stopped ? 1 : 0;
+      if (B->init_error[i]) st = B->init_error[i];
+      else if (r.error & kErrTableFull) st = CDFCI_ERR_TABLE_FULL;
+      else if (r.error) st = CDFCI_ERR_NUMERIC;
       status[i] = st;
     }
   }
@@ -2501,22 +2831,44 @@ int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, 
                       uint64_t* sel_beta) {
   if (!B || inst < 0 || inst >= B->count || nsteps < 0) return CDFCI_ERR_INVALID_ARG;
   hipStream_t s = B->stream;
-  std::vector<HubResult> r0, r1;
-  int rc = batch_gather(B, r0);
+  int rc = batch_gather(B);
   if (rc) return rc;
-  const int64_t step0 = r0[inst].steps;
-  if (B->ctx[inst]->mode == 1) {
-    rc = enter_single(B->ctx[inst]);
+  if (!B->ctx[inst]) {
+    // a released finished instance has no state left to continue from
+    if (B->res[inst].error || B->res[inst].stopped) return CDFCI_ERR_INVALID_ARG;
+    std::vector<char> keep((size_t)B->count, 0);
+    keep[inst] = 1;
+    while (B->resident + batch_bytes(B, inst) > B->budget) {
+      bool done = false;
+      rc = batch_evict_one(B, keep, &done);
+      if (rc) return rc;
+      if (!done) return CDFCI_ERR_WORKSPACE;
+    }
+    rc = batch_admit(B, inst);
+    if (rc) return rc;
+    if (!B->ctx[inst]) return CDFCI_ERR_INVALID_ARG;
+    rc = batch_gather(B);
     if (rc) return rc;
   }
+  cdfci_ctx* c = B->ctx[inst];
+  if (c->mode == 1) {
+    rc = enter_single(c);
+    if (rc) return rc;
+  }
+  Ctl h0;
+  rc = ctl_read(c, &h0);
+  if (rc) return rc;
+  const int64_t step0 = h0.steps;  // trace arrays are indexed by the context's step count
   CallBufs bufs;
   double* dE;
   uint64_t *da, *db;
   HIP_TRY(bufs.alloc(&dE, step0 + nsteps));
   HIP_TRY(bufs.alloc(&da, step0 + nsteps));
   HIP_TRY(bufs.alloc(&db, step0 + nsteps));
-  k_hub_limits<<<(B->count + 255) / 256, 256, 0, s>>>(B->d_inst, B->count, nsteps, inst);
-  HubArgs a = batch_args(B);
+  const unsigned id = (unsigned)inst;
+  HIP_TRY(hipMemcpyAsync(B->d_active, &id, sizeof(unsigned), hipMemcpyHostToDevice, s));
+  k_hub_limits<<<1, 256, 0, s>>>(B->d_inst, B->d_active, 1, nsteps);
+  HubArgs a = batch_args(B, 1);
   a.trace_inst = inst;
   a.tr_E = dE;
   a.tr_a = da;
@@ -2524,16 +2876,19 @@ int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, 
   const int64_t visits = (nsteps + B->opts.chunk_steps - 1) / B->opts.chunk_steps;
   for (int64_t it = 0; it < visits + 1 && nsteps > 0; ++it) {
     k_hub_reset<<<1, 1, 0, s>>>(B->d_queue);
-    k_hub_batch<<<B->waves, 64, 0, s>>>(a);
+    k_hub_batch<<<1, 64, 0, s>>>(a);
     HIP_TRY(hipGetLastError());
     unsigned active = 0;
     HIP_TRY(hipMemcpyAsync(&active, B->d_queue + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (active == 0) break;
   }
-  rc = batch_gather(B, r1);
+  Ctl h1;
+  rc = ctl_read(c, &h1);
   if (rc) return rc;
-  const int64_t done = r1[inst].steps - step0;
+  rc = batch_gather(B);
+  if (rc) return rc;
+  const int64_t done = h1.steps - step0;
   if (done > 0) {
     if (energy) HIP_TRY(hipMemcpy(energy, dE + step0, done * sizeof(double), hipMemcpyDeviceToHost));
     if (sel_alpha) HIP_TRY(hipMemcpy(sel_alpha, da + step0, done * sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -2544,12 +2899,16 @@ int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, 
 
 int cdfci_batch_context(cdfci_batch* B, int inst, cdfci_ctx** ctx) {
   if (!B || !ctx || inst < 0 || inst >= B->count) return CDFCI_ERR_INVALID_ARG;
+  if (!B->ctx[inst]) return CDFCI_ERR_INVALID_ARG;
   *ctx = B->ctx[inst];
   return 0;
 }
 
-// ---------------------------------------------------------------------------
-// Autotuning
+int cdfci_batch_tables(cdfci_batch* B, uint64_t* slots) {
+  if (!B || !slots) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < B->count; ++i) slots[i] = B->slots[i];
+  return 0;
+}
 
 int cdfci_tune_k(cdfci_ctx* c, const int* ks, int nk, double seconds_per_trial, int rounds, int* best_k,
                  double* rates) {
@@ -2595,43 +2954,87 @@ int cdfci_tune_k(cdfci_ctx* c, const int* ks, int nk, double seconds_per_trial, 
   return 0;
 }
 
-int cdfci_tune_batch(cdfci_batch* B, const int64_t* chunks, int nc, const int* launches, int nl,
-                     int64_t steps_per_trial, int64_t* best_chunk, int* best_launches) {
-  if (!B || !chunks || nc < 1 || !launches || nl < 1 || steps_per_trial < 1) return CDFCI_ERR_INVALID_ARG;
-  for (int i = 0; i < nc; ++i)
-    if (chunks[i] < 1) return CDFCI_ERR_INVALID_ARG;
-  for (int i = 0; i < nl; ++i)
-    if (launches[i] < 1 || launches[i] > 64) return CDFCI_ERR_INVALID_ARG;
-  double best_rate = -1.0;
-  int64_t bc = B->opts.chunk_steps;
-  int bl = B->opts.launches_per_graph;
-  for (int i = 0; i < nc; ++i)
-    for (int j = 0; j < nl; ++j) {
-      // a new setting needs a new graph
-      if (B->exec) (void)hipGraphExecDestroy(B->exec);
-      if (B->graph) (void)hipGraphDestroy(B->graph);
-      B->exec = nullptr;
-      B->graph = nullptr;
-      B->opts.chunk_steps = chunks[i];
-      B->opts.launches_per_graph = launches[j];
-      cdfci_batch_stats st;
-      const int rc = cdfci_step_batch(B, steps_per_trial, &st);
-      if (rc) return rc;
-      const double rate = st.seconds > 0.0 ? (double)st.steps / st.seconds : 0.0;
-      if (rate > best_rate) {
-        best_rate = rate;
-        bc = chunks[i];
-        bl = launches[j];
-      }
-    }
+// a new load factor: every table is re-planned; resident instances are
+// checkpointed (running) or released (finished) and restarted at their new size
+static int batch_replan(cdfci_batch* B, double lf) {
+  std::vector<char> keep((size_t)B->count, 0);
+  for (;;) {
+    bool done = false;
+    const int rc = batch_evict_one(B, keep, &done);
+    if (rc) return rc;
+    if (!done) break;
+  }
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->exec = nullptr;
   B->graph = nullptr;
+  B->graph_n = -1;
+  B->opts.load_factor = lf;
+  batch_plan(B);
+  return 0;
+}
+
+int cdfci_tune_batch(cdfci_batch* B, const int64_t* chunks, int nc, const int* launches, int nl,
+                     const double* lfs, int nlf, int64_t steps_per_trial, int64_t* best_chunk, int* best_launches,
+                     double* best_lf) {
+  if (!B || !chunks || nc < 1 || !launches || nl < 1 || steps_per_trial < 1 || nlf < 0 || (nlf && !lfs))
+    return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nc; ++i)
+    if (chunks[i] < 1) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nl; ++i)
+    if (launches[i] < 1 || launches[i] > 64) return CDFCI_ERR_INVALID_ARG;
+  for (int i = 0; i < nlf; ++i)
+    if (!(lfs[i] > 0.0 && lfs[i] <= 0.95)) return CDFCI_ERR_INVALID_ARG;
+  std::vector<double> cand_lf;
+  if (nlf) cand_lf.assign(lfs, lfs + nlf);
+  else cand_lf.push_back(B->opts.load_factor);
+  double best_rate = -1.0;
+  int64_t bc = B->opts.chunk_steps;
+  int bl = B->opts.launches_per_graph;
+  double blf = B->opts.load_factor;
+  for (double lf : cand_lf) {
+    if (lf != B->opts.load_factor) {
+      const int rc = batch_replan(B, lf);
+      if (rc) return rc;
+    }
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nl; ++j) {
+        // a new setting needs a new graph
+        if (B->exec) (void)hipGraphExecDestroy(B->exec);
+        if (B->graph) (void)hipGraphDestroy(B->graph);
+        B->exec = nullptr;
+        B->graph = nullptr;
+        B->graph_n = -1;
+        B->opts.chunk_steps = chunks[i];
+        B->opts.launches_per_graph = launches[j];
+        cdfci_batch_stats st;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = cdfci_step_batch(B, steps_per_trial, &st);
+        if (rc) return rc;
+        const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const double rate = wall > 0.0 ? (double)st.steps / wall : 0.0;
+        if (rate > best_rate) {
+          best_rate = rate;
+          bc = chunks[i];
+          bl = launches[j];
+          blf = lf;
+        }
+      }
+  }
+  if (blf != B->opts.load_factor) {
+    const int rc = batch_replan(B, blf);
+    if (rc) return rc;
+  }
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  B->graph_n = -1;
   B->opts.chunk_steps = bc;
   B->opts.launches_per_graph = bl;
   if (best_chunk) *best_chunk = bc;
   if (best_launches) *best_launches = bl;
+  if (best_lf) *best_lf = blf;
   return 0;
 }
 
@@ -3017,6 +3420,8 @@ int cdfci_xstep(cdfci_xctx* X, int64_t nsteps, double* energies, uint64_t* sel_a
     out->total_steps = h.steps;
     out->elements = done * X->n_col;
     out->inserts = (int64_t)(h.inserts - before.inserts);
+    out->probes = 0;
+    out->atomics = 0;
     out->occupied = h.occupied;
     out->max_probe = h.max_probe;
     out->stopped = h.stopped;

@@ -26,8 +26,9 @@ struct HubInst {
 };
 
 struct HubArgs {
-  const HubInst* inst;
-  int n_inst;
+  const HubInst* inst;    // every instance of the batch
+  const unsigned* active; // ids of the resident instances this launch serves
+  int n_inst;             // entries of `active`
   unsigned* queue;  // [0] next instance, [1] instances still running after their visit
   int64_t chunk;
   double tau, theta, dx_tol;
@@ -78,8 +79,9 @@ __global__ void __launch_bounds__(64) k_hub_batch(HubArgs A) {
   // wave stays whole on every path.
   for (;;) {
     const unsigned got = atomicAdd(&A.queue[0], lane == 0 ? 1u : 0u);
-    const unsigned id = uni32(got);
-    if (id >= (unsigned)A.n_inst) break;
+    const unsigned q = uni32(got);
+    if (q >= (unsigned)A.n_inst) break;
+    const unsigned id = uni32(A.active[q]);
     const HubInst& P = A.inst[id];
     Slot* T = P.T;
     const uint64_t mask = uni64(P.mask);

@@ -863,6 +863,302 @@ __global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
   mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
 }
 
+// Several workgroup sums at once (one barrier pair for all of them), each in
+// a fixed order; v[0..NS) per thread in, the totals in every thread out.
+template <int NS>
+__device__ __forceinline__ void wg_sums(double* v, double* s_red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v[q], off);
+      v[q] = (lane & off) ? (o + v[q]) : (v[q] + o);
+    }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) s_red[q * 16 + w] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += s_red[q * 16 + i];
+    v[q] = t;
+  }
+  __syncthreads();
+}
+
+// Lowest eigenpair of a symmetric 3 x 3 matrix g (row-major) by cyclic Jacobi
+// rotations, one thread; columns whose `use` flag is off are left out (their
+// rows and columns are zero and never chosen).  y gets the unit eigenvector.
+__device__ inline double sym3_lowest(const double* g_in, const int* use, double* y) {
+  double a[3][3], v[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      a[i][j] = (use[i] && use[j]) ? g_in[i * 3 + j] : 0.0;
+      v[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {  // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = c * vkp - sn * vkq;
+          v[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  int best = -1;
+  for (int i = 0; i < 3; ++i)
+    if (use[i] && (best < 0 || a[i][i] < a[best][best])) best = i;
+  for (int k = 0; k < 3; ++k) y[k] = use[k] ? v[k][best] : 0.0;
+  return a[best][best];
+}
+
+// The reduced problem for k > 64 by LOBPCG (locally optimal block
+// preconditioned conjugate gradient, one vector): from x = [nu; c_I] / |.|,
+// each iteration takes the Rayleigh-Ritz minimum of A over span{x, w, p}
+// with w = D^-1 (A x - theta x) the residual preconditioned by the diagonal
+// D = diag(A) - theta and p the previous step; p and then w are
+// orthonormalised against the others (Gram-Schmidt twice, the products with
+// A transformed alike) before the 3 x 3 eigenproblem, so the Ritz pair stays
+// accurate to rounding.  Stops at |A x - theta x| <= 1e-11 |theta| (the
+// eigenvalue error is quadratic in the residual) or after kLobpcgMax
+// iterations.  One matrix-vector product per iteration; everything else is
+// a handful of workgroup sums.
+constexpr int kLobpcgMax = 300;
+
+template <int KM>
+__global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
+  __shared__ double s_c[KM], s_b[KM], s_a0[KM], s_d[KM + 1];
+  __shared__ double s_x[KM + 1], s_w[KM + 1], s_p[KM + 1], s_ax[KM + 1], s_aw[KM + 1], s_ap[KM + 1];
+  __shared__ double s_part[1024];
+  __shared__ double s_red[16 * 8];
+  __shared__ double s_g[9], s_y[3];
+  __shared__ int s_use[3];
+  if (blockIdx.x > 0) {
+    mc_clear_bitmap(A);
+    return;
+  }
+  Ctl* ctl = A.ctl;
+  if (A.st->skip) return;
+  const int tid = threadIdx.x;
+  const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
+  const double s = A.st->scale;
+  const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
+  const double* hii = A.hii;
+  for (int i = tid; i < m; i += blockDim.x) {
+    const Slot sl = A.T[A.sel_slot[i]];
+    s_c[i] = s * sl.c;
+    s_b[i] = s * sl.b;
+  }
+  __syncthreads();
+  // hc = H_II c_I
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_c, s_w, s_part);
+  __syncthreads();
+  const double hc_i = tid < m ? s_w[tid] : 0.0;
+  const double ci = tid < m ? s_c[tid] : 0.0, bi = tid < m ? s_b[tid] : 0.0;
+  const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
+  const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
+  const dd chc = wg_sum_dd(two_prod(ci, hc_i), s_red);
+  const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
+  const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
+  const double nu2v = dd_val(nu2);
+  const int off = nu2v > kNu2Floor * dd_val(mu) ? 1 : 0;
+  const double nu = off ? sqrt(nu2v) : 0.0;
+  const double a00 = off ? dd_val(num) / nu2v : 0.0;
+  if (tid < m) {
+    s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
+    s_d[off + tid] = hii[(size_t)tid * m + tid];
+  }
+  if (tid == 0 && off) s_d[0] = a00;
+  const int n = m + off;
+  if (n == 0) {  // nothing stored and nothing chosen: no step is possible
+    if (tid == 0) ctl->stopped = 1;
+    return;
+  }
+  // x = [nu; c_I] normalised, Ax, theta
+  {
+    double v[1] = {0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      const double t = (off && r == 0) ? nu : s_c[r - off];
+      s_x[r] = t;
+      v[0] += t * t;
+    }
+    wg_sums<1>(v, s_red);
+    const double nrm = sqrt(v[0]);
+    for (int r = tid; r < n; r += blockDim.x) s_x[r] = nrm > 0.0 ? s_x[r] / nrm : (r == 0 ? 1.0 : 0.0);
+    for (int r = tid; r < n; r += blockDim.x) {
+      s_p[r] = 0.0;
+      s_ap[r] = 0.0;
+    }
+  }
+  __syncthreads();
+  mc_matvec(hii, m, off, a00, s_a0, s_x, s_ax, s_part);
+  __syncthreads();
+  double theta;
+  {
+    double v[1] = {0.0};
+    for (int r = tid; r < n; r += blockDim.x) v[0] += s_x[r] * s_ax[r];
+    wg_sums<1>(v, s_red);
+    theta = v[0];
+  }
+  bool have_p = false;
+  int iters = 0;
+  for (int it = 0; it < kLobpcgMax; ++it) {
+    // residual and its preconditioned form
+    double v[1] = {0.0};
+    const double dfloor = 1e-8 * (fabs(theta) + 1.0);
+    for (int r = tid; r < n; r += blockDim.x) {
+      const double res = s_ax[r] - theta * s_x[r];
+      v[0] += res * res;
+      double dn = s_d[r] - theta;
+      if (fabs(dn) < dfloor) dn = dn < 0.0 ? -dfloor : dfloor;
+      s_w[r] = res / dn;
+    }
+    wg_sums<1>(v, s_red);
+    iters = it;
+    if (sqrt(v[0]) <= 1e-11 * fabs(theta)) break;
+    // orthonormalise p against x (twice, A p along), then w against x and p
+    if (have_p) {
+      for (int pass = 0; pass < 2; ++pass) {
+        double q[1] = {0.0};
+        for (int r = tid; r < n; r += blockDim.x) q[0] += s_x[r] * s_p[r];
+        wg_sums<1>(q, s_red);
+        for (int r = tid; r < n; r += blockDim.x) {
+          s_p[r] -= q[0] * s_x[r];
+          s_ap[r] -= q[0] * s_ax[r];
+        }
+        __syncthreads();
+      }
+      double pq[1] = {0.0};
+      for (int r = tid; r < n; r += blockDim.x) pq[0] += s_p[r] * s_p[r];
+      wg_sums<1>(pq, s_red);
+      have_p = pq[0] > 1e-28;
+      const double ip = have_p ? 1.0 / sqrt(pq[0]) : 0.0;
+      for (int r = tid; r < n; r += blockDim.x) {
+        s_p[r] *= ip;
+        s_ap[r] *= ip;
+      }
+      __syncthreads();
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      double q[2] = {0.0, 0.0};
+      for (int r = tid; r < n; r += blockDim.x) {
+        q[0] += s_x[r] * s_w[r];
+        q[1] += s_p[r] * s_w[r];
+      }
+      wg_sums<2>(q, s_red);
+      for (int r = tid; r < n; r += blockDim.x) s_w[r] -= q[0] * s_x[r] + (have_p ? q[1] * s_p[r] : 0.0);
+      __syncthreads();
+    }
+    double nw[1] = {0.0};
+    for (int r = tid; r < n; r += blockDim.x) nw[0] += s_w[r] * s_w[r];
+    wg_sums<1>(nw, s_red);
+    const bool use_w = nw[0] > 1e-28;
+    const double inw = use_w ? 1.0 / sqrt(nw[0]) : 0.0;
+    for (int r = tid; r < n; r += blockDim.x) s_w[r] *= inw;
+    __syncthreads();
+    // A w (A p is carried)
+    mc_matvec(hii, m, off, a00, s_a0, s_w, s_aw, s_part);
+    __syncthreads();
+    // Gram matrix of A on [x, w, p]
+    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      g[0] += s_x[r] * s_ax[r];
+      g[1] += s_x[r] * s_aw[r];
+      g[2] += s_x[r] * s_ap[r];
+      g[3] += s_w[r] * s_aw[r];
+      g[4] += s_w[r] * s_ap[r];
+      g[5] += s_p[r] * s_ap[r];
+    }
+    wg_sums<6>(g, s_red);
+    if (tid == 0) {
+      const double G[9] = {g[0], g[1], g[2], g[1], g[3], g[4], g[2], g[4], g[5]};
+      for (int q = 0; q < 9; ++q) s_g[q] = G[q];
+      s_use[0] = 1;
+      s_use[1] = use_w ? 1 : 0;
+      s_use[2] = have_p ? 1 : 0;
+      double y[3];
+      sym3_lowest(s_g, s_use, y);
+      s_y[0] = y[0];
+      s_y[1] = y[1];
+      s_y[2] = y[2];
+    }
+    __syncthreads();
+    const double y0 = s_y[0], y1 = s_y[1], y2 = s_y[2];
+    // p <- y1 w + y2 p, x <- y0 x + p (and the same for the products with A)
+    double pn[1] = {0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      const double np = y1 * s_w[r] + y2 * s_p[r];
+      const double nap = y1 * s_aw[r] + y2 * s_ap[r];
+      s_x[r] = y0 * s_x[r] + np;
+      s_ax[r] = y0 * s_ax[r] + nap;
+      s_p[r] = np;
+      s_ap[r] = nap;
+      pn[0] += np * np;
+    }
+    wg_sums<1>(pn, s_red);
+    have_p = pn[0] > 1e-28;
+    // p kept of unit length (the basis is re-orthonormalised each iteration)
+    const double ipn = have_p ? 1.0 / sqrt(pn[0]) : 0.0;
+    double xx[2] = {0.0, 0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      s_p[r] *= ipn;
+      s_ap[r] *= ipn;
+      xx[0] += s_x[r] * s_x[r];
+      xx[1] += s_x[r] * s_ax[r];
+    }
+    wg_sums<2>(xx, s_red);
+    // x renormalised against rounding drift; theta its Rayleigh quotient
+    const double ixn = 1.0 / sqrt(xx[0]);
+    for (int r = tid; r < n; r += blockDim.x) {
+      s_x[r] *= ixn;
+      s_ax[r] *= ixn;
+    }
+    theta = xx[1] / xx[0];
+    __syncthreads();
+    iters = it + 1;
+  }
+  const double lam = theta;
+  // z = sqrt(-lambda) x
+  const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
+  for (int r = tid; r < n; r += blockDim.x) s_w[r] = zscale * s_x[r];
+  __syncthreads();
+  // sign: z_0 >= 0 with the c~ column, else z . c_I >= 0
+  double zc[1] = {0.0};
+  if (!off)
+    for (int r = tid; r < n; r += blockDim.x) zc[0] += s_w[r] * s_c[r];
+  wg_sums<1>(zc, s_red);
+  const double sgn = off ? (s_w[0] < 0.0 ? -1.0 : 1.0) : (zc[0] < 0.0 ? -1.0 : 1.0);
+  const double gamma = off ? sgn * s_w[0] / nu : 1.0;
+  double eta_i = 0.0;
+  if (tid < m) eta_i = sgn * s_w[off + tid] - gamma * s_c[tid];
+  __syncthreads();
+  if (tid < m) s_x[tid] = eta_i;
+  __syncthreads();
+  mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, s_part);
+  __syncthreads();
+  const double heta_i = tid < m ? s_w[tid] : 0.0;
+  mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
+}
+
 constexpr int kEigSmall = 64;  // m up to this: the eigen step runs from shared memory
 constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest clear)
 
@@ -1172,10 +1468,11 @@ struct ScatterArgs {
 // leaves b alone exactly as for an absent key.  A key seen while its beta word
 // is still being published is looked up again with coherent loads.
 __device__ __forceinline__ int64_t scatter_find(const Slot* __restrict__ T, uint64_t mask, uint64_t a,
-                                                uint64_t b, double* c) {
+                                                uint64_t b, double* c, int* nprobe) {
   uint64_t idx = hash_key(a, b) & mask;
   for (int n = 0; n < kMaxProbe; ++n) {
     const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&T[idx]);
+    *nprobe = n + 1;
     if (kk.x == kEmpty) return -1;
     if (kk.x == a) {
       if (kk.y == b) {
@@ -1187,6 +1484,7 @@ __device__ __forceinline__ int64_t scatter_find(const Slot* __restrict__ T, uint
         SlotVal sv;
         const int64_t s = table_find(T, mask, a, b, &probes, &sv);
         if (s >= 0) *c = sv.c;
+        *nprobe = n + 1 + probes;
         return s;
       }
     }
@@ -1199,7 +1497,7 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
   __shared__ Lists L;
   __shared__ double s_diag;
   __shared__ double s_red[4];
-  __shared__ unsigned s_ins, s_ncand;
+  __shared__ unsigned s_ins, s_ncand, s_probes, s_atomics;
   __shared__ int s_err;
   const int y = blockIdx.y;
   const unsigned page = (unsigned)(y * gridDim.x + blockIdx.x);
@@ -1218,6 +1516,8 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
     s_ins = 0;
     s_err = 0;
     s_ncand = 0;
+    s_probes = 0;
+    s_atomics = 0;
   }
   __syncthreads();
   const Ham H = A.H;
@@ -1236,7 +1536,7 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
     __syncthreads();
   }
   double recalc = 0.0;
-  int err = 0;
+  int err = 0, my_probes = 0, my_atomics = 0;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < A.n_col) {
     uint64_t ja = a, jb = b;
@@ -1245,16 +1545,22 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
       int probes = 0;
       SlotVal sv;
       double cj = 0.0;
-      int64_t slot = scatter_find(A.T, A.mask, ja, jb, &cj);
+      int nfind = 0;
+      int64_t slot = scatter_find(A.T, A.mask, ja, jb, &cj, &nfind);
+      my_probes += nfind;
       if (e != 0) {
         const bool big = fabs(eta * Hj) >= A.tau;
         if (slot < 0 && big) {
           int ins = 0;
           slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
+          my_probes += probes;
           if (ins) atomicAdd(&s_ins, 1u);
           cj = slot >= 0 ? sv.c : 0.0;
         }
-        if (slot >= 0 && (cj != 0.0 || big)) atomic_add_f64(&A.T[slot].b, Hj * coef);
+        if (slot >= 0 && (cj != 0.0 || big)) {
+          atomic_add_f64(&A.T[slot].b, Hj * coef);
+          ++my_atomics;
+        }
         if (slot >= 0) {
           const unsigned bit = 1u << (slot & 31);
           const unsigned old = atomicOr(&A.bitmap[slot >> 5], bit);
@@ -1272,12 +1578,16 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
   for (int offs = 32; offs > 0; offs >>= 1) recalc += __shfl_xor(recalc, offs);
   if (lane == 0) s_red[w] = recalc;
   if (err) atomicOr(&s_err, err);
+  if (my_probes) atomicAdd(&s_probes, (unsigned)my_probes);
+  if (my_atomics) atomicAdd(&s_atomics, (unsigned)my_atomics);
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += s_red[i];
     atomic_add_f64(&A.recalc[y], r);
     A.cnt[page] = s_ncand;
+    if (s_probes) atomicAdd(&ctl->probes, (unsigned long long)s_probes);
+    if (s_atomics) atomicAdd(&ctl->atomics, (unsigned long long)s_atomics);
     if (s_ins) atomicAdd(&ctl->occupied, (unsigned long long)s_ins);
     if (s_ins) atomicAdd(&ctl->inserts, (unsigned long long)s_ins);
     if (s_err) atomicOr(&ctl->error, s_err);

@@ -49,8 +49,13 @@ def test_tune_batch_then_converge(api):
         L = int(np.prod(dims))
         specs.append({"dims": dims, "t": 1.0, "U": U, "n_alpha": (L + 1) // 2, "n_beta": L // 2})
     B = api.cdfci_init_hubbard_batch(specs, dx_threshold=1e-11)
-    chunk, launches = api.cdfci_tune_batch(B, chunks=(128, 1024), launches=(1, 4), steps_per_trial=2000)
-    assert chunk in (128, 1024) and launches in (1, 4)
+    slots0 = api.cdfci_batch_tables(B)
+    chunk, launches, lf = api.cdfci_tune_batch(B, chunks=(128, 1024), launches=(1, 4), load_factors=(0.3, 0.79),
+                                               steps_per_trial=2000)
+    assert chunk in (128, 1024) and launches in (1, 4) and lf in (0.3, 0.79)
+    slots = api.cdfci_batch_tables(B)
+    # the tables follow the chosen load factor (larger at 0.3 for the sizes here)
+    assert np.all(slots >= slots0) if lf == 0.3 else np.array_equal(slots, slots0)
     for _ in range(10):
         st = api.cdfci_step_batch(B, 500_000)
         print(f"batch: {st}", flush=True)

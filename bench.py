@@ -1,38 +1,31 @@
 """Benchmark of the coordinate-descent FCI hot path on one MI355X.
 
-Headline workload (`value`): synthetic ab initio Hamiltonian, 24 spatial
-orbitals, 6 alpha + 6 beta electrons, 72 auxiliary vectors (seed 2024), hash
-table of 2^28 slots, single-coordinate CDFCI (Alg. 1) for 10^6 iterations in
-total (warmup + timed) with compression threshold tau = 5e-5 (at tau = 0 the
-2^28-slot table reaches its 0.79 load limit after about 4.6e5 iterations).
-One benchmark step = one cdfci_step call of --iters iterations (each: select,
-line search, enumerate the 16471-entry column, Slater-Condon, probe, scatter,
-recalculate b_i).  `value` = enumerated column entries per second.
+Headline workload (`value`): batched multicoordinate CDFCI (Alg. 2) on the
+synthetic ab initio Hamiltonian of 36 spatial orbitals, 8 alpha + 8 beta
+electrons, 108 auxiliary vectors (seed 3636), hash table of 2^30 slots,
+compression threshold tau = 5e-5, k coordinates per step chosen by the
+autotuner among {64, 256, 1024} (energy decrease per device-second, trial
+steps counted as warm-up).  One benchmark step = --iters multicoordinate
+iterations, each: top-k selection over the previous columns, H_II, the
+(k+1)-dimensional reduced eigenproblem, enumeration and Slater-Condon
+evaluation of the k columns (71,793 entries each), hash probes, FP64
+scatter of H eta into b under the compression rule, recalculation of b_I.
+`value` = enumerated column entries per second (zeros included).
 
 Further blocks on the same JSON line (skipped with --no-extra):
-  batched_vs_plain  the same N = 24 system from a fresh start with the
-                    multicoordinate step (k picked by the autotuner), timed to
-                    the energy the plain run reached;
-  mcd_n36           N = 36, 8+8, naux 108, 2^30 slots, tau 5e-5: elements/s and
-                    ms per step for k = 64, 256, 1024; k = 1 for a fixed wall time,
-                    then the autotuned multicoordinate step timed to that energy;
-  hubbard_batch     256 periodic lattices from {2x4, 3x4, 4x4, 2x8, 3x5}, half
-                    filling, U ~ [2, 10], in one persistent kernel under a
-                    replayed graph (autotuned), against the single-instance
-                    path on a sample of the same instances;
-  rdm               RDM reverse pass on the top 10^6 determinants of the
-                    headline run's final state;
-  xcdfci            several low-lying states (Alg. 3) on the headline system:
-                    4 states, 2^26-slot table, tau = 5e-5, iterations/s and
-                    entries/s of the persistent multi-state kernel, with the
-                    multi-state oracle timed on its first iterations;
-  hubbard_k         the paper's 4x4 momentum-space Hubbard case (U/t = 4,
-                    8+8, degenerate-subspace start): iterations/s and the
-                    energy after 2e5 iterations against the exact value the
-                    paper quotes;
-  optorb            OptOrbFCI (Alg. 4) on the headline integrals: 12 of the 24
-                    orbitals, 4a+4b, 3 outer iterations of 20000 CD steps and
-                    up to 30 projected steps each; seconds per outer iteration.
+  to_target         "batched vs plain to 1e-5 Ha": a smaller synthetic system
+                    whose CD limit one GPU reaches, run by plain CD and by the
+                    autotuned multicoordinate step until converged; E* = the
+                    lower of the two limits, and the wall time of each to
+                    E* + 1e-5 Ha;
+  plain_n24         single-coordinate CDFCI (Alg. 1) on 24 orbitals, 6+6,
+                    2^28 slots, tau = 5e-5, 1e6 iterations, with the roofline
+                    of its persistent kernel k_cd1;
+  rdm               the reverse pass on the top 1e6 determinants of that run;
+  random_access     the rates of the scatter's memory operations alone on
+                    random slots (the ceilings the probes and atomics are
+                    compared with);
+  xcdfci, hubbard_k, optorb, hubbard_batch   the widened rows.
 
 --copy-probe runs only a device copy of known size (for calibrating the HBM
 byte counters of a profiler run) and exits.
@@ -49,163 +42,237 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_ELEMENT = 40
-COUNTERS = os.path.join(ROOT, "profiles", "k_cd1_abinitio_n24_hbm_counters.md")
-# k_cd1 is compiled from csrc/device.h and the part of csrc/cdfci.hip up to the
-# end of the kernel (the multicoordinate, reverse-pass and batch code follows it)
+BYTES_PER_ELEMENT = 40  # 32-byte slot read + 8-byte b update per column entry
+N36 = (36, 8, 8, 108)
+N36_COLUMN = 71793
+N24_COLUMN = 16471
+SCATTER_COUNTERS = os.path.join(ROOT, "profiles", "k_mc_scatter_abinitio_n36_hbm_counters.md")
+CD1_COUNTERS = os.path.join(ROOT, "profiles", "k_cd1_abinitio_n24_hbm_counters.md")
 K_CD1_END = b"// Adds the step count after the persistent kernel"
 
 
-def sources_sha256():
-    """sha256 of device.h followed by cdfci.hip up to the end of k_cd1."""
+def _sha(paths, cut=None):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2605_04483_amd/csrc/device.h"), "rb") as f:
-        h.update(f.read())
-    with open(os.path.join(ROOT, "paper_2605_04483_amd/csrc/cdfci.hip"), "rb") as f:
-        src = f.read()
-    end = src.find(K_CD1_END)
-    h.update(src if end < 0 else src[:end])
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            data = f.read()
+        if cut and p.endswith("cdfci.hip"):
+            end = data.find(cut)
+            data = data if end < 0 else data[:end]
+        h.update(data)
     return h.hexdigest()
 
 
-def measured_traffic_per_element():
-    """HBM bytes per column entry of k_cd1 from the committed counter runs,
-    or None when the kernel sources changed since they were taken."""
+def scatter_sources_sha256():
+    """sha256 of the sources k_mc_scatter is compiled from."""
+    return _sha(["paper_2605_04483_amd/csrc/device.h", "paper_2605_04483_amd/csrc/mcd_kernels.h"])
+
+
+def cd1_sources_sha256():
+    """sha256 of device.h followed by cdfci.hip up to the end of k_cd1."""
+    return _sha(["paper_2605_04483_amd/csrc/device.h", "paper_2605_04483_amd/csrc/cdfci.hip"], K_CD1_END)
+
+
+def measured_traffic_per_element(path, sha, k=None):
+    """HBM bytes per column entry from a committed counter profile, or None
+    when the kernel's sources (or the k it was taken at) differ."""
     try:
-        text = open(COUNTERS).read()
+        text = open(path).read()
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_element:\s*([0-9.]+)", text)
     s = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
-    if not m or not s or s.group(1) != sources_sha256():
+    if not m or not s or s.group(1) != sha:
         return None
+    if k is not None:
+        kk = re.search(r"profiled_k:\s*([0-9]+)", text)
+        if not kk or int(kk.group(1)) != k:
+            return None
     return float(m.group(1))
-
-
-def cpu_baseline_xcdfci(synth_inputs, tau, steps=20):
-    """The multi-state oracle (one core) on the first iterations of the
-    xcdfci block's run."""
-    from oracle import cd as ocd
-    from oracle import xcdfci as oxc
-
-    N, na, nb, n = 24, 6, 6, 4
-    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
-    keys, C0 = oxc.initial_rows(h, eri, ocd.aufbau(h, na, nb), n)
-    t0 = time.perf_counter()
-    orc = oxc.xcdfci_run(h, eri, keys, C0, tau=tau, max_steps=steps)
-    t_cpu = time.perf_counter() - t0
-    return {"value": orc.steps / t_cpu, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {steps} iterations from the same start (set-up included)"}
-
-
-def cpu_baseline(h, eri, na, nb, seconds_target=15.0):
-    """Serial oracle (C++, one core) on the same workload from the same start:
-    elements/s over a bounded number of iterations."""
-    from oracle import cd as ocd
-    from oracle import fci
-
-    keys, c0 = ocd.init_single(h, eri, na, nb)
-    n_col = fci.column_size(h.shape[0], na, nb)
-    t = time.perf_counter()
-    r = ocd.cd_run(h, eri, keys, c0, max_steps=200, trajectory=False)
-    dt = time.perf_counter() - t
-    iters = max(200, int(200 * seconds_target / max(dt, 1e-3)))
-    t = time.perf_counter()
-    r = ocd.cd_run(h, eri, keys, c0, max_steps=iters, trajectory=False)
-    dt = time.perf_counter() - t
-    return {"value": r.steps * n_col / dt, "unit": "H elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r.steps} iterations of the same run (serial C++ oracle, "
-                      f"{dt:.1f} s), iters/s = {r.steps / dt:.1f}"}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_vs_plain(api, h, eri, na, nb, args, E_plain, t_plain, n_col):
-    """Multicoordinate descent from a fresh start until it reaches E_plain."""
-    t0 = time.perf_counter()
-    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << args.table_log2, z_threshold=args.tau)
-    t_init = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    best_k, rates = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.05, rounds=2)
-    E = api.cdfci_energy(ctx)
-    steps = 0
-    elements = 0
-    while E > E_plain and time.perf_counter() - t0 < args.mc_limit:
-        st = api.cdfci_step(ctx, best_k, 20)
-        steps += st["steps"]
-        elements += st["elements"]
-        E = st["energy"]
-        if st["stopped"]:
-            break
-    t_mc = time.perf_counter() - t0
-    ctx.close()
-    return {"plain_seconds": t_plain, "plain_energy": E_plain,
-            "batched_seconds": t_mc, "batched_energy": E, "reached": bool(E <= E_plain),
-            "speedup": t_plain / t_mc if E <= E_plain else None,
-            "k": best_k, "tune_rates_Ha_per_s": rates, "batched_steps_after_tuning": steps,
-            "batched_elements_per_s_after_tuning": elements / max(t_mc, 1e-9),
-            "init_seconds": t_init,
-            "note": "both from their own fresh init; tuning trials count toward the batched time"}
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
-def mcd_n36(api, synth_inputs, args):
-    N, na, nb = 36, 8, 8
-    h, eri = synth_inputs.ab_initio(N, 108, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
-    out = {"workload": "ab initio N=36 8a+8b naux=108 seed=3636, 2^30-slot table, tau=5e-5",
-           "column_entries": 71793}
+def cpu_baselines(synth_inputs, args, seconds_target=12.0):
+    """The C++ oracle of Alg. 1 (serial, and its OpenMP form on every core the
+    process may use) on the headline's Hamiltonian from the same start, and
+    the Python oracle of Alg. 2 on its first multicoordinate step."""
+    from oracle import cd as ocd
+    from oracle import mcdfci as omc
+
+    N, na, nb, naux = N36
+    h, eri = synth_inputs.ab_initio(N, naux, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    cores = host_cores()
+    out = {}
+    for name, threads in (("serial", 1), ("openmp", cores)):
+        run = (lambda n: ocd.cd_run(h, eri, keys, c0, tau=args.tau, max_steps=n, trajectory=False)) if threads == 1 \
+            else (lambda n: ocd.cd_run_mt(h, eri, keys, c0, threads, tau=args.tau, max_steps=n, trajectory=False))
+        t = time.perf_counter()
+        run(40)
+        dt = time.perf_counter() - t
+        iters = max(40, int(40 * seconds_target / max(dt, 1e-3)))
+        t = time.perf_counter()
+        r = run(iters)
+        dt = time.perf_counter() - t
+        out[name] = {"value": r.steps * N36_COLUMN / dt, "unit": "H elements/s", "cores": threads, "kind": "oracle",
+                     "sample": f"first {r.steps} iterations of Alg. 1 (C++ oracle"
+                               f"{', OpenMP' if threads > 1 else ''}) on the headline's 36-orbital Hamiltonian "
+                               f"from the aufbau start, tau={args.tau}, {dt:.1f} s; {r.steps / dt:.1f} iterations/s"}
+    if not args.no_mc_oracle:
+        k = 16
+        t = time.perf_counter()
+        st = omc.mcdfci_run(h, eri, keys, c0, k, tau=args.tau, max_steps=1)
+        dt = time.perf_counter() - t
+        out["batched_oracle"] = {"value": k * N36_COLUMN / dt, "unit": "H elements/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"first step of Alg. 2 at k={k} (Python oracle, set-up included), {dt:.1f} s"}
+    return out
+
+
+def headline(api, synth_inputs, args):
     import torch
 
-    for k in ((args.n36_k,) if args.n36_k else (64, 256, 1024)):
-        ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
-        api.cdfci_step(ctx, k, 2)
+    N, na, nb, naux = N36
+    h, eri = synth_inputs.ab_initio(N, naux, synth_inputs.CONFIG_SEEDS["abinitio_n36"])
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=args.tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if args.k:
+        k, rates = args.k, None
+    else:
+        k, rates = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.05, rounds=2)
+    t_tune = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        api.cdfci_step(ctx, k, args.iters)
+    torch.cuda.synchronize()
+    api.cdfci_set_timing(ctx, True)
+    steps = elements = probes = atomics = inserts = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = api.cdfci_step(ctx, k, args.iters)
+        steps += st["steps"]
+        elements += st["elements"]
+        probes += st["probes"]
+        atomics += st["atomics"]
+        inserts += st["inserts"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = api.cdfci_mc_phase_times(ctx)
+    api.cdfci_set_timing(ctx, False)
+    e_exact = api.cdfci_energy(ctx, exact=1)
+    ctx.close()
+    return {"k": k, "tune_rates_Ha_per_s": rates, "tune_seconds": t_tune, "wall": wall, "steps": steps,
+            "elements": elements, "probes": probes, "atomics": atomics, "inserts": inserts,
+            "energy": st["energy"], "energy_exact": e_exact, "occupied": st["occupied"],
+            "phases": phases}
+
+
+def to_target(api, synth_inputs, args):
+    """Plain CD against the autotuned multicoordinate step on a system whose
+    CD limit one GPU reaches: both run from their own fresh start until they
+    converge (d < 1e-10, or the energy moves less than 1e-10 Ha over ten
+    reports) or a time limit; E* = the lower limit; time of each to E* + 1e-5.
+    The default system has n_alpha != n_beta: with equal counts H commutes
+    with the spin flip, and a multicoordinate run whose chosen sets stay
+    closed under it keeps one flip parity and may end at the lowest state of
+    the other parity than the ground state's (a stationary point of f)."""
+    import torch
+
+    N, na, nb, naux, seed = args.target_system
+    h, eri = synth_inputs.ab_initio(N, naux, seed)
+    out = {"workload": f"ab initio N={N} {na}a+{nb}b naux={naux} seed={seed}, 2^27-slot table, tau=0",
+           "tolerance_Ha": 1e-5}
+    traces = {}
+    for mode in ("plain", "batched"):
+        ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 27, dx_threshold=1e-10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = api.cdfci_step(ctx, k, args.n36_steps)
-        wall = time.perf_counter() - t0
-        out[f"k{k}"] = {"ms_per_step": 1e3 * wall / max(1, st["steps"]),
-                        "elements_per_s": st["elements"] / wall,
-                        "coordinate_updates_per_s": st["steps"] * k / wall,
-                        "energy": st["energy"]}
+        tr = [(0.0, api.cdfci_energy(ctx))]
+        k = 1
+        if mode == "batched":
+            k, _ = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.02, rounds=2)
+            tr.append((time.perf_counter() - t0, api.cdfci_energy(ctx)))
+        while time.perf_counter() - t0 < args.target_limit:
+            st = api.cdfci_step(ctx, k, 2000 if k == 1 else 10)
+            tr.append((time.perf_counter() - t0, st["energy"]))
+            if st["stopped"] or (len(tr) > 12 and abs(tr[-11][1] - tr[-1][1]) < 1e-10):
+                break
+        e_exact = api.cdfci_energy(ctx, exact=1)
         ctx.close()
-        log(f"n36 k={k}: {out[f'k{k}']}")
-    if args.n36_k:
-        return out
-    # plain single-coordinate descent for a fixed wall time, then the
-    # multicoordinate step (k autotuned) from its own fresh start, timed to the
-    # energy the plain run reached
-    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    while time.perf_counter() - t0 < args.n36_plain_seconds:
-        st = api.cdfci_step(ctx, 1, 20000)
-        iters += st["steps"]
-    t_plain = time.perf_counter() - t0
-    E_plain = st["energy"]
-    out["k1"] = {"iters_per_s": iters / t_plain, "elements_per_s": iters * 71793 / t_plain,
-                 "seconds": t_plain, "energy": E_plain}
-    ctx.close()
-    log(f"n36 plain: {out['k1']}")
-    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 30, z_threshold=5e-5)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    best_k, rates = api.cdfci_tune_k(ctx, (64, 256, 1024), seconds_per_trial=0.05, rounds=2)
-    E = api.cdfci_energy(ctx)
-    while E > E_plain and time.perf_counter() - t0 < 3 * t_plain:
-        st = api.cdfci_step(ctx, best_k, 10)
-        E = st["energy"]
-        if st["stopped"]:
-            break
-    t_mc = time.perf_counter() - t0
-    ctx.close()
-    out["batched_vs_plain"] = {"plain_seconds": t_plain, "plain_energy": E_plain, "batched_seconds": t_mc,
-                               "batched_energy": E, "reached": bool(E <= E_plain), "k": best_k,
-                               "speedup": t_plain / t_mc if E <= E_plain else None,
-                               "tune_rates_Ha_per_s": rates}
-    log(f"n36 batched vs plain: {out['batched_vs_plain']}")
+        traces[mode] = tr
+        out[mode] = {"k": k, "limit_energy": tr[-1][1], "limit_energy_exact": e_exact, "seconds": tr[-1][0],
+                     "converged": bool(st["stopped"] or abs(tr[-11][1] - tr[-1][1]) < 1e-10) if len(tr) > 11 else
+                     bool(st["stopped"])}
+        log(f"to_target {mode}: {out[mode]}")
+    E_star = min(out["plain"]["limit_energy"], out["batched"]["limit_energy"])
+    out["E_star"] = E_star
+    out["limit_gap_Ha"] = abs(out["plain"]["limit_energy"] - out["batched"]["limit_energy"])
+    for mode in ("plain", "batched"):
+        hit = next((t for t, e in traces[mode] if e <= E_star + 1e-5), None)
+        out[mode]["seconds_to_target"] = hit
+    tp, tb = out["plain"]["seconds_to_target"], out["batched"]["seconds_to_target"]
+    out["speedup"] = tp / tb if tp and tb else None
     return out
+
+
+def plain_n24(api, synth_inputs, args):
+    """Alg. 1 on 24 orbitals for args.n24_iters iterations; returns the block
+    and the live context (for the reverse pass)."""
+    import torch
+
+    N, na, nb, naux = 24, 6, 6, 72
+    h, eri = synth_inputs.ab_initio(N, naux, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 28, z_threshold=args.tau)
+    torch.cuda.synchronize()
+    chunk = 10000
+    kernel_s = 0.0
+    iters = 0
+    launches = 0
+    t0 = time.perf_counter()
+    while iters < args.n24_iters:
+        st = api.cdfci_step(ctx, 1, min(chunk, args.n24_iters - iters))
+        kernel_s += st["seconds"]
+        iters += st["steps"]
+        launches += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch = chunk * N24_COLUMN
+    avg = kernel_s / launches
+    per_el = measured_traffic_per_element(CD1_COUNTERS, cd1_sources_sha256())
+    achieved = BYTES_PER_ELEMENT * iters * N24_COLUMN / kernel_s / 1e9
+    blk = {"workload": f"ab initio N=24 6a+6b naux=72 seed=2024, 2^28-slot table, tau={args.tau}, "
+                       f"single-coordinate CDFCI, {iters} iterations",
+           "iterations": iters, "elements_per_s": iters * N24_COLUMN / wall, "cd_iters_per_s": iters / wall,
+           "us_per_iter": 1e6 * wall / iters, "energy": st["energy"], "occupied": st["occupied"],
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": (per_el * per_launch) if per_el is not None else None,
+                        "kernel": "k_cd1", "avg_launch_ms": 1e3 * avg,
+                        "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * per_launch}}
+    return blk, ctx
+
+
+def rdm_block(api, ctx, n_col):
+    top_n = 1_000_000
+    ka, _, _, _ = api.cdfci_export(ctx, top_n=top_n)
+    n_sup = len(ka)
+    t0 = time.perf_counter()
+    energy, dh, deri, kap = api.cdfci_rdm_backward(ctx, 1.0, top_n)
+    wall = time.perf_counter() - t0
+    return {"top_n": top_n, "support": n_sup, "seconds": wall,
+            "pair_visits_per_s": n_sup * n_col / wall, "energy_rdm": energy[0],
+            "energy_direct": energy[1], "note": "the support holds every determinant with c != 0 when it has "
+                                                "fewer than top_n; wall time of cdfci_rdm_backward incl. host copies "
+                                                "of gamma, Gamma (24^4) and kappa"}
 
 
 def hubbard_batch(api, synth_inputs, args):
@@ -213,11 +280,16 @@ def hubbard_batch(api, synth_inputs, args):
     t0 = time.perf_counter()
     B = api.cdfci_init_hubbard_batch(specs, dx_threshold=1e-10)
     t_init = time.perf_counter() - t0
-    chunk, launches, lf = api.cdfci_tune_batch(B, chunks=(512, 2048), launches=(2, 8), load_factors=(0.5, 0.79),
-                                               steps_per_trial=4000)
+    log(f"hubbard_batch: {len(specs)} lattices created in {t_init:.1f} s")
+    t0 = time.perf_counter()
+    chunk, launches, lf = api.cdfci_tune_batch(B, chunks=(1024,), launches=(2, 8), load_factors=(0.5, 0.79),
+                                               steps_per_trial=2000)
+    t_tune = time.perf_counter() - t0
+    log(f"hubbard_batch: tuned in {t_tune:.1f} s: chunk {chunk}, launches {launches}, load factor {lf}")
     t0 = time.perf_counter()
     st = api.cdfci_step_batch(B, args.batch_steps)
     wall = time.perf_counter() - t0
+    log(f"hubbard_batch: {st}")
     E, steps, status = api.cdfci_batch_results(B)
     B.close()
     # the single-instance path on a sample of the same instances, one after another
@@ -228,7 +300,7 @@ def hubbard_batch(api, synth_inputs, args):
             continue
         seen.add(sp["dims"])
         ctx = api.cdfci_init_hubbard(sp["dims"], sp["t"], sp["U"], sp["n_alpha"], sp["n_beta"],
-                                     table_slots=1 << 22)
+                                     table_slots=1 << 24)
         t1 = time.perf_counter()
         s1 = api.cdfci_step(ctx, 1, 20000)
         plain_wall += time.perf_counter() - t1
@@ -238,8 +310,9 @@ def hubbard_batch(api, synth_inputs, args):
     shapes = {}
     for sp in specs:
         shapes[str(sp["dims"])] = shapes.get(str(sp["dims"]), 0) + 1
-    return {"instances": len(specs), "shapes": shapes, "init_seconds": t_init,
-            "chunk_steps": chunk, "launches_per_graph": launches,
+    return {"instances": len(specs), "shapes": shapes, "init_seconds": t_init, "tune_seconds": t_tune,
+            "chunk_steps": chunk, "launches_per_graph": launches, "load_factor": lf,
+            "rounds": st["rounds"], "restarts": st["restarts"], "peak_table_bytes": st["peak_bytes"],
             "budget_per_instance": args.batch_steps,
             "iters_per_s": st["steps"] / wall, "elements_per_s": st["elements"] / wall,
             "wall_seconds": wall, "graph_replays": st["graph_replays"],
@@ -303,40 +376,43 @@ def optorb_block(api, synth_inputs, args):
             "energies": E.tolist(), "p4": P.tolist(), "seconds": wall, "seconds_per_outer": wall / len(E)}
 
 
-def rdm_block(api, ctx, n_col):
-    top_n = 1_000_000
-    ka, _, _, _ = api.cdfci_export(ctx, top_n=top_n)
-    n_sup = len(ka)
+def cpu_baseline_xcdfci(synth_inputs, tau, steps=20):
+    """The multi-state oracle (one core) on the first iterations of the
+    xcdfci block's run."""
+    from oracle import cd as ocd
+    from oracle import xcdfci as oxc
+
+    N, na, nb, n = 24, 6, 6, 4
+    h, eri = synth_inputs.ab_initio(N, 72, synth_inputs.CONFIG_SEEDS["abinitio_n24"])
+    keys, C0 = oxc.initial_rows(h, eri, ocd.aufbau(h, na, nb), n)
     t0 = time.perf_counter()
-    energy, dh, deri, kap = api.cdfci_rdm_backward(ctx, 1.0, top_n)
-    wall = time.perf_counter() - t0
-    return {"top_n": top_n, "support": n_sup, "seconds": wall,
-            "pair_visits_per_s": n_sup * n_col / wall, "energy_rdm": energy[0],
-            "energy_direct": energy[1], "note": "wall time of cdfci_rdm_backward incl. host copies of "
-                                                "gamma, Gamma (24^4) and kappa"}
+    orc = oxc.xcdfci_run(h, eri, keys, C0, tau=tau, max_steps=steps)
+    t_cpu = time.perf_counter() - t0
+    return {"value": orc.steps / t_cpu, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {steps} iterations from the same start (set-up included)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=95)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--iters", type=int, default=10000, help="CD iterations per benchmark step")
-    ap.add_argument("--table-log2", type=int, default=28)
+    ap.add_argument("--iters", type=int, default=10, help="multicoordinate iterations per benchmark step")
+    ap.add_argument("--k", type=int, default=0, help="coordinates per step (0: autotuned among 64, 256, 1024)")
     ap.add_argument("--tau", type=float, default=5e-5)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mc-oracle", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mc-limit", type=float, default=60.0)
-    ap.add_argument("--n36-steps", type=int, default=8)
-    ap.add_argument("--n36-plain-seconds", type=float, default=20.0)
+    ap.add_argument("--n24-iters", type=int, default=1_000_000)
+    ap.add_argument("--target-limit", type=float, default=40.0, help="seconds per run of the to_target block")
+    ap.add_argument("--target-system", type=int, nargs=5, default=(12, 6, 5, 36, 1),
+                    metavar=("N", "NA", "NB", "NAUX", "SEED"))
     ap.add_argument("--batch-steps", type=int, default=100000)
     ap.add_argument("--xcd-iters", type=int, default=20000)
     ap.add_argument("--hubk-iters", type=int, default=200000)
-    ap.add_argument("--only", choices=("n36", "hubbard", "rdm", "xcd", "optorb", "hubk"), default=None,
-                    help="diagnostic: run one extra block alone (for profiler runs) and print it")
-    ap.add_argument("--n36-k", type=int, default=0, help="with --only n36: a single k")
+    ap.add_argument("--only", choices=("headline", "n24", "target", "hubbard", "xcd", "optorb", "hubk", "random"),
+                    default=None, help="diagnostic: run one block alone (for profiler runs) and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU layout is a design "
@@ -358,53 +434,34 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8}), flush=True)
         return
-    if args.only == "n36":
-        print(json.dumps({"mcd_n36": mcd_n36(api, synth_inputs, args)}), flush=True)
+    single = {"hubbard": lambda: hubbard_batch(api, synth_inputs, args),
+              "hubk": lambda: hubbard_k_block(api, args),
+              "optorb": lambda: optorb_block(api, synth_inputs, args),
+              "xcd": lambda: xcdfci_block(api, synth_inputs, args),
+              "target": lambda: to_target(api, synth_inputs, args),
+              "random": lambda: api.cdfci_random_access_rates(1 << 30, 18_379_008)}
+    if args.only in single:
+        print(json.dumps({args.only: single[args.only]()}), flush=True)
         return
-    if args.only == "hubbard":
-        print(json.dumps({"hubbard_batch": hubbard_batch(api, synth_inputs, args)}), flush=True)
+    if args.only == "n24":
+        blk, ctx = plain_n24(api, synth_inputs, args)
+        ctx.close()
+        print(json.dumps({"plain_n24": blk}), flush=True)
         return
-    if args.only == "hubk":
-        print(json.dumps({"hubbard_k": hubbard_k_block(api, args)}), flush=True)
-        return
-    if args.only == "optorb":
-        print(json.dumps({"optorb": optorb_block(api, synth_inputs, args)}), flush=True)
-        return
-    if args.only == "xcd":
-        blk = xcdfci_block(api, synth_inputs, args)
-        if not args.no_cpu:
-            blk["cpu_baseline"] = cpu_baseline_xcdfci(synth_inputs, args.tau)
-        print(json.dumps({"xcdfci": blk}), flush=True)
-        return
-    N, na, nb, naux = 24, 6, 6, 72
-    seed = synth_inputs.CONFIG_SEEDS["abinitio_n24"]
-    h, eri = synth_inputs.ab_initio(N, naux, seed)
-    n_col = 16471
-    ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << args.table_log2, z_threshold=args.tau,
-                         grid_blocks=args.grid)
-    torch.cuda.synchronize()
-    tw = time.perf_counter()
-    for _ in range(args.warmup):
-        api.cdfci_step(ctx, 1, args.iters)
-    torch.cuda.synchronize()
-    warm_wall = time.perf_counter() - tw
-    kernel_s = 0.0
-    iters = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = api.cdfci_step(ctx, 1, args.iters)
-        kernel_s += st["seconds"]
-        iters += st["steps"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    log(f"plain: {iters} iterations in {wall:.2f} s, E = {st['energy']:.10f}")
-    elements = iters * n_col
-    value = elements / wall
-    achieved = BYTES_PER_ELEMENT * elements / kernel_s / 1e9
-    per_el = measured_traffic_per_element()
+
+    H = headline(api, synth_inputs, args)
+    torch.cuda.empty_cache()  # the table workspace goes back to the device for the later blocks
+    k, wall = H["k"], H["wall"]
+    log(f"headline: k={k}, {H['steps']} iterations in {wall:.3f} s, E = {H['energy']:.10f}")
+    per_launch = k * N36_COLUMN
+    ph = H["phases"]
+    n_timed = max(1, ph["steps"])
+    scatter_avg = ph["scatter"] / n_timed
+    achieved = BYTES_PER_ELEMENT * per_launch / scatter_avg / 1e9
+    per_el = measured_traffic_per_element(SCATTER_COUNTERS, scatter_sources_sha256(), k)
     out = {
         "metric": "H elements/s + CD iters/s to 1e-5 Ha, batched vs plain, 1 MI355X",
-        "value": value,
+        "value": H["elements"] / wall,
         "unit": "H elements/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -415,37 +472,59 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "ab initio N=24 6a+6b naux=72 seed=2024, 2^28-slot table, "
-                               "single-coordinate CDFCI, 1e6 iterations",
-                   "iters_per_step": args.iters, "tau": args.tau,
-                   "column_entries": n_col},
-        "cd_iters_per_s": iters / wall,
-        "energy": st["energy"],
-        "occupied": st["occupied"],
-        "total_iterations": st["total_steps"],
+        "config": {"workload": f"ab initio N=36 8a+8b naux=108 seed=3636, 2^30-slot table, tau={args.tau}, "
+                               f"batched multicoordinate CDFCI (Alg. 2) with k={k}"
+                               f"{' (autotuned)' if not args.k else ''}, {args.steps} x {args.iters} iterations "
+                               f"timed after {args.warmup} x {args.iters} warm-up"
+                               f"{' and the tuning trials' if not args.k else ''}",
+                   "k": k, "iters_per_step": args.iters, "tau": args.tau, "column_entries": N36_COLUMN},
+        "cd_iters_per_s": H["steps"] / wall,
+        "coordinate_updates_per_s": H["steps"] * k / wall,
+        "energy": H["energy"], "energy_exact": H["energy_exact"], "occupied": H["occupied"],
+        "total_iterations_timed": H["steps"],
+        "tune": {"k": k, "rates_Ha_per_s": H["tune_rates_Ha_per_s"], "seconds": H["tune_seconds"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (per_el * args.iters * n_col) if per_el is not None else None,
-                     "kernel": "k_cd1", "avg_launch_ms": 1e3 * kernel_s / args.steps,
-                     "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * args.iters * n_col},
+                     "traffic": (per_el * per_launch) if per_el is not None else None,
+                     "kernel": "k_mc_scatter", "avg_launch_ms": 1e3 * scatter_avg,
+                     "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * per_launch,
+                     "whole_step_GBs": BYTES_PER_ELEMENT * H["elements"] / wall / 1e9},
+        "phases_ms_per_step": {q: 1e3 * ph[q] / n_timed for q in ("select", "hii", "eigen", "scatter", "finish")},
+        "hash": {"probes": H["probes"], "fp64_atomics": H["atomics"], "inserts": H["inserts"],
+                 "probes_per_entry": H["probes"] / max(1, H["elements"]),
+                 "probes_per_s_in_scatter": H["probes"] / max(1e-12, ph["scatter"]),
+                 "atomics_per_s_in_scatter": H["atomics"] / max(1e-12, ph["scatter"])},
     }
-    if args.only == "rdm":
-        print(json.dumps({"rdm": rdm_block(api, ctx, n_col)}), flush=True)
-        ctx.close()
-        return
     if not args.no_extra:
         try:
-            out["rdm"] = rdm_block(api, ctx, n_col)
-            log(f"rdm: {out['rdm']}")
-        except Exception as e:  # reported, not fatal
-            out["rdm"] = {"error": str(e)}
-    ctx.close()
-    if not args.no_extra:
-        for name, fn in (("batched_vs_plain",
-                          lambda: batched_vs_plain(api, h, eri, na, nb, args, st["energy"], warm_wall + wall,
-                                                   n_col)),
-                         ("mcd_n36", lambda: mcd_n36(api, synth_inputs, args)),
-                         ("xcdfci", lambda: xcdfci_block(api, synth_inputs, args)),
+            ra = api.cdfci_random_access_rates(1 << 30, 18_379_008)
+            out["random_access"] = ra
+            out["hash"]["probes_vs_gather_ceiling"] = out["hash"]["probes_per_s_in_scatter"] / ra["gather16_per_s"]
+            out["hash"]["atomics_vs_atomic_ceiling"] = (out["hash"]["atomics_per_s_in_scatter"] /
+                                                        ra["gather_atomic_f64_per_s"])
+            log(f"random_access: {ra}")
+        except Exception as e:
+            out["random_access"] = {"error": str(e)}
+        for name, fn in (("to_target", lambda: to_target(api, synth_inputs, args)),):
+            try:
+                out[name] = fn()
+                log(f"{name}: done")
+            except Exception as e:
+                out[name] = {"error": str(e)}
+                log(f"{name}: error {e}")
+        try:
+            blk, ctx = plain_n24(api, synth_inputs, args)
+            out["plain_n24"] = blk
+            log(f"plain_n24: {blk['elements_per_s']:.3e} entries/s")
+            try:
+                out["rdm"] = rdm_block(api, ctx, N24_COLUMN)
+            except Exception as e:
+                out["rdm"] = {"error": str(e)}
+            ctx.close()
+            torch.cuda.empty_cache()
+        except Exception as e:
+            out["plain_n24"] = {"error": str(e)}
+        for name, fn in (("xcdfci", lambda: xcdfci_block(api, synth_inputs, args)),
                          ("optorb", lambda: optorb_block(api, synth_inputs, args)),
                          ("hubbard_k", lambda: hubbard_k_block(api, args)),
                          ("hubbard_batch", lambda: hubbard_batch(api, synth_inputs, args))):
@@ -455,10 +534,18 @@ def main():
             except Exception as e:
                 out[name] = {"error": str(e)}
                 log(f"{name}: error {e}")
+            torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(h, eri, na, nb)
+        cb = cpu_baselines(synth_inputs, args)
+        out["cpu_baseline"] = cb["openmp"]
+        out["cpu_baseline_serial"] = cb["serial"]
+        if "batched_oracle" in cb:
+            out["cpu_baseline_batched_oracle"] = cb["batched_oracle"]
         if isinstance(out.get("xcdfci"), dict) and "error" not in out["xcdfci"]:
             out["xcdfci"]["cpu_baseline"] = cpu_baseline_xcdfci(synth_inputs, args.tau)
+    live = api.live_objects() if hasattr(api, "live_objects") else None
+    if live:
+        out["live_objects_at_exit"] = live
     print(json.dumps(out), flush=True)
 
 

@@ -229,6 +229,15 @@ int cdfci_mc_selection(cdfci_ctx* ctx, uint64_t* keys, double* eta, int64_t cap,
  * of the solver are compared with. */
 int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates);
 
+/* Measurement aid: with timing on (cdfci_set_timing; switching it resets the
+ * sums), every multicoordinate step records HIP events on the context's
+ * stream between its phases, and cdfci_mc_phase_times returns the summed
+ * device seconds of [0] selection (begin, radix passes, gather), [1] H_II,
+ * [2] the reduced eigenproblem, [3] the column scatter, [4] finish and
+ * rescale (5 doubles), and in *steps (may be NULL) the steps timed. */
+int cdfci_set_timing(cdfci_ctx* ctx, int on);
+int cdfci_mc_phase_times(cdfci_ctx* ctx, double* seconds, int64_t* steps);
+
 /* Restart (Sec. 4.1.3: checkpoints for termination and restart from stored
  * wavefunctions).  Replaces the context's state by the wavefunction
  * c = sum_i cv[i] e_{key i}: keys 2*count uint64 (alpha, beta) and cv count

@@ -2,6 +2,7 @@
 step of the solver runs in the HIP library; PyTorch supplies device memory (the
 hash-table workspace) and the stream."""
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -16,6 +17,15 @@ class CDFCIError(RuntimeError):
         last = L.cdfci_last_error().decode()
         super().__init__(f"{where}: {msg} ({code})" + (f" [{last}]" if last else ""))
         self.code = code
+
+
+# every library object this module has opened and not yet closed
+_live = weakref.WeakSet()
+
+
+def live_objects():
+    """Number of contexts and batches opened through this module and still open."""
+    return sum(1 for o in list(_live) if getattr(o, "handle", None) and not isinstance(o, _BorrowedContext))
 
 
 def _check(rc, where):
@@ -80,6 +90,7 @@ class Context:
         self.workspace = workspace
         self.N, self.na, self.nb = N, na, nb
         self.integrals = None
+        _live.add(self)
 
     def __del__(self):
         try:
@@ -306,6 +317,18 @@ def cdfci_random_access_rates(table_slots=1 << 28, n_ops=18_379_008):
             "n_ops": int(n_ops)}
 
 
+def cdfci_set_timing(ctx, on=True):
+    _check(_lib.load().cdfci_set_timing(ctx.handle, int(bool(on))), "cdfci_set_timing")
+
+
+def cdfci_mc_phase_times(ctx):
+    """Summed device seconds per phase of the timed multicoordinate steps."""
+    t = np.zeros(5)
+    n = ctypes.c_int64(0)
+    _check(_lib.load().cdfci_mc_phase_times(ctx.handle, _dp(t), ctypes.byref(n)), "cdfci_mc_phase_times")
+    return {"select": t[0], "hii": t[1], "eigen": t[2], "scatter": t[3], "finish": t[4], "steps": n.value}
+
+
 def cdfci_load(ctx, keys_alpha, keys_beta, c):
     """Restart from a stored wavefunction (keys and c as cdfci_export returns)."""
     ka = np.asarray(keys_alpha, dtype=np.uint64)
@@ -359,6 +382,7 @@ class Batch:
         self.handle = handle
         self.specs = specs
         self.count = len(specs)
+        _live.add(self)
 
     def __del__(self):
         try:
@@ -488,6 +512,7 @@ class XContext:
         self.N, self.na, self.nb = N, na, nb
         self.n_states = n_states
         self.shift = shift
+        _live.add(self)
 
     def __del__(self):
         try:

@@ -1149,7 +1149,13 @@ struct cdfci_ctx {
   uint64_t* sel_a = nullptr;
   uint64_t* sel_b = nullptr;
   double* eta = nullptr;
-  double* recalc = nullptr;
+  PageStat* pstat = nullptr;  // per scatter workgroup: recalculation part and counts
+  uint64_t pstat_cap = 0;
+  // per-phase device time of multicoordinate steps (cdfci_set_timing)
+  int timing = 0;
+  std::vector<hipEvent_t> tev;
+  double t_phase_mc[5] = {0, 0, 0, 0, 0};  // select, H_II, reduced problem, scatter, finish
+  int64_t n_timed = 0;
   double* hii = nullptr;
   double* lan = nullptr;
   unsigned* bitmap = nullptr;
@@ -1166,7 +1172,9 @@ struct cdfci_batch {
   std::vector<int64_t> base_steps;          // iterations before the last restart
   std::vector<std::vector<uint64_t>> ck_keys;  // checkpoint of an evicted running instance
   std::vector<std::vector<double>> ck_c;
-  uint64_t budget = 0, resident = 0, peak = 0;
+  uint64_t budget = 0, resident = 0, peak = 0;  // resident: table memory held (in use or pooled)
+  std::vector<std::pair<uint64_t, void*>> pool;  // released tables kept for the next admission
+  std::vector<void*> table_of;                   // table buffer of each resident instance
   int restarts = 0;
   HubInst* d_inst = nullptr;
   unsigned* d_active = nullptr;
@@ -1678,7 +1686,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
   if (k > c->mc_kcap || need_cand > c->cand_cap) {
     // release and reallocate at the larger size
     void* olds[] = {c->cand, c->cnt, c->gkey, c->hii, c->lan, c->sel_slot, c->sel_a, c->sel_b, c->eta,
-                    c->recalc};
+                    c->pstat};
     for (void* p : olds)
       if (p) (void)hipFree(p);
     const int kc = std::max(k, c->mc_kcap);
@@ -1692,8 +1700,8 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     HIP_TRY(hipMalloc(&c->sel_a, (size_t)kc * sizeof(uint64_t)));
     HIP_TRY(hipMalloc(&c->sel_b, (size_t)kc * sizeof(uint64_t)));
     HIP_TRY(hipMalloc(&c->eta, (size_t)kc * sizeof(double)));
-    HIP_TRY(hipMalloc(&c->recalc, (size_t)kc * sizeof(double)));
-    HIP_TRY(hipMemsetAsync(c->recalc, 0, (size_t)kc * sizeof(double), c->stream));
+    c->pstat_cap = (uint64_t)kc * chunks;
+    HIP_TRY(hipMalloc(&c->pstat, (c->pstat_cap + kc) * sizeof(PageStat)));  // pages, then column sums
     c->mc_kcap = kc;
     c->cand_cap = cc;
     *lost = true;
@@ -1763,18 +1771,30 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   EigArgs ea{c->bitmap, nwords, c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, k,
              c->opts.dx_damping, c->opts.dx_threshold, dE};
   ScatterArgs sa{H,        c->T,      c->mask,   c->sel_a, c->sel_b, c->eta,  c->mst,
-                 c->ctl,   c->recalc, c->bitmap, c->cand,  c->cnt,   c->n_col, c->opts.z_threshold,
+                 c->ctl,   c->pstat,  c->bitmap, c->cand,  c->cnt,   c->n_col, c->opts.z_threshold,
                  k};
   const unsigned page0 = (unsigned)(k * chunks);
   k_reset_barrier<<<1, 1, 0, s>>>(c->ctl);
+  if (c->timing)
+    while ((int64_t)c->tev.size() < 6 * nsteps) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      c->tev.push_back(e);
+    }
+  auto mark = [&](int64_t step, int q) {
+    return c->timing ? hipEventRecord(c->tev[(size_t)(6 * step + q)], s) : hipSuccess;
+  };
   HIP_TRY(hipEventRecord(c->ev0, s));
   for (int64_t step = 0; step < nsteps; ++step) {
+    HIP_TRY(mark(step, 0));
     k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
     for (int pass = 0; pass < kRadixPasses; ++pass)
       k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist, pass, 0, k);
     k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties,
                                                 c->sel_a, c->sel_b, k);
+    HIP_TRY(mark(step, 1));
     k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k);
+    HIP_TRY(mark(step, 2));
     // workgroup 0 solves the reduced problem; the others clear the bitmap
     if (k <= kEigSmall)
       k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
@@ -1782,10 +1802,14 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
       k_mc_lobpcg<256><<<kEigGrid, 1024, 0, s>>>(ea);
     else
       k_mc_lobpcg<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
+    HIP_TRY(mark(step, 3));
     k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
-    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->recalc, c->bitmap, c->cand, c->cnt, c->mst,
+    HIP_TRY(mark(step, 4));
+    k_mc_colsum<<<k, 64, 0, s>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k);
+    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->bitmap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);
     k_mc_rescale<<<256, 256, 0, s>>>(c->T, c->nslots, c->mst, 0);
+    HIP_TRY(mark(step, 5));
     if (((step + 1) & 63) == 0) HIP_TRY(hipGetLastError());
   }
   k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);  // inside the loop k_mc_begin does this
@@ -1797,6 +1821,15 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const int64_t done = h.steps - before.steps;
+  if (c->timing)
+    for (int64_t step = 0; step < nsteps; ++step) {
+      for (int q = 0; q < 5; ++q) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, c->tev[(size_t)(6 * step + q)], c->tev[(size_t)(6 * step + q + 1)]));
+        c->t_phase_mc[q] += 1e-3 * t;
+      }
+      ++c->n_timed;
+    }
   if (trE) {
     if (done > 0) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < done; ++i) trE[i] += c->shift;
@@ -2342,11 +2375,12 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
   void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
-                c->eta, c->recalc, c->hii, c->lan, c->bitmap};
+                c->eta, c->pstat, c->hii, c->lan, c->bitmap};
   for (void* p : mc)
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   delete c;
   return 0;
 }
@@ -2396,12 +2430,43 @@ static int export_support(cdfci_ctx* c, std::vector<uint64_t>& keys, std::vector
 
 static uint64_t batch_bytes(const cdfci_batch* B, int i) { return B->slots[i] * sizeof(Slot); }
 
+// release instance i; its table goes to the pool (still counted as held)
 static int batch_release(cdfci_batch* B, int i) {
   if (!B->ctx[i]) return 0;
   cdfci_free(B->ctx[i]);
   B->ctx[i] = nullptr;
-  B->resident -= batch_bytes(B, i);
+  B->pool.push_back({batch_bytes(B, i), B->table_of[i]});
+  B->table_of[i] = nullptr;
   return 0;
+}
+
+// a table buffer of `bytes` from the pool, or a new one; pooled buffers of
+// other sizes are freed first when the budget would be exceeded
+static int batch_table(cdfci_batch* B, uint64_t bytes, void** out) {
+  for (size_t q = 0; q < B->pool.size(); ++q)
+    if (B->pool[q].first == bytes) {
+      *out = B->pool[q].second;
+      B->pool.erase(B->pool.begin() + (long)q);
+      return 0;
+    }
+  while (B->resident + bytes > B->budget && !B->pool.empty()) {
+    (void)hipFree(B->pool.back().second);
+    B->resident -= B->pool.back().first;
+    B->pool.pop_back();
+  }
+  void* p = nullptr;
+  HIP_TRY(hipMalloc(&p, bytes));
+  B->resident += bytes;
+  *out = p;
+  return 0;
+}
+
+// memory the budget still allows for a new table: pooled buffers count as free
+static uint64_t batch_free_bytes(const cdfci_batch* B) {
+  uint64_t pooled = 0;
+  for (const auto& pb : B->pool) pooled += pb.first;
+  const uint64_t used = B->resident - pooled;
+  return used >= B->budget ? 0 : B->budget - used;
 }
 
 int cdfci_free_batch(cdfci_batch* B) {
@@ -2415,6 +2480,9 @@ int cdfci_free_batch(cdfci_batch* B) {
     if (p) (void)hipFree(p);
   if (B->ev0) (void)hipEventDestroy(B->ev0);
   if (B->ev1) (void)hipEventDestroy(B->ev1);
+  for (auto& pb : B->pool) (void)hipFree(pb.second);
+  for (void* t : B->table_of)
+    if (t) (void)hipFree(t);
   if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
   delete B;
   return 0;
@@ -2476,14 +2544,20 @@ static int batch_admit(cdfci_batch* B, int i) {
   co.dx_damping = o.dx_damping;
   co.dx_threshold = o.dx_threshold;
   co.stream = B->stream;
+  void* table = nullptr;
+  int rc = batch_table(B, batch_bytes(B, i), &table);
+  if (rc) return rc;
+  co.workspace = table;
+  co.workspace_bytes = batch_bytes(B, i);
   cdfci_ctx* c = nullptr;
-  int rc = cdfci_init_hubbard(sp.dims, sp.ndim, sp.t, sp.U, sp.n_alpha, sp.n_beta, &co, &c);
+  rc = cdfci_init_hubbard(sp.dims, sp.ndim, sp.t, sp.U, sp.n_alpha, sp.n_beta, &co, &c);
   if (rc == 0 && !B->ck_keys[i].empty()) {
     rc = cdfci_load(c, B->ck_keys[i].data(), B->ck_c[i].data(), (int64_t)B->ck_c[i].size());
     if (rc == 0) ++B->restarts;
   }
   if (rc) {
     if (c) cdfci_free(c);
+    B->pool.push_back({batch_bytes(B, i), table});
     if (rc == CDFCI_ERR_HIP || rc == CDFCI_ERR_INVALID_ARG) return rc;
     B->res[i].error = rc == CDFCI_ERR_TABLE_FULL ? kErrTableFull : kErrNumeric;
     B->init_error[i] = rc;
@@ -2494,7 +2568,7 @@ static int batch_admit(cdfci_batch* B, int i) {
   B->ck_c[i].clear();
   B->ck_c[i].shrink_to_fit();
   B->ctx[i] = c;
-  B->resident += batch_bytes(B, i);
+  B->table_of[i] = table;
   B->peak = std::max(B->peak, B->resident);
   HubInst& hi = B->h_inst[i];
   hi.T = c->T;
@@ -2629,7 +2703,7 @@ static int batch_schedule(cdfci_batch* B, const std::vector<char>& want, int64_t
     for (int i = 0; i < B->count; ++i) {
       if (!pending[i] || B->ctx[i] || B->res[i].error) continue;
       const uint64_t need = batch_bytes(B, i);
-      bool fits = B->resident + need <= B->budget;
+      bool fits = need <= batch_free_bytes(B);
       while (!fits) {
         std::vector<char> keep(pending);
         for (int j = 0; j < B->count; ++j) keep[j] |= wave[j];
@@ -2637,7 +2711,7 @@ static int batch_schedule(cdfci_batch* B, const std::vector<char>& want, int64_t
         const int rc = batch_evict_one(B, keep, &done);
         if (rc) return rc;
         if (!done) break;
-        fits = B->resident + need <= B->budget;
+        fits = need <= batch_free_bytes(B);
       }
       if (!fits) break;  // the rest waits for the next wave
       const int rc = batch_admit(B, i);
@@ -2705,6 +2779,7 @@ int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const c
   B->waves = o.waves;
   B->specs.assign(specs, specs + count);
   B->ctx.assign(count, nullptr);
+  B->table_of.assign(count, nullptr);
   B->slots.assign(count, 0);
   B->res.assign(count, HubResult{0.0, 0, 0, 0, 0, 0});
   B->init_error.assign(count, 0);
@@ -2759,7 +2834,7 @@ int cdfci_init_hubbard_batch(const cdfci_hubbard_spec* specs, int count, const c
   // admit what fits now (the instances' starts), so small batches are resident at once
   std::vector<char> none((size_t)count, 0);
   for (int i = 0; i < count; ++i) {
-    if (B->resident + batch_bytes(B, i) > B->budget) break;
+    if (batch_bytes(B, i) > batch_free_bytes(B)) break;
     const int rc = batch_admit(B, i);
     if (rc) return fail(rc);
   }
@@ -2838,7 +2913,7 @@ int cdfci_batch_trace(cdfci_batch* B, int inst, int64_t nsteps, double* energy, 
     if (B->res[inst].error || B->res[inst].stopped) return CDFCI_ERR_INVALID_ARG;
     std::vector<char> keep((size_t)B->count, 0);
     keep[inst] = 1;
-    while (B->resident + batch_bytes(B, inst) > B->budget) {
+    while (batch_bytes(B, inst) > batch_free_bytes(B)) {
       bool done = false;
       rc = batch_evict_one(B, keep, &done);
       if (rc) return rc;
@@ -3054,6 +3129,21 @@ const char* cdfci_strerror(int code) {
 }
 
 const char* cdfci_last_error(void) { return g_last_error.c_str(); }
+
+int cdfci_set_timing(cdfci_ctx* c, int on) {
+  if (!c) return CDFCI_ERR_INVALID_ARG;
+  c->timing = on ? 1 : 0;
+  for (double& t : c->t_phase_mc) t = 0.0;
+  c->n_timed = 0;
+  return 0;
+}
+
+int cdfci_mc_phase_times(cdfci_ctx* c, double* seconds, int64_t* steps) {
+  if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
+  for (int q = 0; q < 5; ++q) seconds[q] = c->t_phase_mc[q];
+  if (steps) *steps = c->n_timed;
+  return 0;
+}
 
 int cdfci_phase_times(cdfci_ctx* c, double* seconds) {
   if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;

@@ -898,9 +898,12 @@ __device__ inline double sym3_lowest(const double* g_in, const int* use, double*
       a[i][j] = (use[i] && use[j]) ? g_in[i * 3 + j] : 0.0;
       v[i][j] = i == j ? 1.0 : 0.0;
     }
+  const double scale = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]) + 1e-300;
   for (int sweep = 0; sweep < 12; ++sweep) {
-    double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
-    if (off == 0.0) break;
+    // quadratic convergence: off-diagonals below 1e-20 of the diagonal change
+    // the eigenvalues by (1e-20)^2 relative
+    const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off <= 1e-20 * scale) break;
     for (int p = 0; p < 2; ++p)
       for (int q = p + 1; q < 3; ++q) {
         if (a[p][q] == 0.0) continue;
@@ -938,11 +941,13 @@ __device__ inline double sym3_lowest(const double* g_in, const int* use, double*
 // D = diag(A) - theta and p the previous step; p and then w are
 // orthonormalised against the others (Gram-Schmidt twice, the products with
 // A transformed alike) before the 3 x 3 eigenproblem, so the Ritz pair stays
-// accurate to rounding.  Stops at |A x - theta x| <= 1e-11 |theta| (the
-// eigenvalue error is quadratic in the residual) or after kLobpcgMax
-// iterations.  One matrix-vector product per iteration; everything else is
-// a handful of workgroup sums.
+// accurate to rounding.  Stops at |A x - theta x| <= 1e-9 |theta| or after
+// kLobpcgMax iterations: the eigenvalue error is quadratic in the residual
+// (about 1e-18 theta^2 / gap), and any eta is a valid step, since the
+// updates of mu and alpha are exact for the eta taken.  One matrix-vector
+// product per iteration; everything else is a handful of workgroup sums.
 constexpr int kLobpcgMax = 300;
+constexpr double kLobpcgTol = 1e-9;
 
 template <int KM>
 __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
@@ -1022,58 +1027,63 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
   bool have_p = false;
   int iters = 0;
   for (int it = 0; it < kLobpcgMax; ++it) {
-    // residual and its preconditioned form
-    double v[1] = {0.0};
+    // residual, its preconditioned form, and x . p (first Gram-Schmidt pass of p)
+    double v[2] = {0.0, 0.0};
     const double dfloor = 1e-8 * (fabs(theta) + 1.0);
     for (int r = tid; r < n; r += blockDim.x) {
       const double res = s_ax[r] - theta * s_x[r];
       v[0] += res * res;
+      v[1] += s_x[r] * s_p[r];
       double dn = s_d[r] - theta;
       if (fabs(dn) < dfloor) dn = dn < 0.0 ? -dfloor : dfloor;
       s_w[r] = res / dn;
     }
-    wg_sums<1>(v, s_red);
+    wg_sums<2>(v, s_red);
     iters = it;
-    if (sqrt(v[0]) <= 1e-11 * fabs(theta)) break;
-    // orthonormalise p against x (twice, A p along), then w against x and p
+    if (sqrt(v[0]) <= kLobpcgTol * fabs(theta)) break;
+    // p orthonormalised against x (two passes; the second pass's coefficient
+    // and the norm come from one sum, |p''|^2 = |p'|^2 - q'^2 as |x| = 1), A p along
     if (have_p) {
-      for (int pass = 0; pass < 2; ++pass) {
-        double q[1] = {0.0};
-        for (int r = tid; r < n; r += blockDim.x) q[0] += s_x[r] * s_p[r];
-        wg_sums<1>(q, s_red);
-        for (int r = tid; r < n; r += blockDim.x) {
-          s_p[r] -= q[0] * s_x[r];
-          s_ap[r] -= q[0] * s_ax[r];
-        }
-        __syncthreads();
-      }
-      double pq[1] = {0.0};
-      for (int r = tid; r < n; r += blockDim.x) pq[0] += s_p[r] * s_p[r];
-      wg_sums<1>(pq, s_red);
-      have_p = pq[0] > 1e-28;
-      const double ip = have_p ? 1.0 / sqrt(pq[0]) : 0.0;
+      double q2[2] = {0.0, 0.0};
       for (int r = tid; r < n; r += blockDim.x) {
-        s_p[r] *= ip;
-        s_ap[r] *= ip;
+        const double pr = s_p[r] - v[1] * s_x[r];
+        s_p[r] = pr;
+        s_ap[r] -= v[1] * s_ax[r];
+        q2[0] += s_x[r] * pr;
+        q2[1] += pr * pr;
+      }
+      wg_sums<2>(q2, s_red);
+      const double pp = q2[1] - q2[0] * q2[0];
+      have_p = pp > 1e-28;
+      const double ip = have_p ? 1.0 / sqrt(pp) : 0.0;
+      for (int r = tid; r < n; r += blockDim.x) {
+        s_p[r] = (s_p[r] - q2[0] * s_x[r]) * ip;
+        s_ap[r] = (s_ap[r] - q2[0] * s_ax[r]) * ip;
       }
       __syncthreads();
     }
-    for (int pass = 0; pass < 2; ++pass) {
-      double q[2] = {0.0, 0.0};
-      for (int r = tid; r < n; r += blockDim.x) {
-        q[0] += s_x[r] * s_w[r];
-        q[1] += s_p[r] * s_w[r];
-      }
-      wg_sums<2>(q, s_red);
-      for (int r = tid; r < n; r += blockDim.x) s_w[r] -= q[0] * s_x[r] + (have_p ? q[1] * s_p[r] : 0.0);
-      __syncthreads();
+    // w orthonormalised against x and p (two passes, the norm with the second)
+    double q[2] = {0.0, 0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      q[0] += s_x[r] * s_w[r];
+      q[1] += s_p[r] * s_w[r];
     }
-    double nw[1] = {0.0};
-    for (int r = tid; r < n; r += blockDim.x) nw[0] += s_w[r] * s_w[r];
-    wg_sums<1>(nw, s_red);
-    const bool use_w = nw[0] > 1e-28;
-    const double inw = use_w ? 1.0 / sqrt(nw[0]) : 0.0;
-    for (int r = tid; r < n; r += blockDim.x) s_w[r] *= inw;
+    wg_sums<2>(q, s_red);
+    double q3[3] = {0.0, 0.0, 0.0};
+    for (int r = tid; r < n; r += blockDim.x) {
+      const double wr = s_w[r] - q[0] * s_x[r] - (have_p ? q[1] * s_p[r] : 0.0);
+      s_w[r] = wr;
+      q3[0] += s_x[r] * wr;
+      q3[1] += s_p[r] * wr;
+      q3[2] += wr * wr;
+    }
+    wg_sums<3>(q3, s_red);
+    if (!have_p) q3[1] = 0.0;
+    const double ww = q3[2] - q3[0] * q3[0] - q3[1] * q3[1];
+    const bool use_w = ww > 1e-28;
+    const double inw = use_w ? 1.0 / sqrt(ww) : 0.0;
+    for (int r = tid; r < n; r += blockDim.x)
+      s_w[r] = (s_w[r] - q3[0] * s_x[r] - (have_p ? q3[1] * s_p[r] : 0.0)) * inw;
     __syncthreads();
     // A w (A p is carried)
     mc_matvec(hii, m, off, a00, s_a0, s_w, s_aw, s_part);
@@ -1091,7 +1101,7 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
     wg_sums<6>(g, s_red);
     if (tid == 0) {
       const double G[9] = {g[0], g[1], g[2], g[1], g[3], g[4], g[2], g[4], g[5]};
-      for (int q = 0; q < 9; ++q) s_g[q] = G[q];
+      for (int t = 0; t < 9; ++t) s_g[t] = G[t];
       s_use[0] = 1;
       s_use[1] = use_w ? 1 : 0;
       s_use[2] = have_p ? 1 : 0;
@@ -1103,36 +1113,35 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
     }
     __syncthreads();
     const double y0 = s_y[0], y1 = s_y[1], y2 = s_y[2];
-    // p <- y1 w + y2 p, x <- y0 x + p (and the same for the products with A)
-    double pn[1] = {0.0};
+    // p <- y1 w + y2 p, x <- y0 x + p (and the same for the products with A);
+    // one sum gives |p|^2, |x|^2 and x . A x
+    double nx[3] = {0.0, 0.0, 0.0};
     for (int r = tid; r < n; r += blockDim.x) {
       const double np = y1 * s_w[r] + y2 * s_p[r];
       const double nap = y1 * s_aw[r] + y2 * s_ap[r];
-      s_x[r] = y0 * s_x[r] + np;
-      s_ax[r] = y0 * s_ax[r] + nap;
+      const double xr = y0 * s_x[r] + np;
+      const double axr = y0 * s_ax[r] + nap;
+      s_x[r] = xr;
+      s_ax[r] = axr;
       s_p[r] = np;
       s_ap[r] = nap;
-      pn[0] += np * np;
+      nx[0] += np * np;
+      nx[1] += xr * xr;
+      nx[2] += xr * axr;
     }
-    wg_sums<1>(pn, s_red);
-    have_p = pn[0] > 1e-28;
-    // p kept of unit length (the basis is re-orthonormalised each iteration)
-    const double ipn = have_p ? 1.0 / sqrt(pn[0]) : 0.0;
-    double xx[2] = {0.0, 0.0};
+    wg_sums<3>(nx, s_red);
+    have_p = nx[0] > 1e-28;
+    // p kept of unit length, x renormalised against rounding drift; theta
+    // its Rayleigh quotient
+    const double ipn = have_p ? 1.0 / sqrt(nx[0]) : 0.0;
+    const double ixn = 1.0 / sqrt(nx[1]);
     for (int r = tid; r < n; r += blockDim.x) {
       s_p[r] *= ipn;
       s_ap[r] *= ipn;
-      xx[0] += s_x[r] * s_x[r];
-      xx[1] += s_x[r] * s_ax[r];
-    }
-    wg_sums<2>(xx, s_red);
-    // x renormalised against rounding drift; theta its Rayleigh quotient
-    const double ixn = 1.0 / sqrt(xx[0]);
-    for (int r = tid; r < n; r += blockDim.x) {
       s_x[r] *= ixn;
       s_ax[r] *= ixn;
     }
-    theta = xx[1] / xx[0];
+    theta = nx[2] / nx[1];
     __syncthreads();
     iters = it + 1;
   }
@@ -1443,6 +1452,16 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
 // b_hat += H_{:,I} eta / s' with the compression rule; recalculation sums;
 // touched entries marked once in the bitmap and written to this workgroup's
 // candidate page.  grid = (column chunks, k); one column entry per thread.
+// What a scatter workgroup hands to the finish kernel, written once without
+// atomics (contended device atomics on a few counters cost more than the
+// scatter itself): its part of the recalculated b of its column and its
+// counts of probes, FP64 atomics and inserts.
+struct PageStat {
+  double recalc;
+  unsigned probes, atomics, inserts;
+  int err;
+};
+
 struct ScatterArgs {
   Ham H;
   Slot* T;
@@ -1452,7 +1471,7 @@ struct ScatterArgs {
   const double* eta;
   McState* st;
   Ctl* ctl;
-  double* recalc;
+  PageStat* pstat;  // one per scatter workgroup (page)
   unsigned* bitmap;
   unsigned* cand;
   unsigned* cnt;
@@ -1504,10 +1523,12 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
   if (A.st->skip) return;
   const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
   if (y >= m) {
-    if (threadIdx.x == 0) A.cnt[page] = 0;
+    if (threadIdx.x == 0) {
+      A.cnt[page] = 0;
+      A.pstat[page] = PageStat{0.0, 0u, 0u, 0u, 0};
+    }
     return;
   }
-  Ctl* ctl = A.ctl;
   const uint64_t a = A.sel_a[y], b = A.sel_b[y];
   const double eta = A.eta[y];
   const double coef = eta * A.st->inv_scale;
@@ -1573,7 +1594,7 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
       recalc += Hj * cj;
     }
   }
-  // workgroup sum of the recalculation part, one atomic per workgroup
+  // workgroup sum of the recalculation part and the counts, stored for the finish
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int offs = 32; offs > 0; offs >>= 1) recalc += __shfl_xor(recalc, offs);
   if (lane == 0) s_red[w] = recalc;
@@ -1584,31 +1605,79 @@ __global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
   if (threadIdx.x == 0) {
     double r = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += s_red[i];
-    atomic_add_f64(&A.recalc[y], r);
     A.cnt[page] = s_ncand;
-    if (s_probes) atomicAdd(&ctl->probes, (unsigned long long)s_probes);
-    if (s_atomics) atomicAdd(&ctl->atomics, (unsigned long long)s_atomics);
-    if (s_ins) atomicAdd(&ctl->occupied, (unsigned long long)s_ins);
-    if (s_ins) atomicAdd(&ctl->inserts, (unsigned long long)s_ins);
-    if (s_err) atomicOr(&ctl->error, s_err);
+    A.pstat[page] = PageStat{r, s_probes, s_atomics, s_ins, s_err};
   }
 }
 
-// b_hat_I <- recalculated values; I joins the candidates (own pages after the
-// scatter pages); occupancy check
-__global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_slot, double* recalc,
+// One wave per chosen column: its scatter pages summed in a fixed order into
+// colstat[i] (the recalculated b_i and the column's counts).
+__global__ void __launch_bounds__(64) k_mc_colsum(const PageStat* pstat, int chunks, PageStat* colstat,
+                                                  const McState* st, int k) {
+  if (st->skip) return;
+  const int m = (int)min(st->n_sel, (unsigned long long)k);
+  const int i = blockIdx.x;
+  if (i >= m) return;
+  const int lane = threadIdx.x;
+  double r = 0.0;
+  unsigned pr = 0, at = 0, in = 0;
+  int er = 0;
+  for (int x = lane; x < chunks; x += 64) {
+    const PageStat q = pstat[(size_t)i * chunks + x];
+    r += q.recalc;
+    pr += q.probes;
+    at += q.atomics;
+    in += q.inserts;
+    er |= q.err;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(r, off);
+    r = (lane & off) ? (o + r) : (r + o);
+    pr += __shfl_xor(pr, off);
+    at += __shfl_xor(at, off);
+    in += __shfl_xor(in, off);
+    er |= __shfl_xor(er, off);
+  }
+  if (lane == 0) colstat[i] = PageStat{r, pr, at, in, er};
+}
+
+// b_hat_I <- recalculated values (from the column sums); I joins the
+// candidates (own pages after the scatter pages); the scatter's counts;
+// occupancy check
+__global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_slot, const PageStat* colstat,
                                                     unsigned* bitmap, unsigned* cand, unsigned* cnt,
                                                     McState* st, Ctl* ctl, uint64_t max_entries,
                                                     unsigned page0, int k) {
   __shared__ unsigned s_n;
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_err;
   if (st->skip) return;
   const int m = (int)min(st->n_sel, (unsigned long long)k);
-  if (threadIdx.x == 0) s_n = 0;
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
+    s_err = 0;
+  }
   __syncthreads();
+  // the scatter's counts over the chosen columns
+  {
+    unsigned long long pr = 0, at = 0, in = 0;
+    int er = 0;
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+      const PageStat q = colstat[p];
+      pr += q.probes;
+      at += q.atomics;
+      in += q.inserts;
+      er |= q.err;
+    }
+    if (pr) atomicAdd(&s_cnt[0], pr);
+    if (at) atomicAdd(&s_cnt[1], at);
+    if (in) atomicAdd(&s_cnt[2], in);
+    if (er) atomicOr(&s_err, er);
+  }
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const int64_t slot = sel_slot[i];
-    T[slot].b = recalc[i];
-    recalc[i] = 0.0;
+    T[slot].b = colstat[i].recalc;
     const unsigned bit = 1u << (slot & 31);
     const unsigned old = atomicOr(&bitmap[slot >> 5], bit);
     if (!(old & bit)) {
@@ -1620,10 +1689,16 @@ __global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_
   const unsigned npg = (unsigned)((k + kPage - 1) / kPage);
   for (unsigned p = threadIdx.x; p < npg; p += blockDim.x)
     cnt[page0 + p] = s_n > p * kPage ? min((unsigned)kPage, s_n - p * kPage) : 0u;
+  __syncthreads();
   if (threadIdx.x == 0) {
     st->last_sel = (unsigned long long)m;
     st->n_sel = 0;
     st->n_pages = (unsigned long long)page0 + npg;
+    ctl->probes += s_cnt[0];
+    ctl->atomics += s_cnt[1];
+    ctl->inserts += s_cnt[2];
+    ctl->occupied += s_cnt[2];
+    ctl->error |= s_err;
     if (ctl->occupied > max_entries) ctl->error |= kErrTableFull;
   }
 }

@@ -222,13 +222,11 @@ def test_batch_small_lattices_reach_the_oracle(api):
     assert len(i2) >= 30 and len(i3) == 8
     specs = [all_specs[i] for i in i2 + i3]
     B = api.cdfci_init_hubbard_batch(specs, dx_threshold=1e-11)
-    E_first = None
+    E_first = api.cdfci_batch_results(B)[0].copy()  # the starts
     for _ in range(8):
         st = api.cdfci_step_batch(B, 500_000)
         print(f"batch: {st}", flush=True)
         E, steps, status = api.cdfci_batch_results(B)
-        if E_first is None:
-            E_first = E.copy()
         if all(status[k] == 1 for k in range(len(i2))):
             break
     assert st["failed"] == 0

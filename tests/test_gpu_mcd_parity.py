@@ -160,3 +160,40 @@ def test_mc_step_energy_is_lowest_eigenvalue_full_size(api, k):
     lam = np.linalg.eigvalsh(A)[0]
     assert abs(E1[0] - lam) <= 1e-9 * abs(lam), (E1[0], lam)
     ctx.close()
+
+
+def test_mc_keeps_the_spin_flip_parity_like_the_oracle(api):
+    """8 orbitals, 4+4, k = 64: as in the oracle's Alg. 2 the first step
+    leaves the even (ground-state) flip sector and the run approaches the
+    lowest odd eigenvalue; k = 128 reaches E0.  Sector eigenvalues from the
+    dense H split by parity (LAPACK)."""
+    from oracle import fci
+
+    N, n = 8, 4
+    h, eri = synth_inputs.ab_initio(N, 24, 1)
+    H, B = fci.dense_H(h, eri, N, n, n)
+    index = {q: i for i, q in enumerate(B)}
+    flip = np.array([index[(b, a)] for (a, b) in B])
+    odd_pairs = [(i, int(flip[i])) for i in range(len(B)) if i < flip[i]]
+    odd = np.zeros((len(B), len(odd_pairs)))
+    for t, (i, j) in enumerate(odd_pairs):
+        odd[i, t], odd[j, t] = 1.0 / np.sqrt(2.0), -1.0 / np.sqrt(2.0)
+    E0 = np.linalg.eigvalsh(H)[0]
+    e_odd = np.linalg.eigvalsh(odd.T @ H @ odd)[0]
+    assert e_odd > E0 + 1e-2
+    keys, c0 = ocd.init_single(h, eri, n, n)
+    orc = omc.mcdfci_run(h, eri, keys, c0, 64, max_steps=150)
+    ctx = api.cdfci_init(h, eri, n, n, table_slots=1 << 16)
+    E, _ = api.cdfci_step_energies(ctx, 64, 150)
+    assert np.all(E >= e_odd - 1e-9)
+    assert E[-1] - e_odd < 1e-5
+    assert abs(E[-1] - orc.energies[-1]) < 1e-8
+    ka, kb, c, _ = api.cdfci_export(ctx)
+    where = {(int(x), int(y)): v for x, y, v in zip(ka, kb, c)}
+    x = np.array([where.get(q, 0.0) for q in B])
+    assert np.linalg.norm(x + x[flip]) <= 1e-10 * np.linalg.norm(x)  # odd
+    ctx.close()
+    ctx = api.cdfci_init(h, eri, n, n, table_slots=1 << 16)
+    E, _ = api.cdfci_step_energies(ctx, 128, 150)
+    assert abs(E[-1] - E0) < 1e-8
+    ctx.close()

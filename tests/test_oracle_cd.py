@@ -201,6 +201,48 @@ def test_mcdfci_converges_to_dense(m):
     assert np.all(np.array(st.energies) >= E0 - 1e-12)  # variational
 
 
+def test_mcdfci_keeps_the_spin_flip_parity_of_a_closed_chosen_set():
+    """With n_alpha = n_beta, H commutes with the spin flip P (alpha string <->
+    beta string).  A step whose chosen set is closed under P maps a state of
+    one P-parity to that parity, and a first step whose reduced eigenvector has
+    no weight on the start (gamma = 0) leaves the start's parity altogether.
+    Here (8 orbitals, 4+4, m = 64) the first step lands in the odd sector while
+    the ground state is even; every later chosen set is closed under P, so the
+    run stays odd and approaches the lowest odd eigenvalue, not E0.  Checked
+    against the dense H split by parity (LAPACK on each sector)."""
+    N, n = 8, 4
+    h, eri = synth_inputs.ab_initio(N, 24, 1)
+    H, B = fci.dense_H(h, eri, N, n, n)
+    index = {k: i for i, k in enumerate(B)}
+    flip = np.array([index[(b, a)] for (a, b) in B])
+    assert np.max(np.abs(H[np.ix_(flip, flip)] - H)) < 1e-12
+    # orthonormal bases of the even and odd sectors
+    pairs = [(i, int(flip[i])) for i in range(len(B)) if i <= flip[i]]
+    even = np.zeros((len(B), len(pairs)))
+    odd_pairs = [(i, j) for i, j in pairs if i != j]
+    odd = np.zeros((len(B), len(odd_pairs)))
+    for t, (i, j) in enumerate(pairs):
+        even[[i, j], t] = 1.0 / np.sqrt(2.0) if i != j else 1.0
+    for t, (i, j) in enumerate(odd_pairs):
+        odd[i, t], odd[j, t] = 1.0 / np.sqrt(2.0), -1.0 / np.sqrt(2.0)
+    E0 = np.linalg.eigvalsh(H)[0]
+    e_even = np.linalg.eigvalsh(even.T @ H @ even)[0]
+    e_odd = np.linalg.eigvalsh(odd.T @ H @ odd)[0]
+    assert abs(e_even - E0) < 1e-10 and e_odd > E0 + 1e-2
+    keys, c0 = ocd.init_single(h, eri, n, n)
+    st = omc.mcdfci_run(h, eri, keys, c0, 64, max_steps=150)
+    assert st.gammas[0] < 1e-10
+    for I in st.selections:
+        assert {(b, a) for a, b in I} == set(I)
+    x = np.zeros(len(B))
+    for k, v in st.c.items():
+        x[index[k]] = v
+    x /= np.linalg.norm(x)
+    assert np.linalg.norm(even.T @ x) < 1e-11
+    assert np.all(np.array(st.energies) >= e_odd - 1e-10)
+    assert st.energy - e_odd < 1e-5
+
+
 @pytest.mark.parametrize("na,nb,tau", [(4, 3, 0.0), (4, 4, 1e-3)])
 def test_cd_multithreaded_equals_serial(na, nb, tau):
     """The OpenMP form of Algorithm 1 (the all-core CPU baseline) follows the

@@ -80,15 +80,12 @@ def measured_traffic_per_element(path, sha, k=None):
         text = open(path).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_element:\s*([0-9.]+)", text)
     s = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
-    if not m or not s or s.group(1) != sha:
+    if not s or s.group(1) != sha:
         return None
-    if k is not None:
-        kk = re.search(r"profiled_k:\s*([0-9]+)", text)
-        if not kk or int(kk.group(1)) != k:
-            return None
-    return float(m.group(1))
+    key = "traffic_bytes_per_element" + (f"_k{k}" if k is not None else "")
+    m = re.search(key + r":\s*([0-9.]+)", text)
+    return float(m.group(1)) if m else None
 
 
 def log(msg):
@@ -117,13 +114,16 @@ def cpu_baselines(synth_inputs, args, seconds_target=12.0):
     for name, threads in (("serial", 1), ("openmp", cores)):
         run = (lambda n: ocd.cd_run(h, eri, keys, c0, tau=args.tau, max_steps=n, trajectory=False)) if threads == 1 \
             else (lambda n: ocd.cd_run_mt(h, eri, keys, c0, threads, tau=args.tau, max_steps=n, trajectory=False))
-        t = time.perf_counter()
-        run(40)
-        dt = time.perf_counter() - t
-        iters = max(40, int(40 * seconds_target / max(dt, 1e-3)))
-        t = time.perf_counter()
-        r = run(iters)
-        dt = time.perf_counter() - t
+        # grow the sample until it takes about seconds_target (a run restarts
+        # from the same start, so the last one is the measured sample)
+        iters = 40
+        while True:
+            t = time.perf_counter()
+            r = run(iters)
+            dt = time.perf_counter() - t
+            if dt >= 0.7 * seconds_target or r.steps < iters:
+                break
+            iters = int(iters * min(50.0, seconds_target / max(dt, 1e-3)))
         out[name] = {"value": r.steps * N36_COLUMN / dt, "unit": "H elements/s", "cores": threads, "kind": "oracle",
                      "sample": f"first {r.steps} iterations of Alg. 1 (C++ oracle"
                                f"{', OpenMP' if threads > 1 else ''}) on the headline's 36-orbital Hamiltonian "
@@ -543,9 +543,7 @@ def main():
             out["cpu_baseline_batched_oracle"] = cb["batched_oracle"]
         if isinstance(out.get("xcdfci"), dict) and "error" not in out["xcdfci"]:
             out["xcdfci"]["cpu_baseline"] = cpu_baseline_xcdfci(synth_inputs, args.tau)
-    live = api.live_objects() if hasattr(api, "live_objects") else None
-    if live:
-        out["live_objects_at_exit"] = live
+    out["live_objects_at_exit"] = api.live_objects()
     print(json.dumps(out), flush=True)
 
 

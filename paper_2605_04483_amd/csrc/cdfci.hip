@@ -1142,7 +1142,9 @@ struct cdfci_ctx {
   McState* mst = nullptr;
   unsigned* cand = nullptr;  // candidate pages (kPage slot ids each)
   unsigned* cnt = nullptr;   // entries used per page
-  unsigned long long* gkey = nullptr;
+  unsigned long long* gkey = nullptr;  // dense selection keys (cand_cap + one grid of slack)
+  unsigned* dslot = nullptr;           // dense selection slots
+  unsigned* dcount = nullptr;          // dense region lengths (kSelBlocks)
   unsigned* hist = nullptr;
   unsigned* ties = nullptr;
   int64_t* sel_slot = nullptr;
@@ -1154,11 +1156,14 @@ struct cdfci_ctx {
   // per-phase device time of multicoordinate steps (cdfci_set_timing)
   int timing = 0;
   std::vector<hipEvent_t> tev;
-  double t_phase_mc[5] = {0, 0, 0, 0, 0};  // select, H_II, reduced problem, scatter, finish
+  double t_phase_mc[5] = {0, 0, 0, 0, 0};  // select, H_II, reduced problem + probe half, apply half, finish
   int64_t n_timed = 0;
   double* hii = nullptr;
   double* lan = nullptr;
-  unsigned* bitmap = nullptr;
+  double* chat = nullptr;       // c_hat of the chosen set after a step
+  ScatRec* rec = nullptr;       // probe-half records, one per column entry of each chosen column
+  unsigned* bitmap = nullptr;   // one bit per slot, clear between selections (bm_words words)
+  uint64_t bm_words = 0;
 };
 
 struct cdfci_batch {
@@ -1486,10 +1491,13 @@ int select_support(cdfci_ctx* c, int64_t top_n, CallBufs& bufs, int64_t** sel, i
   McState* st;
   unsigned *cand, *cnt, *hist, *ties;
   unsigned long long* gkey;
+  unsigned *dslot, *dcount;
   HIP_TRY(bufs.alloc(&st, 1));
   HIP_TRY(bufs.alloc(&cand, cap));
   HIP_TRY(bufs.alloc(&cnt, pages));
-  HIP_TRY(bufs.alloc(&gkey, cap));
+  HIP_TRY(bufs.alloc(&gkey, cap + (uint64_t)kSelBlocks * kPage));
+  HIP_TRY(bufs.alloc(&dslot, cap + (uint64_t)kSelBlocks * kPage));
+  HIP_TRY(bufs.alloc(&dcount, kSelBlocks));
   HIP_TRY(bufs.alloc(&hist, kRadixBins));
   HIP_TRY(bufs.alloc(&ties, kMaxTies));
   HIP_TRY(hipMemsetAsync(st, 0, sizeof(McState), s));
@@ -1508,8 +1516,9 @@ int select_support(cdfci_ctx* c, int64_t top_n, CallBufs& bufs, int64_t** sel, i
   HIP_TRY(bufs.alloc(&sa, n));
   HIP_TRY(bufs.alloc(&sb, n));
   for (int pass = 0; pass < kRadixPasses; ++pass)
-    k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, gkey, c->ctl, st, hist, pass, 1, (int)n);
-  k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, gkey, st, *sel, ties, sa, sb, (int)n);
+    k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, SelBufs{gkey, dslot, dcount}, c->ctl, st, hist, pass, 1,
+                                          (int)n, nullptr, 0);
+  k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, SelBufs{gkey, dslot, dcount}, st, *sel, ties, sa, sb, (int)n);
   HIP_TRY(hipGetLastError());
   unsigned long long got = 0;
   HIP_TRY(hipMemcpyAsync(&got, &st->n_sel, sizeof(got), hipMemcpyDeviceToHost, s));
@@ -1685,23 +1694,26 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
   const uint64_t need_cand = pages * kPage;
   if (k > c->mc_kcap || need_cand > c->cand_cap) {
     // release and reallocate at the larger size
-    void* olds[] = {c->cand, c->cnt, c->gkey, c->hii, c->lan, c->sel_slot, c->sel_a, c->sel_b, c->eta,
-                    c->pstat};
+    void* olds[] = {c->cand, c->cnt, c->gkey, c->dslot, c->hii, c->lan, c->sel_slot, c->sel_a, c->sel_b,
+                    c->eta, c->pstat, c->chat, c->rec};
     for (void* p : olds)
       if (p) (void)hipFree(p);
     const int kc = std::max(k, c->mc_kcap);
     const uint64_t cc = std::max(need_cand + need_cand / 4, c->cand_cap);
     HIP_TRY(hipMalloc(&c->cand, cc * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->cnt, (cc / kPage) * sizeof(unsigned)));
-    HIP_TRY(hipMalloc(&c->gkey, cc * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&c->gkey, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&c->dslot, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->hii, (size_t)kc * kc * sizeof(double)));
     HIP_TRY(hipMalloc(&c->lan, (size_t)(kLanczosMax + 1) * (kc + 1) * sizeof(double)));
     HIP_TRY(hipMalloc(&c->sel_slot, (size_t)kc * sizeof(int64_t)));
     HIP_TRY(hipMalloc(&c->sel_a, (size_t)kc * sizeof(uint64_t)));
     HIP_TRY(hipMalloc(&c->sel_b, (size_t)kc * sizeof(uint64_t)));
     HIP_TRY(hipMalloc(&c->eta, (size_t)kc * sizeof(double)));
-    c->pstat_cap = (uint64_t)kc * chunks;
-    HIP_TRY(hipMalloc(&c->pstat, (c->pstat_cap + kc) * sizeof(PageStat)));  // pages, then column sums
+    HIP_TRY(hipMalloc(&c->chat, (size_t)kc * sizeof(double)));
+    HIP_TRY(hipMalloc(&c->rec, (size_t)kc * chunks * kPage * sizeof(ScatRec)));
+    c->pstat_cap = (uint64_t)kc * chunks * 4;
+    HIP_TRY(hipMalloc(&c->pstat, (c->pstat_cap + kc) * sizeof(PageStat)));  // page quarters, then column sums
     c->mc_kcap = kc;
     c->cand_cap = cc;
     *lost = true;
@@ -1716,7 +1728,9 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     HIP_TRY(hipMalloc(&c->hist, kRadixBins * sizeof(unsigned)));
     HIP_TRY(hipMemsetAsync(c->hist, 0, kRadixBins * sizeof(unsigned), c->stream));
     HIP_TRY(hipMalloc(&c->ties, kMaxTies * sizeof(unsigned)));
-    HIP_TRY(hipMalloc(&c->bitmap, (c->nslots / 32 + 1) * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->dcount, kSelBlocks * sizeof(unsigned)));
+    c->bm_words = (c->nslots / 32 + 1 + 3) & ~3ull;  // whole 16-byte vectors
+    HIP_TRY(hipMalloc(&c->bitmap, c->bm_words * sizeof(unsigned)));
   }
   return 0;
 }
@@ -1726,8 +1740,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
 // columns of the starting determinants, as Alg. 2 prescribes)
 static int enter_multi(cdfci_ctx* c) {
   hipStream_t s = c->stream;
-  const uint64_t nwords = c->nslots / 32 + 1;
-  k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, nwords, c->mst);
+  k_mc_clear<<<1024, 256, 0, s>>>(c->bitmap, c->bm_words, c->mst);
   k_mc_init_cands<<<2048, 256, 0, s>>>(c->T, c->nslots, c->cand, c->mst, c->cand_cap);
   k_mc_dense_pages<<<256, 256, 0, s>>>(c->cnt, c->mst, c->cand_cap);
   HIP_TRY(hipGetLastError());
@@ -1767,12 +1780,11 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   hipStream_t s = c->stream;
   const Ham H = ham_of(c);
   const int chunks = (int)((c->n_col + kPage - 1) / kPage);
-  const uint64_t nwords = c->nslots / 32 + 1;
-  EigArgs ea{c->bitmap, nwords, c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, k,
-             c->opts.dx_damping, c->opts.dx_threshold, dE};
-  ScatterArgs sa{H,        c->T,      c->mask,   c->sel_a, c->sel_b, c->eta,  c->mst,
-                 c->ctl,   c->pstat,  c->bitmap, c->cand,  c->cnt,   c->n_col, c->opts.z_threshold,
-                 k};
+  EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, c->chat, k,
+             c->opts.dx_damping, c->opts.dx_threshold, dE,
+             ProbeArgs{H, c->mask, c->sel_a, c->sel_b, c->cand, c->pstat, c->rec, c->n_col}};
+  ApplyArgs aa{H,      c->T,    c->mask,  c->sel_a, c->sel_b,           c->eta, c->mst, c->pstat,
+               c->rec, c->cand, c->n_col, c->opts.z_threshold, k};
   const unsigned page0 = (unsigned)(k * chunks);
   k_reset_barrier<<<1, 1, 0, s>>>(c->ctl);
   if (c->timing)
@@ -1789,13 +1801,15 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     HIP_TRY(mark(step, 0));
     k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
     for (int pass = 0; pass < kRadixPasses; ++pass)
-      k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->ctl, c->mst, c->hist, pass, 0, k);
-    k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->gkey, c->mst, c->sel_slot, c->ties,
-                                                c->sel_a, c->sel_b, k);
+      k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, SelBufs{c->gkey, c->dslot, c->dcount}, c->ctl,
+                                            c->mst, c->hist, pass, 0, k, c->bitmap, c->bm_words);
+    k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, SelBufs{c->gkey, c->dslot, c->dcount}, c->mst, c->sel_slot,
+                                                c->ties, c->sel_a, c->sel_b, k);
     HIP_TRY(mark(step, 1));
-    k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k);
+    k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k, c->cnt, c->n_col);
     HIP_TRY(mark(step, 2));
-    // workgroup 0 solves the reduced problem; the others clear the bitmap
+    // workgroup 0 solves the reduced problem; the others run the probe half
+    // of the scatter
     if (k <= kEigSmall)
       k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
     else if (k <= 256)
@@ -1803,10 +1817,10 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     else
       k_mc_lobpcg<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
     HIP_TRY(mark(step, 3));
-    k_mc_scatter<<<dim3(chunks, k), 256, 0, s>>>(sa);
+    k_mc_apply<<<dim3(chunks, k), 256, 0, s>>>(aa);
     HIP_TRY(mark(step, 4));
-    k_mc_colsum<<<k, 64, 0, s>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k);
-    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->bitmap, c->cand, c->cnt, c->mst,
+    k_mc_colsum<<<k, 64, 0, s>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k, c->hii, c->chat);
+    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);
     k_mc_rescale<<<256, 256, 0, s>>>(c->T, c->nslots, c->mst, 0);
     HIP_TRY(mark(step, 5));
@@ -2138,7 +2152,8 @@ int cdfci_mc_candidates(cdfci_ctx* c, uint64_t* keys, double* g, double* cv, dou
   HIP_TRY(bufs.alloc(&dn, 1));
   HIP_TRY(hipMemsetAsync(dn, 0, sizeof(unsigned long long), s));
   k_mc_export_cands<<<1024, 256, 0, s>>>(c->T, c->cand, c->cnt, c->mst, c->ctl, dk, dg, dc, db,
-                                         (unsigned long long)cap, dn);
+                                         (unsigned long long)cap, dn, c->bitmap);
+  k_mc_clear_words<<<1024, 256, 0, s>>>(c->bitmap, c->bm_words);  // clear again for the next selection
   HIP_TRY(hipGetLastError());
   unsigned long long n = 0;
   HIP_TRY(hipMemcpyAsync(&n, dn, sizeof(n), hipMemcpyDeviceToHost, s));
@@ -2374,8 +2389,8 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->parts) (void)hipFree(c->parts);
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
-  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
-                c->eta, c->pstat, c->hii, c->lan, c->bitmap};
+  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->dslot, c->dcount, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
+                c->eta, c->pstat, c->hii, c->lan, c->bitmap, c->chat, c->rec};
   for (void* p : mc)
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

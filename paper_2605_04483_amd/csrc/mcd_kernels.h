@@ -10,11 +10,15 @@
 //   H_II     pairwise Slater-Condon entries among the chosen determinants;
 //   reduced  A = Q^T H Q with Q = [c~, E_I] (eq. (def-z)); its lowest
 //            eigenpair (k <= 64: Householder tridiagonalisation in shared
-//            memory; larger k: Lanczos with full reorthogonalisation started
-//            from the current point [nu; c_I]); gamma, eta; mu and alpha;
-//   scatter  b += H_{:,I} eta over the k columns with the compression rule,
-//            recalculation sums for b_I, touched entries marked in a slot
-//            bitmap and written to the workgroup's own candidate page;
+//            memory; larger k: LOBPCG started from the current point
+//            [nu; c_I]); gamma, eta; mu and alpha.  The same launch's other
+//            workgroups run the probe half of the scatter, which needs the
+//            chosen set but not eta: the k columns enumerated, their entries
+//            looked up once, stored entries marked in a slot bitmap and
+//            written to the unit's own candidate page, recalculation sums for
+//            b_I, one record per entry;
+//   apply    b += H_{:,I} eta from the records with the compression rule
+//            (inserting the absent entries whose increment is kept);
 //   finish   b_I <- recalculated values, I appended to the candidates.
 // c and b are stored with a lazy global scale: c = s * c_hat, b = s * b_hat, so
 // the gamma rescaling of every entry costs one scalar update (s <- gamma s).
@@ -42,6 +46,12 @@ struct McState {
 };
 
 constexpr int kPage = 256;
+// A candidate position that holds no slot (the entry is absent, zero, or in
+// the chosen set), and the selection key of a position the selection ignores
+// (no slot, or a slot already seen at an earlier position); a key of a real
+// candidate is the bit pattern of a non-negative double, so bit 63 is free.
+constexpr unsigned kNoCand = 0xffffffffu;
+constexpr unsigned long long kKeyExcluded = 1ull << 63;
 constexpr int kRadixBits = 11;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 6;  // digits at bits 53, 42, 31, 20, 9 (11 wide) and 0 (9 wide)
@@ -111,7 +121,7 @@ __global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* 
 }
 
 // clear the candidate bitmap and the gather counters (entering the
-// multicoordinate state; inside a step the eigen launch clears the bitmap)
+// multicoordinate state; inside a step the selection's passes clear the bitmap)
 __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwords, McState* st) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -120,6 +130,12 @@ __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwo
     st->n_tie = 0;
     st->n_dense = 0;
   }
+}
+
+__global__ void __launch_bounds__(256) k_mc_clear_words(unsigned* bitmap, uint64_t nwords) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    bitmap[i] = 0u;
 }
 
 // ---------------------------------------------------------------- selection with last-workgroup scans
@@ -236,45 +252,104 @@ __device__ void mc_scan_last(unsigned* hist, McState* st, int k, int pass) {
   for (int i = tid; i < kRadixBins; i += blockDim.x) hist[i] = 0u;
 }
 
+// The selection's dense lists: pass 0 writes the kept candidates of
+// workgroup b (key and slot) to region b, whose length it records in
+// count[b]; the later passes and the gather read only those.  A region holds
+// as many entries as the positions its workgroup visits, so the arrays need
+// the positions plus one grid of slack.
+struct SelBufs {
+  unsigned long long* key;
+  unsigned* slot;
+  unsigned* count;  // kSelBlocks
+};
+
+__device__ __forceinline__ unsigned long long sel_region(unsigned long long n) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  return (n + stride - 1) / stride * blockDim.x;
+}
+
 // One radix-select pass over the step's candidates; pass 0 also computes the
-// keys (|g|, or |c| when by_c is set) and counts the candidates.  The last
-// workgroup to finish chooses the digit.
+// keys (|g|, or |c| when by_c is set), counts the candidates and compacts
+// them into the dense lists.  The last workgroup to finish chooses the digit.
+// With a bitmap (one bit per slot, clear on entry) pass 0 keeps only the first
+// position of each slot (a determinant reached from several columns) and
+// passes 1..5 clear a fifth of the bitmap each for the next selection (these
+// passes wait on latency, not bandwidth); without one the positions are taken
+// as distinct.
 __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned* cand, const unsigned* cnt,
-                                                  unsigned long long* gkey, const Ctl* ctl, McState* st,
-                                                  unsigned* hist, int pass, int by_c, int k) {
+                                                  SelBufs D, const Ctl* ctl, McState* st, unsigned* hist,
+                                                  int pass, int by_c, int k, unsigned* bitmap, uint64_t nwords) {
   __shared__ unsigned h[kRadixBins];
-  __shared__ unsigned s_cnt;
+  __shared__ unsigned s_wn[4];
+  __shared__ unsigned s_run;
   if (st->skip) return;
+  if (bitmap && pass > 0) {
+    const uint64_t nvec = nwords / 4;  // nwords is a multiple of 4
+    const uint64_t lo = nvec * (pass - 1) / (kRadixPasses - 1), hi = nvec * pass / (kRadixPasses - 1);
+    uint4* v = reinterpret_cast<uint4*>(bitmap);
+    for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (uint64_t)gridDim.x * blockDim.x)
+      v[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
   if (pass > 0 && (st->all || st->done)) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
-  if (tid == 0) s_cnt = 0u;
+  if (tid == 0) s_run = 0u;
   __syncthreads();
   const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long region = sel_region(n), base = blockIdx.x * region;
   const double mu = ctl->mu_hi + ctl->mu_lo;
   const int sh = radix_shift(pass);
   const unsigned long long dm = radix_digit_mask(pass);
   const unsigned long long P = st->prefix, M = st->pmask;
-  unsigned mine = 0;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + tid; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
-    unsigned long long key;
-    if (pass == 0) {
-      key = by_c ? c_key(T[cand[i]]) : g_key(T[cand[i]], mu);
-      gkey[i] = key;
-      ++mine;
-    } else {
-      key = gkey[i];
-      if ((key & M) != P) continue;
+  if (pass == 0) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+      const unsigned long long i = i0 + tid;
+      bool keep = false;
+      unsigned sl = 0u;
+      unsigned long long key = 0ull;
+      if (i < n && (i & (kPage - 1)) < cnt[i / kPage]) {
+        sl = cand[i];
+        keep = sl != kNoCand;
+        if (keep && bitmap) {
+          const unsigned bit = 1u << (sl & 31);
+          keep = !(atomicOr(&bitmap[sl >> 5], bit) & bit);
+        }
+        if (keep) {
+          key = by_c ? c_key(T[sl]) : g_key(T[sl], mu);
+          atomicAdd(&h[(key >> sh) & dm], 1u);
+        }
+      }
+      const unsigned long long bal = __ballot(keep);
+      if (lane == 0) s_wn[w] = (unsigned)__popcll(bal);
+      __syncthreads();
+      unsigned off = s_run;
+      for (int q = 0; q < w; ++q) off += s_wn[q];
+      if (keep) {
+        const unsigned long long at = base + off + (unsigned)__popcll(bal & ((1ull << lane) - 1ull));
+        D.key[at] = key;
+        D.slot[at] = sl;
+      }
+      __syncthreads();
+      if (tid == 0) s_run += s_wn[0] + s_wn[1] + s_wn[2] + s_wn[3];
     }
-    atomicAdd(&h[(key >> sh) & dm], 1u);
+    __syncthreads();
+  } else {
+    const unsigned nb = D.count[blockIdx.x];
+    for (unsigned j = tid; j < nb; j += blockDim.x) {
+      const unsigned long long key = D.key[base + j];
+      if ((key & M) != P) continue;
+      atomicAdd(&h[(key >> sh) & dm], 1u);
+    }
+    __syncthreads();
   }
-  if (pass == 0 && mine) atomicAdd(&s_cnt, mine);
-  __syncthreads();
   for (int i = tid; i < kRadixBins; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
-  if (pass == 0 && tid == 0 && s_cnt) atomicAdd(&st->n_total, (unsigned long long)s_cnt);
+  if (pass == 0 && tid == 0) {
+    D.count[blockIdx.x] = s_run;
+    if (s_run) atomicAdd(&st->n_total, (unsigned long long)s_run);
+  }
   if (last_workgroup(&st->arrive)) mc_scan_last(hist, st, k, pass);
 }
 
@@ -282,28 +357,27 @@ __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned*
 // ties; the last workgroup resolves the ties by key order and fills the keys
 // of the chosen set.  Slots shared between workgroups go through
 // agent-scope atomics (the XCDs' L2 caches are not coherent).
-__global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, const unsigned* cand,
-                                                        const unsigned* cnt,
-                                                        const unsigned long long* gkey, McState* st,
+__global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, SelBufs D, McState* st,
                                                         int64_t* sel_slot, unsigned* ties, uint64_t* sel_a,
                                                         uint64_t* sel_b, int k) {
   if (st->skip) return;
   const int tid = threadIdx.x;
   const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long base = blockIdx.x * sel_region(n);
   const unsigned long long P = st->prefix, M = st->pmask;
   const int all = st->all, done = st->done;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + tid; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
-    const unsigned long long km = gkey[i] & M;
+  const unsigned nb = D.count[blockIdx.x];
+  for (unsigned j = tid; j < nb; j += blockDim.x) {
+    const unsigned long long km = D.key[base + j] & M;
+    const unsigned sl = D.slot[base + j];
     const bool take = all || km > P || (done && km == P);
     if (take) {
       const unsigned long long q = atomicAdd(&st->n_sel, 1ull);
       if (q < (unsigned long long)k)
-        __hip_atomic_store(&sel_slot[q], (int64_t)cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sel_slot[q], (int64_t)sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (km == P) {
       const unsigned long long t = atomicAdd(&st->n_tie, 1ull);
-      if (t < kMaxTies) __hip_atomic_store(&ties[t], cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t < kMaxTies) __hip_atomic_store(&ties[t], sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (!last_workgroup(&st->arrive)) return;
@@ -345,11 +419,20 @@ __global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, const uns
 
 // H_II: block y builds column y (ket = chosen determinant y)
 __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, const uint64_t* sel_b,
-                                                const McState* st, double* hii, int k) {
+                                                const McState* st, double* hii, int k, unsigned* cnt,
+                                                int64_t n_col) {
   __shared__ Lists L;
   __shared__ double s_red[4];
   if (st->skip) return;
   const int m = (int)min(st->n_sel, (unsigned long long)k);
+  // the scatter pages' lengths (the selection has read the previous ones):
+  // every entry of a chosen column has a position, columns past m none
+  const int chunks = (int)((n_col + kPage - 1) / kPage);
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < (int64_t)k * chunks;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = p % chunks;
+    cnt[p] = p / chunks < m ? (unsigned)min((int64_t)kPage, n_col - x * kPage) : 0u;
+  }
   const int y = blockIdx.x;
   if (y >= m) return;
   const uint64_t a = sel_a[y], b = sel_b[y];
@@ -553,9 +636,100 @@ __device__ __forceinline__ double tri_lowest_wg(const double* __restrict__ a, co
   return lam;
 }
 
+// ---------------------------------------------------------------- scatter, probe half
+
+// Per quarter of a scatter page (a page is one chosen column x one chunk of
+// 256 entries): the partial recalculation sum of b_i over the entries outside
+// the chosen set, and the probe / atomic / insert counts of both halves.
+struct PageStat {
+  double recalc;
+  unsigned probes, atomics, inserts;
+  int err;
+};
+
+// What the probe half learnt about one column entry j of chosen column i,
+// for the apply half (same page and lane).
+struct ScatRec {
+  unsigned slot;  // table slot (kinds kRecZero, kRecLive)
+  unsigned kind;
+  double h;       // H_ji
+};
+constexpr unsigned kRecNone = 0;  // H_ji = 0, j in the chosen set, or past the column
+constexpr unsigned kRecZero = 1;  // stored with c_j = 0
+constexpr unsigned kRecLive = 2;  // stored with c_j != 0
+constexpr unsigned kRecMiss = 3;  // not stored
+
+// The probe half runs in the workgroups 1.. of an eigen launch while
+// workgroup 0 solves the reduced problem: enumerating the chosen columns,
+// their Slater-Condon entries and the table lookups need the chosen set but
+// not eta.  Only c of the chosen determinants changes during that launch, and
+// the probe half neither reads nor marks those (their b is recalculated and
+// they join the candidates in the finish), so it sees the table as the
+// selection left it.
+struct ProbeArgs {
+  Ham H;
+  uint64_t mask;
+  const uint64_t* sel_a;
+  const uint64_t* sel_b;
+  unsigned* cand;
+  PageStat* pstat;
+  ScatRec* rec;
+  int64_t n_col;
+};
+
+// Lookup for the scatter: the key pair in one 16-byte cached load, c only on
+// a match.  Within the scatter launch c never changes and keys only appear
+// (with c = 0), so a stale "empty" costs nothing: a large update then goes
+// through the claiming insert, which sees the current slot, and a small one
+// leaves b alone exactly as for an absent key.  A key seen while its beta word
+// is still being published is looked up again with coherent loads.
+__device__ __forceinline__ int64_t scatter_find(const Slot* __restrict__ T, uint64_t mask, uint64_t a,
+                                                uint64_t b, double* c, int* nprobe) {
+  uint64_t idx = hash_key(a, b) & mask;
+  for (int n = 0; n < kMaxProbe; ++n) {
+    const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&T[idx]);
+    *nprobe = n + 1;
+    if (kk.x == kEmpty) return -1;
+    if (kk.x == a) {
+      if (kk.y == b) {
+        *c = T[idx].c;
+        return (int64_t)idx;
+      }
+      if (kk.y == kPending) {
+        int probes = 0;
+        SlotVal sv;
+        const int64_t s = table_find(T, mask, a, b, &probes, &sv);
+        if (s >= 0) *c = sv.c;
+        *nprobe = n + 1 + probes;
+        return s;
+      }
+    }
+    idx = (idx + 1) & mask;
+  }
+  return -1;
+}
+
+// The lists of one chosen determinant built by a group of 256 threads (t is
+// the thread's index in the group; threads 0..N-1 must take part, a barrier
+// must follow).
+__device__ inline void make_lists_group(uint64_t a, uint64_t b, int N, Lists& L, int t) {
+  if (t < N) {
+    const uint64_t below = (1ull << t) - 1ull;
+    const int ia = popc(a & below), ib = popc(b & below);
+    if ((a >> t) & 1) L.oa[ia] = (int8_t)t;
+    else L.va[t - ia] = (int8_t)t;
+    if ((b >> t) & 1) L.ob[ib] = (int8_t)t;
+    else L.vb[t - ib] = (int8_t)t;
+  }
+  if (t == 0) {
+    L.na = popc(a);
+    L.nva = N - L.na;
+    L.nb = popc(b);
+    L.nvb = N - L.nb;
+  }
+}
+
 struct EigArgs {
-  unsigned* bitmap;  // cleared by the launch's workgroups 1.. for the coming scatter
-  uint64_t nwords;
   const Slot* T;
   Slot* Tw;
   const int64_t* sel_slot;
@@ -564,9 +738,11 @@ struct EigArgs {
   Ctl* ctl;
   double* lan;  // (kLanczosMax + 1) * (k + 1) scratch
   double* eta_out;
+  double* chat_out;  // c_hat of the chosen determinants after the step
   int k;
   double theta, dx_tol;
   double* tr_E;  // optional per-step energy trace
+  ProbeArgs P;   // the probe half, run by the other workgroups
 };
 
 // The reduced matrix A (order n = m + off, off = 1 when the c~ column exists):
@@ -659,21 +835,122 @@ __device__ void mc_multidot(const double* V, int n, int j, const double* s_w, do
   __syncthreads();
 }
 
-// Workgroups 1.. of an eigen launch: clear the candidate bitmap for the coming
-// scatter (16-byte stores) and reset the gather counters, while workgroup 0
-// solves the reduced problem on its own compute unit.
-__device__ void mc_clear_bitmap(const EigArgs& A) {
+// Membership of a slot in the chosen set, through an open-addressing set of
+// the chosen slots in shared memory (2 kSetSlots >= 2 k entries).
+constexpr int kSetSlots = 2048;
+__device__ __forceinline__ unsigned set_hash(unsigned long long x) {
+  return (unsigned)((x * 0x9e3779b97f4a7c15ull) >> 53);  // 11 bits
+}
+__device__ inline bool chosen_set_has(const unsigned long long* set, unsigned long long slot) {
+  for (unsigned h = set_hash(slot);; h = (h + 1) & (kSetSlots - 1)) {
+    const unsigned long long v = set[h];
+    if (v == slot) return true;
+    if (v == ~0ull) return false;
+  }
+}
+
+// Orders a wave's shared-memory writes before its later reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Workgroups 1.. of an eigen launch, while workgroup 0 solves the reduced
+// problem on its own compute unit.  Unless the step is skipped, the probe half
+// of the scatter.  Its work is cut into quarter pages (64 entries of one
+// chosen column); every wave takes a contiguous range of them and runs with
+// no workgroup barrier and no atomic (its determinant lists in its own shared
+// memory).  An entry j of column i with H_ji != 0, j outside the chosen set,
+// is looked up once; a stored j takes the entry's own position in the page's
+// candidate list and adds H_ji c_hat_j to the quarter's recalculation sum;
+// its record tells the apply half whether j is stored and whether c_j != 0.
+// A determinant reached from several columns appears at several positions:
+// the selection's first pass keeps its first occurrence.  No entry is
+// inserted during the launch, so a lookup whose first slot holds neither the
+// key nor the empty mark is the only one that walks on.
+__device__ void mc_probe_phase(const EigArgs& A) {
+  __shared__ unsigned long long s_set[kSetSlots];
+  __shared__ Lists s_wl[16];
+  const ProbeArgs& P = A.P;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t part = blockIdx.x - 1, nparts = gridDim.x - 1;
-  const uint64_t nvec = A.nwords / 4;
-  uint4* v = reinterpret_cast<uint4*>(A.bitmap);
-  for (uint64_t i = part * blockDim.x + threadIdx.x; i < nvec; i += nparts * blockDim.x)
-    v[i] = make_uint4(0u, 0u, 0u, 0u);
-  if (part == 0) {
-    for (uint64_t i = nvec * 4 + threadIdx.x; i < A.nwords; i += blockDim.x) A.bitmap[i] = 0u;
-    if (threadIdx.x == 0) {
-      A.st->n_tie = 0;
-      A.st->n_dense = 0;
+  if (part == 0 && tid == 0) {  // gather counters of the next selection
+    A.st->n_tie = 0;
+    A.st->n_dense = 0;
+  }
+  if (A.st->skip) return;
+  const int chunks = (int)((P.n_col + kPage - 1) / kPage);
+  const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
+  for (int i = tid; i < kSetSlots; i += blockDim.x) s_set[i] = ~0ull;
+  __syncthreads();
+  for (int q = tid; q < m; q += blockDim.x) {
+    const unsigned long long v = (unsigned long long)A.sel_slot[q];
+    for (unsigned h = set_hash(v);; h = (h + 1) & (kSetSlots - 1))
+      if (atomicCAS(&s_set[h], ~0ull, v) == ~0ull) break;
+  }
+  __syncthreads();
+  const long long nw = (long long)nparts * (blockDim.x >> 6);
+  const long long wid = (long long)part * (blockDim.x >> 6) + w;
+  const long long perc = 4LL * chunks;  // quarter pages per column
+  const long long Q = (long long)m * perc;
+  const long long q0 = wid * Q / nw, q1 = (wid + 1) * Q / nw;
+  Lists& L = s_wl[w];
+  int ycur = -1;
+  uint64_t a = 0, b = 0;
+  for (long long q = q0; q < q1; ++q) {
+    const int y = (int)(q / perc);
+    const int rem = (int)(q - (long long)y * perc);
+    const int x = rem >> 2, qq = rem & 3;
+    if (y != ycur) {
+      ycur = y;
+      a = P.sel_a[y];
+      b = P.sel_b[y];
+      wave_sync();  // the previous column's lists are no longer read
+      make_lists_group(a, b, P.H.N, L, lane);
+      wave_sync();
     }
+    const size_t pos = (size_t)(y * chunks + x) * kPage + qq * 64 + lane;
+    const int64_t e = (int64_t)x * kPage + qq * 64 + lane;
+    double recalc = 0.0;
+    unsigned probes = 0u;
+    if (e < P.n_col) {
+      ScatRec rc{0u, kRecNone, 0.0};
+      unsigned cslot = kNoCand;
+      if (e != 0) {  // entry 0 is the chosen determinant itself
+        uint64_t ja = a, jb = b;
+        const double Hj = column_entry(P.H, L, a, b, e, 0.0, &ja, &jb);
+        if (Hj != 0.0) {
+          const uint64_t idx = hash_key(ja, jb) & P.mask;
+          const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&A.T[idx]);
+          int64_t slot = -1;
+          probes = 1u;
+          if (kk.x == ja && kk.y == jb) {
+            slot = (int64_t)idx;
+          } else if (kk.x != kEmpty) {
+            double cdummy = 0.0;
+            int nf = 0;
+            slot = scatter_find(A.T, P.mask, ja, jb, &cdummy, &nf);
+            probes = (unsigned)nf;
+          }
+          if (slot < 0) {
+            rc = ScatRec{0u, kRecMiss, Hj};
+          } else if (!chosen_set_has(s_set, (unsigned long long)slot)) {
+            const double cj = A.T[slot].c;
+            rc = ScatRec{(unsigned)slot, cj != 0.0 ? kRecLive : kRecZero, Hj};
+            recalc = Hj * cj;
+            cslot = (unsigned)slot;
+          }
+        }
+      }
+      P.rec[pos] = rc;
+      P.cand[pos] = cslot;
+    }
+    for (int offs = 32; offs > 0; offs >>= 1) {
+      recalc += __shfl_xor(recalc, offs);
+      probes += __shfl_xor(probes, offs);
+    }
+    if (lane == 0) P.pstat[(size_t)(y * chunks + x) * 4 + qq] = PageStat{recalc, probes, 0u, 0u, 0};
   }
 }
 
@@ -698,7 +975,9 @@ __device__ void mc_step_finish(const EigArgs& A, int m, double s, dd mu, dd al, 
   if (tid < m) {
     A.eta_out[tid] = eta_i;
     Slot* sl = A.Tw + A.sel_slot[tid];
-    sl->c = sl->c + eta_i / s_new;  // c_hat_I += eta / s'
+    const double cn = sl->c + eta_i / s_new;  // c_hat_I += eta / s'
+    sl->c = cn;
+    A.chat_out[tid] = cn;
   }
   if (tid == 0) {
     ctl->mu_hi = mu_n.hi;
@@ -721,146 +1000,6 @@ __device__ void mc_step_finish(const EigArgs& A, int m, double s, dd mu, dd al, 
     A.st->rescale = fabs(log2(fabs(s_new))) > 400.0 ? 1 : 0;
     if (!(fabs(s_new) > 1e-250) || !(E == E)) ctl->error |= kErrNumeric;
   }
-}
-
-// one workgroup of 1024 threads
-// KM = largest k the instance serves; for KM <= 256 the Lanczos basis
-// (64 x 257 doubles) lives in shared memory, otherwise in global memory.
-template <int KM>
-__global__ void __launch_bounds__(1024) k_mc_eig(EigArgs A) {
-  constexpr bool kVshared = KM <= 256;
-  __shared__ double s_c[KM], s_b[KM], s_a0[KM], s_x[KM + 1], s_w[KM + 1];
-  __shared__ double s_part[1024];
-  __shared__ double s_red[16];
-  __shared__ double s_alpha[kLanczosMax + 1], s_beta[kLanczosMax + 1];
-  __shared__ double s_y[kLanczosMax + 1], s_h[kLanczosMax + 1], s_h2[kLanczosMax + 1];
-  __shared__ double s_wk[5 * (kLanczosMax + 1)];
-  __shared__ unsigned long long s_bal[16];
-  __shared__ double sV[kVshared ? kLanczosMax * (KM + 1) : 1];
-  if (blockIdx.x > 0) {
-    mc_clear_bitmap(A);
-    return;
-  }
-  Ctl* ctl = A.ctl;
-  if (A.st->skip) return;
-  const int tid = threadIdx.x;
-  const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
-  const double s = A.st->scale;
-  const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
-  const double* hii = A.hii;
-  for (int i = tid; i < m; i += blockDim.x) {
-    const Slot sl = A.T[A.sel_slot[i]];
-    s_c[i] = s * sl.c;
-    s_b[i] = s * sl.b;
-  }
-  __syncthreads();
-  // hc = H_II c_I
-  mc_matvec(hii, m, 0, 0.0, s_a0, s_c, s_w, s_part);
-  __syncthreads();
-  const double hc_i = tid < m ? s_w[tid] : 0.0;
-  const double ci = tid < m ? s_c[tid] : 0.0, bi = tid < m ? s_b[tid] : 0.0;
-  const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
-  const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
-  const dd chc = wg_sum_dd(two_prod(ci, hc_i), s_red);
-  // nu^2 = mu - c_I.c_I and the numerator of A_00 = alpha - 2 c_I.b_I + c_I.H_II.c_I
-  const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
-  const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
-  const double nu2v = dd_val(nu2);
-  const int off = nu2v > kNu2Floor * dd_val(mu) ? 1 : 0;
-  const double nu = off ? sqrt(nu2v) : 0.0;
-  const double a00 = off ? dd_val(num) / nu2v : 0.0;
-  if (tid < m) s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
-  const int n = m + off;
-  if (n == 0) {  // nothing stored and nothing chosen: no step is possible
-    if (tid == 0) ctl->stopped = 1;
-    return;
-  }
-  double* V = kVshared ? sV : A.lan;  // rows 0..kLanczosMax-1: Lanczos vectors
-  // start vector: the current point [nu; c_I]
-  {
-    double part = 0.0;
-    for (int r = tid; r < n; r += blockDim.x) {
-      const double v = (off && r == 0) ? nu : s_c[r - off];
-      V[r] = v;
-      part += v * v;
-    }
-    double nrm = sqrt(wg_sum(part, s_red));
-    const bool ok = nrm > 0.0;
-    for (int r = tid; r < n; r += blockDim.x) V[r] = ok ? V[r] / nrm : (r == 0 ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  int iters = 0;
-  const int jmax = min(kLanczosMax, n);
-  for (int j = 0; j < jmax; ++j) {
-    for (int r = tid; r < n; r += blockDim.x) s_x[r] = V[(size_t)j * n + r];
-    __syncthreads();
-    mc_matvec(hii, m, off, a00, s_a0, s_x, s_w, s_part);
-    __syncthreads();
-    // classical Gram-Schmidt against V_0..V_j, twice
-    mc_multidot(V, n, j, s_w, s_h);
-    for (int r = tid; r < n; r += blockDim.x) {
-      double t = s_w[r];
-#pragma unroll 8
-      for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
-      s_w[r] = t;
-    }
-    __syncthreads();
-    if (tid <= j) s_h2[tid] = s_h[tid];
-    __syncthreads();
-    mc_multidot(V, n, j, s_w, s_h);
-    double part = 0.0;
-    for (int r = tid; r < n; r += blockDim.x) {
-      double t = s_w[r];
-#pragma unroll 8
-      for (int i = 0; i <= j; ++i) t -= s_h[i] * V[(size_t)i * n + r];
-      s_w[r] = t;
-      part += t * t;
-    }
-    const double beta = sqrt(wg_sum(part, s_red));
-    if (tid == 0) {
-      s_alpha[j] = s_h2[j] + s_h[j];
-      s_beta[j] = beta;
-    }
-    __syncthreads();
-    iters = j + 1;
-    bool stop = (j + 1 == jmax) || !(beta > 1e-14 * fabs(s_alpha[0]) + 1e-300);
-    if (!stop && j >= 5 && (j & 3) == 1) {
-      // residual of the lowest Ritz pair: |beta_j y_j|; the eigenvalue error
-      // is quadratic in it
-      const double l = tri_lowest_wg(s_alpha, s_beta, j + 1, s_y, s_wk, s_bal);
-      if (fabs(beta * s_y[j]) <= 1e-10 * fabs(l)) stop = true;
-      __syncthreads();  // s_y is rewritten by the next check
-    }
-    if (stop) break;
-    const double inv_beta = 1.0 / beta;
-    for (int r = tid; r < n; r += blockDim.x) V[(size_t)(j + 1) * n + r] = s_w[r] * inv_beta;
-    __syncthreads();
-  }
-  const double lam = tri_lowest_wg(s_alpha, s_beta, iters, s_y, s_wk, s_bal);
-  // z = sqrt(-lambda) * (V^T y)
-  const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
-  for (int r = tid; r < n; r += blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < iters; ++j) acc += V[(size_t)j * n + r] * s_y[j];
-    s_x[r] = zscale * acc;
-  }
-  __syncthreads();
-  // sign: z_0 >= 0 with the c~ column, else z . c_I >= 0
-  double zc_part = 0.0;
-  if (!off)
-    for (int r = tid; r < n; r += blockDim.x) zc_part += s_x[r] * s_c[r];
-  const double zc = wg_sum(zc_part, s_red);
-  const double sgn = off ? (s_x[0] < 0.0 ? -1.0 : 1.0) : (zc < 0.0 ? -1.0 : 1.0);
-  const double gamma = off ? sgn * s_x[0] / nu : 1.0;
-  double eta_i = 0.0;
-  if (tid < m) eta_i = sgn * s_x[off + tid] - gamma * s_c[tid];
-  __syncthreads();
-  if (tid < m) s_x[tid] = eta_i;
-  __syncthreads();
-  mc_matvec(hii, m, 0, 0.0, s_a0, s_x, s_w, s_part);
-  __syncthreads();
-  const double heta_i = tid < m ? s_w[tid] : 0.0;
-  mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
 }
 
 // Several workgroup sums at once (one barrier pair for all of them), each in
@@ -958,7 +1097,7 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
   __shared__ double s_g[9], s_y[3];
   __shared__ int s_use[3];
   if (blockIdx.x > 0) {
-    mc_clear_bitmap(A);
+    mc_probe_phase(A);
     return;
   }
   Ctl* ctl = A.ctl;
@@ -1169,7 +1308,7 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
 }
 
 constexpr int kEigSmall = 64;  // m up to this: the eigen step runs from shared memory
-constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest clear)
+constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest run the probe half)
 
 // y = A x with H_II in shared memory, for m <= 64: lane i forms row off + i,
 // the wave's sum forms row 0.
@@ -1331,7 +1470,7 @@ __device__ void tridiagonalize_wg(double* __restrict__ sA, int n, double* __rest
   __syncthreads();
 }
 
-// The eigen step for m <= 64 (same mathematics as k_mc_eig) in one
+// The eigen step for m <= 64 (same mathematics as k_mc_lobpcg) in one
 // workgroup of kEigWaves waves.  H_II, the reduced matrix and the reflectors
 // sit in shared memory; the lowest eigenpair comes from a Householder
 // tridiagonalisation, the tridiagonal solver (multisection + inverse
@@ -1349,7 +1488,7 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
   __shared__ double s_wk[5 * NV];
   __shared__ unsigned long long s_bal[kEigWaves];
   if (blockIdx.x > 0) {
-    mc_clear_bitmap(A);
+    mc_probe_phase(A);
     return;
   }
   Ctl* ctl = A.ctl;
@@ -1449,187 +1588,117 @@ __global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
   mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, n, s_red);
 }
 
-// b_hat += H_{:,I} eta / s' with the compression rule; recalculation sums;
-// touched entries marked once in the bitmap and written to this workgroup's
-// candidate page.  grid = (column chunks, k); one column entry per thread.
-// What a scatter workgroup hands to the finish kernel, written once without
-// atomics (contended device atomics on a few counters cost more than the
-// scatter itself): its part of the recalculated b of its column and its
-// counts of probes, FP64 atomics and inserts.
-struct PageStat {
-  double recalc;
-  unsigned probes, atomics, inserts;
-  int err;
-};
+// ---------------------------------------------------------------- scatter, apply half
 
-struct ScatterArgs {
+// b_hat += H_{:,I} eta / s' under the compression rule (update b_j iff
+// c_j != 0 or |eta_i H_ji| >= tau), from the probe half's records: a stored j
+// costs one FP64 atomic on its recorded slot (none when c_j = 0 and the
+// increment is small); an absent j with a large increment is inserted (its key
+// enumerated again) and takes the entry's position in the page's candidate
+// list.  grid =
+// (column chunks, k), one record per thread.  Entries of the chosen set are
+// skipped: their b is recalculated in the finish.  The page's counts are added
+// to the probe half's record of its first quarter.
+struct ApplyArgs {
   Ham H;
   Slot* T;
   uint64_t mask;
   const uint64_t* sel_a;
   const uint64_t* sel_b;
   const double* eta;
-  McState* st;
-  Ctl* ctl;
-  PageStat* pstat;  // one per scatter workgroup (page)
-  unsigned* bitmap;
+  const McState* st;
+  PageStat* pstat;
+  const ScatRec* rec;
   unsigned* cand;
-  unsigned* cnt;
   int64_t n_col;
   double tau;
   int k;
 };
 
-// Lookup for the scatter: the key pair in one 16-byte cached load, c only on
-// a match.  Within the scatter launch c never changes and keys only appear
-// (with c = 0), so a stale "empty" costs nothing: a large update then goes
-// through the claiming insert, which sees the current slot, and a small one
-// leaves b alone exactly as for an absent key.  A key seen while its beta word
-// is still being published is looked up again with coherent loads.
-__device__ __forceinline__ int64_t scatter_find(const Slot* __restrict__ T, uint64_t mask, uint64_t a,
-                                                uint64_t b, double* c, int* nprobe) {
-  uint64_t idx = hash_key(a, b) & mask;
-  for (int n = 0; n < kMaxProbe; ++n) {
-    const ulonglong2 kk = *reinterpret_cast<const ulonglong2*>(&T[idx]);
-    *nprobe = n + 1;
-    if (kk.x == kEmpty) return -1;
-    if (kk.x == a) {
-      if (kk.y == b) {
-        *c = T[idx].c;
-        return (int64_t)idx;
-      }
-      if (kk.y == kPending) {
-        int probes = 0;
-        SlotVal sv;
-        const int64_t s = table_find(T, mask, a, b, &probes, &sv);
-        if (s >= 0) *c = sv.c;
-        *nprobe = n + 1 + probes;
-        return s;
-      }
-    }
-    idx = (idx + 1) & mask;
-  }
-  return -1;
-}
-
-__global__ void __launch_bounds__(256) k_mc_scatter(ScatterArgs A) {
+__global__ void __launch_bounds__(256) k_mc_apply(ApplyArgs A) {
   __shared__ Lists L;
-  __shared__ double s_diag;
-  __shared__ double s_red[4];
-  __shared__ unsigned s_ins, s_ncand, s_probes, s_atomics;
-  __shared__ int s_err;
-  const int y = blockIdx.y;
-  const unsigned page = (unsigned)(y * gridDim.x + blockIdx.x);
+  __shared__ unsigned s_ins, s_probes, s_atomics;
+  __shared__ int s_err, s_need;
   if (A.st->skip) return;
+  const int y = blockIdx.y;
   const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
-  if (y >= m) {
-    if (threadIdx.x == 0) {
-      A.cnt[page] = 0;
-      A.pstat[page] = PageStat{0.0, 0u, 0u, 0u, 0};
-    }
-    return;
-  }
-  const uint64_t a = A.sel_a[y], b = A.sel_b[y];
-  const double eta = A.eta[y];
-  const double coef = eta * A.st->inv_scale;
-  make_lists_block(a, b, A.H.N, L);
+  if (y >= m) return;
+  const unsigned page = (unsigned)(y * gridDim.x + blockIdx.x);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (threadIdx.x == 0) {
-    s_ins = 0;
+    s_ins = s_probes = s_atomics = 0u;
     s_err = 0;
-    s_ncand = 0;
-    s_probes = 0;
-    s_atomics = 0;
+    s_need = 0;
   }
   __syncthreads();
-  const Ham H = A.H;
-  if (blockIdx.x == 0) {  // H_DD of this column, shared by the workgroup
-    double part = 0.0;
-    const int nt = diag_terms(L);
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) part += diag_term(H, L, t);
-    for (int offs = 32; offs > 0; offs >>= 1) part += __shfl_xor(part, offs);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += s_red[i];
-      s_diag = t;
-    }
-    __syncthreads();
-  }
-  double recalc = 0.0;
-  int err = 0, my_probes = 0, my_atomics = 0;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < A.n_col) {
+  ScatRec r{0u, kRecNone, 0.0};
+  if (e < A.n_col) r = A.rec[(size_t)page * kPage + threadIdx.x];
+  const double eta = A.eta[y];
+  const double coef = eta * A.st->inv_scale;
+  const bool big = fabs(eta * r.h) >= A.tau;
+  const bool insert = r.kind == kRecMiss && big;
+  if (insert) s_need = 1;
+  __syncthreads();
+  const uint64_t a = A.sel_a[y], b = A.sel_b[y];
+  if (s_need) make_lists_block(a, b, A.H.N, L);
+  __syncthreads();
+  int my_atomics = 0, my_probes = 0, err = 0;
+  if (r.kind == kRecLive || (r.kind == kRecZero && big)) {
+    atomic_add_f64(&A.T[r.slot].b, r.h * coef);
+    my_atomics = 1;
+  } else if (insert) {
     uint64_t ja = a, jb = b;
-    const double Hj = e == 0 ? s_diag : column_entry(H, L, a, b, e, 0.0, &ja, &jb);
-    if (Hj != 0.0) {
-      int probes = 0;
-      SlotVal sv;
-      double cj = 0.0;
-      int nfind = 0;
-      int64_t slot = scatter_find(A.T, A.mask, ja, jb, &cj, &nfind);
-      my_probes += nfind;
-      if (e != 0) {
-        const bool big = fabs(eta * Hj) >= A.tau;
-        if (slot < 0 && big) {
-          int ins = 0;
-          slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
-          my_probes += probes;
-          if (ins) atomicAdd(&s_ins, 1u);
-          cj = slot >= 0 ? sv.c : 0.0;
-        }
-        if (slot >= 0 && (cj != 0.0 || big)) {
-          atomic_add_f64(&A.T[slot].b, Hj * coef);
-          ++my_atomics;
-        }
-        if (slot >= 0) {
-          const unsigned bit = 1u << (slot & 31);
-          const unsigned old = atomicOr(&A.bitmap[slot >> 5], bit);
-          if (!(old & bit)) {
-            const unsigned pos = atomicAdd(&s_ncand, 1u);
-            A.cand[(size_t)page * kPage + pos] = (unsigned)slot;
-          }
-        }
-      }
-      recalc += Hj * cj;
+    (void)column_entry(A.H, L, a, b, e, 0.0, &ja, &jb);
+    int ins = 0, probes = 0;
+    SlotVal sv;
+    const int64_t slot = table_upsert(A.T, A.mask, ja, jb, &ins, &probes, &err, &sv);
+    my_probes = probes;
+    if (slot >= 0) {
+      if (ins) atomicAdd(&s_ins, 1u);
+      atomic_add_f64(&A.T[slot].b, r.h * coef);
+      my_atomics = 1;
+      A.cand[(size_t)page * kPage + threadIdx.x] = (unsigned)slot;
     }
   }
-  // workgroup sum of the recalculation part and the counts, stored for the finish
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int offs = 32; offs > 0; offs >>= 1) recalc += __shfl_xor(recalc, offs);
-  if (lane == 0) s_red[w] = recalc;
   if (err) atomicOr(&s_err, err);
   if (my_probes) atomicAdd(&s_probes, (unsigned)my_probes);
   if (my_atomics) atomicAdd(&s_atomics, (unsigned)my_atomics);
   __syncthreads();
   if (threadIdx.x == 0) {
-    double r = 0.0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += s_red[i];
-    A.cnt[page] = s_ncand;
-    A.pstat[page] = PageStat{r, s_probes, s_atomics, s_ins, s_err};
+    PageStat q = A.pstat[(size_t)page * 4];
+    q.probes += s_probes;
+    q.atomics += s_atomics;
+    q.inserts += s_ins;
+    q.err |= s_err;
+    A.pstat[(size_t)page * 4] = q;
   }
 }
 
-// One wave per chosen column: its scatter pages summed in a fixed order into
-// colstat[i] (the recalculated b_i and the column's counts).
+// One wave per chosen column: colstat[i] = its scatter pages summed in a
+// fixed order (the part of the recalculated b_i from entries outside the
+// chosen set, and the column's counts) plus (H_II c_hat_I)_i, the part from
+// the chosen set with its new coefficients.
 __global__ void __launch_bounds__(64) k_mc_colsum(const PageStat* pstat, int chunks, PageStat* colstat,
-                                                  const McState* st, int k) {
+                                                  const McState* st, int k, const double* hii,
+                                                  const double* chat) {
   if (st->skip) return;
   const int m = (int)min(st->n_sel, (unsigned long long)k);
   const int i = blockIdx.x;
   if (i >= m) return;
   const int lane = threadIdx.x;
-  double r = 0.0;
+  double r = 0.0, rh = 0.0;
   unsigned pr = 0, at = 0, in = 0;
   int er = 0;
-  for (int x = lane; x < chunks; x += 64) {
-    const PageStat q = pstat[(size_t)i * chunks + x];
+  for (int x = lane; x < 4 * chunks; x += 64) {
+    const PageStat q = pstat[(size_t)i * chunks * 4 + x];
     r += q.recalc;
     pr += q.probes;
     at += q.atomics;
     in += q.inserts;
     er |= q.err;
   }
+  for (int q = lane; q < m; q += 64) rh += hii[(size_t)i * m + q] * chat[q];
+  r += rh;
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_xor(r, off);
     r = (lane & off) ? (o + r) : (r + o);
@@ -1645,9 +1714,8 @@ __global__ void __launch_bounds__(64) k_mc_colsum(const PageStat* pstat, int chu
 // candidates (own pages after the scatter pages); the scatter's counts;
 // occupancy check
 __global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_slot, const PageStat* colstat,
-                                                    unsigned* bitmap, unsigned* cand, unsigned* cnt,
-                                                    McState* st, Ctl* ctl, uint64_t max_entries,
-                                                    unsigned page0, int k) {
+                                                    unsigned* cand, unsigned* cnt, McState* st, Ctl* ctl,
+                                                    uint64_t max_entries, unsigned page0, int k) {
   __shared__ unsigned s_n;
   __shared__ unsigned long long s_cnt[3];
   __shared__ int s_err;
@@ -1678,13 +1746,9 @@ __global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const int64_t slot = sel_slot[i];
     T[slot].b = colstat[i].recalc;
-    const unsigned bit = 1u << (slot & 31);
-    const unsigned old = atomicOr(&bitmap[slot >> 5], bit);
-    if (!(old & bit)) {
-      const unsigned pos = atomicAdd(&s_n, 1u);
-      cand[(size_t)page0 * kPage + pos] = (unsigned)slot;
-    }
+    cand[(size_t)page0 * kPage + i] = (unsigned)slot;  // the scatter pages never hold the chosen set
   }
+  if (threadIdx.x == 0) s_n = (unsigned)m;
   __syncthreads();
   const unsigned npg = (unsigned)((k + kPage - 1) / kPage);
   for (unsigned p = threadIdx.x; p < npg; p += blockDim.x)
@@ -1730,13 +1794,17 @@ __global__ void k_mc_rescale_done(McState* st, int force) {
 __global__ void __launch_bounds__(256) k_mc_export_cands(const Slot* T, const unsigned* cand, const unsigned* cnt,
                                                          const McState* st, const Ctl* ctl, uint64_t* keys,
                                                          double* g, double* cv, double* bv, unsigned long long cap,
-                                                         unsigned long long* count) {
+                                                         unsigned long long* count, unsigned* bitmap) {
   const unsigned long long n = st->n_pages * kPage;
   const double mu = ctl->mu_hi + ctl->mu_lo;
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (unsigned long long)gridDim.x * blockDim.x) {
     if ((i & (kPage - 1)) >= cnt[i / kPage]) continue;
-    const Slot v = T[cand[i]];
+    const unsigned sl = cand[i];
+    if (sl == kNoCand) continue;
+    const unsigned bit = 1u << (sl & 31);
+    if (atomicOr(&bitmap[sl >> 5], bit) & bit) continue;  // seen at an earlier position
+    const Slot v = T[sl];
     const unsigned long long q = atomicAdd(count, 1ull);
     if (q < cap) {
       keys[2 * q] = v.ka;

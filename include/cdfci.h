@@ -117,8 +117,10 @@ int cdfci_init_hubbard(const int* dims, int ndim, double t, double U, int n_alph
  * Sec. 3.2): the k candidates of largest |4 b_i + 4 mu c_i| from the previous
  * step's columns, the step (gamma, eta) from the lowest eigenpair of the
  * (k+1)-dimensional Q^T H Q, c <- gamma c + E_I eta, b <- gamma b + H_{:,I} eta.
- * Steps with different k may be mixed on one context.  Enqueued on the
- * context's stream; returns after completion.  out may be NULL. */
+ * Steps with different k may be mixed on one context.  k > 1 needs
+ * table_slots <= 2^31 (candidate lists hold 32-bit slot ids), else
+ * CDFCI_ERR_UNSUPPORTED.  Enqueued on the context's stream; returns after
+ * completion.  out may be NULL. */
 int cdfci_step(cdfci_ctx* ctx, int k, int64_t nsteps, cdfci_stats* out);
 
 /* Like cdfci_step and also records the energy alpha/mu after every iteration
@@ -233,8 +235,11 @@ int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates
  * sums), every multicoordinate step records HIP events on the context's
  * stream between its phases, and cdfci_mc_phase_times returns the summed
  * device seconds of [0] selection (begin, radix passes, gather), [1] H_II,
- * [2] the reduced eigenproblem, [3] the column scatter, [4] finish and
- * rescale (5 doubles), and in *steps (may be NULL) the steps timed. */
+ * [2] the launch of the reduced eigenproblem, whose other workgroups run the
+ * probe half of the column scatter, [3] the apply half of the scatter, [4]
+ * finish and rescale, and [5] the probe half alone (from its first
+ * workgroup's start to its last one's end, device wall clock) (6 doubles),
+ * and in *steps (may be NULL) the steps timed. */
 int cdfci_set_timing(cdfci_ctx* ctx, int on);
 int cdfci_mc_phase_times(cdfci_ctx* ctx, double* seconds, int64_t* steps);
 

@@ -1156,8 +1156,11 @@ struct cdfci_ctx {
   // per-phase device time of multicoordinate steps (cdfci_set_timing)
   int timing = 0;
   std::vector<hipEvent_t> tev;
-  double t_phase_mc[5] = {0, 0, 0, 0, 0};  // select, H_II, reduced problem + probe half, apply half, finish
+  // select, H_II, reduced problem with the probe half, apply half, finish; probe half alone
+  double t_phase_mc[6] = {0, 0, 0, 0, 0, 0};
   int64_t n_timed = 0;
+  unsigned long long* ptime = nullptr;  // probe-half timestamps, 2 per timed step
+  int64_t ptime_cap = 0;
   double* hii = nullptr;
   double* lan = nullptr;
   double* chat = nullptr;       // c_hat of the chosen set after a step
@@ -1765,6 +1768,7 @@ static int enter_single(cdfci_ctx* c) {
 static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats* out) {
   if (c->poisoned) return CDFCI_ERR_INVALID_ARG;
   if (k > kMaxK || nsteps < 0) return CDFCI_ERR_INVALID_ARG;
+  if (c->nslots > (1ull << 31)) return CDFCI_ERR_UNSUPPORTED;  // slot ids are 32-bit below an all-ones mark
   Ctl before;
   int rc = ctl_read(c, &before);
   if (rc) return rc;
@@ -1782,7 +1786,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   const int chunks = (int)((c->n_col + kPage - 1) / kPage);
   EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, c->chat, k,
              c->opts.dx_damping, c->opts.dx_threshold, dE,
-             ProbeArgs{H, c->mask, c->sel_a, c->sel_b, c->cand, c->pstat, c->rec, c->n_col}};
+             ProbeArgs{H, c->mask, c->sel_a, c->sel_b, c->cand, c->pstat, c->rec, c->n_col}, nullptr};
   ApplyArgs aa{H,      c->T,    c->mask,  c->sel_a, c->sel_b,           c->eta, c->mst, c->pstat,
                c->rec, c->cand, c->n_col, c->opts.z_threshold, k};
   const unsigned page0 = (unsigned)(k * chunks);
@@ -1796,9 +1800,19 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   auto mark = [&](int64_t step, int q) {
     return c->timing ? hipEventRecord(c->tev[(size_t)(6 * step + q)], s) : hipSuccess;
   };
+  if (c->timing && nsteps > 0) {
+    if (c->ptime_cap < nsteps) {
+      if (c->ptime) (void)hipFree(c->ptime);
+      c->ptime = nullptr;
+      HIP_TRY(hipMalloc(&c->ptime, (size_t)2 * nsteps * sizeof(unsigned long long)));
+      c->ptime_cap = nsteps;
+    }
+    k_ptime_init<<<(unsigned)std::min<int64_t>((nsteps + 255) / 256, 1024), 256, 0, s>>>(c->ptime, nsteps);
+  }
   HIP_TRY(hipEventRecord(c->ev0, s));
   for (int64_t step = 0; step < nsteps; ++step) {
     HIP_TRY(mark(step, 0));
+    ea.ptime = c->timing ? c->ptime + 2 * step : nullptr;
     k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
     for (int pass = 0; pass < kRadixPasses; ++pass)
       k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, SelBufs{c->gkey, c->dslot, c->dcount}, c->ctl,
@@ -1835,15 +1849,23 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const int64_t done = h.steps - before.steps;
-  if (c->timing)
+  if (c->timing && nsteps > 0) {
+    std::vector<unsigned long long> pt((size_t)2 * nsteps);
+    HIP_TRY(hipMemcpy(pt.data(), c->ptime, pt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     for (int64_t step = 0; step < nsteps; ++step) {
       for (int q = 0; q < 5; ++q) {
         float t = 0.0f;
         HIP_TRY(hipEventElapsedTime(&t, c->tev[(size_t)(6 * step + q)], c->tev[(size_t)(6 * step + q + 1)]));
         c->t_phase_mc[q] += 1e-3 * t;
       }
+      const unsigned long long t0 = pt[(size_t)(2 * step)], t1 = pt[(size_t)(2 * step + 1)];
+      if (t0 != ~0ull && t1 > t0 && khz > 0) c->t_phase_mc[5] += (double)(t1 - t0) / (1e3 * khz);
       ++c->n_timed;
     }
+  }
   if (trE) {
     if (done > 0) HIP_TRY(hipMemcpy(trE, dE + before.steps, done * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < done; ++i) trE[i] += c->shift;
@@ -2389,7 +2411,7 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->parts) (void)hipFree(c->parts);
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
-  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->dslot, c->dcount, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
+  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->dslot, c->dcount, c->ptime, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
                 c->eta, c->pstat, c->hii, c->lan, c->bitmap, c->chat, c->rec};
   for (void* p : mc)
     if (p) (void)hipFree(p);
@@ -3155,7 +3177,7 @@ int cdfci_set_timing(cdfci_ctx* c, int on) {
 
 int cdfci_mc_phase_times(cdfci_ctx* c, double* seconds, int64_t* steps) {
   if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
-  for (int q = 0; q < 5; ++q) seconds[q] = c->t_phase_mc[q];
+  for (int q = 0; q < 6; ++q) seconds[q] = c->t_phase_mc[q];
   if (steps) *steps = c->n_timed;
   return 0;
 }

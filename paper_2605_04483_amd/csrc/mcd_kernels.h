@@ -743,6 +743,7 @@ struct EigArgs {
   double theta, dx_tol;
   double* tr_E;  // optional per-step energy trace
   ProbeArgs P;   // the probe half, run by the other workgroups
+  unsigned long long* ptime;  // optional: [0] first start, [1] last end of the probe half (wall clock)
 };
 
 // The reduced matrix A (order n = m + off, off = 1 when the c~ column exists):
@@ -880,6 +881,7 @@ __device__ void mc_probe_phase(const EigArgs& A) {
     A.st->n_dense = 0;
   }
   if (A.st->skip) return;
+  if (A.ptime && tid == 0) atomicMin(&A.ptime[0], (unsigned long long)wall_clock64());
   const int chunks = (int)((P.n_col + kPage - 1) / kPage);
   const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
   for (int i = tid; i < kSetSlots; i += blockDim.x) s_set[i] = ~0ull;
@@ -951,6 +953,18 @@ __device__ void mc_probe_phase(const EigArgs& A) {
       probes += __shfl_xor(probes, offs);
     }
     if (lane == 0) P.pstat[(size_t)(y * chunks + x) * 4 + qq] = PageStat{recalc, probes, 0u, 0u, 0};
+  }
+  if (A.ptime) {
+    __syncthreads();
+    if (tid == 0) atomicMax(&A.ptime[1], (unsigned long long)wall_clock64());
+  }
+}
+
+// per-step probe-half timestamps: first start (min) and last end (max)
+__global__ void k_ptime_init(unsigned long long* ptime, int64_t nsteps) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps; i += (int64_t)gridDim.x * blockDim.x) {
+    ptime[2 * i] = ~0ull;
+    ptime[2 * i + 1] = 0ull;
   }
 }
 

@@ -46,7 +46,7 @@ BYTES_PER_ELEMENT = 40  # 32-byte slot read + 8-byte b update per column entry
 N36 = (36, 8, 8, 108)
 N36_COLUMN = 71793
 N24_COLUMN = 16471
-SCATTER_COUNTERS = os.path.join(ROOT, "profiles", "k_mc_scatter_abinitio_n36_hbm_counters.md")
+SCATTER_COUNTERS = os.path.join(ROOT, "profiles", "mc_scatter_abinitio_n36_hbm_counters.md")
 CD1_COUNTERS = os.path.join(ROOT, "profiles", "k_cd1_abinitio_n24_hbm_counters.md")
 K_CD1_END = b"// Adds the step count after the persistent kernel"
 

@@ -462,7 +462,7 @@ def main():
     t_probe, t_apply = ph["probe"] / n_timed, ph["apply"] / n_timed
     scatter_avg = t_probe + t_apply
     achieved = BYTES_PER_ELEMENT * per_launch / scatter_avg / 1e9
-    eig_kernel = "k_mc_eig_small" if k <= 64 else ("k_mc_lobpcg<256>" if k <= 256 else "k_mc_lobpcg<1024>")
+    eig_kernel = "k_mc_lobpcg<64, 512>" if k <= 64 else ("k_mc_lobpcg<256, 1024>" if k <= 256 else "k_mc_lobpcg<1024, 1024>")
     per_el = measured_traffic_per_element(SCATTER_COUNTERS, scatter_sources_sha256(), k)
     out = {
         "metric": "H elements/s + CD iters/s to 1e-5 Ha, batched vs plain, 1 MI355X",

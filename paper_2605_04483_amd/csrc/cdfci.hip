@@ -1825,11 +1825,11 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     // workgroup 0 solves the reduced problem; the others run the probe half
     // of the scatter
     if (k <= kEigSmall)
-      k_mc_eig_small<<<kEigGrid, 64 * kEigWaves, 0, s>>>(ea);
+      k_mc_lobpcg<kEigSmall, 512><<<kEigGrid, 512, 0, s>>>(ea);
     else if (k <= 256)
-      k_mc_lobpcg<256><<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_lobpcg<256, 1024><<<kEigGrid, 1024, 0, s>>>(ea);
     else
-      k_mc_lobpcg<kMaxK><<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_lobpcg<kMaxK, 1024><<<kEigGrid, 1024, 0, s>>>(ea);
     HIP_TRY(mark(step, 3));
     k_mc_apply<<<dim3(chunks, k), 256, 0, s>>>(aa);
     HIP_TRY(mark(step, 4));

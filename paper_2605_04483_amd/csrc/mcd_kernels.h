@@ -446,196 +446,6 @@ __global__ void __launch_bounds__(256) k_mc_hii(Ham H, const uint64_t* sel_a, co
     hii[(size_t)i * m + y] = sc_entry(H, sel_a[i], sel_b[i], a, b, L, diag);
 }
 
-// ---------------------------------------------------------------- reduced problem
-
-// Sturm count: eigenvalues of the tridiagonal (a, b) below x, as the number
-// of sign changes of the leading principal minors p_i of T - x I, formed by
-// the three-term recurrence p_i = (a_i - x) p_(i-1) - b_(i-1)^2 p_(i-2) with
-// no division (the minors are rescaled by powers of two to stay in range;
-// an exact zero minor counts as a tiny value of the opposite sign, as the
-// ratio form d_i = p_i / p_(i-1) -> -0 does).
-__device__ __forceinline__ int sturm_count(const double* __restrict__ a, const double* __restrict__ b,
-                                           int n, double x) {
-  int cnt = 0;
-  double p0 = 1.0, p1 = a[0] - x;
-  if (p1 == 0.0) p1 = -1e-300;
-  cnt += p1 < 0.0;
-  // eight terms at a time: their loads are issued together, and eight steps
-  // of the recurrence move a minor by far less than the 2^400 margin
-  for (int i0 = 1; i0 < n; i0 += 8) {
-    double av[8], bv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = min(i0 + u, n - 1);
-      av[u] = a[i];
-      bv[u] = b[i - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (i0 + u < n) {
-        double p2 = (av[u] - x) * p1 - (bv[u] * bv[u]) * p0;
-        if (p2 == 0.0) p2 = p1 < 0.0 ? 1e-300 : -1e-300;
-        cnt += (p2 < 0.0) != (p1 < 0.0);
-        p0 = p1;
-        p1 = p2;
-      }
-    }
-    const double mg = fabs(p1);
-    if (mg > 0x1p+400 || mg < 0x1p-400) {
-      const int e = ilogb(mg);
-      p0 = ldexp(p0, -e);
-      p1 = ldexp(p1, -e);
-    }
-  }
-  return cnt;
-}
-
-// Eigenvector of the symmetric tridiagonal (a, b) for the eigenvalue
-// estimate lam, by one thread: inverse iteration on (T - lam I), two sweeps
-// from the all-ones vector (lam is accurate to a few ulps, so one sweep
-// already converges; the second is a margin).  scale bounds |T|.  Each loop
-// loads the next row's shared-memory operands one iteration ahead, so the
-// dependent chain runs register to register; the row interchanges are
-// selects, not branches.  y is normalised on return.
-__device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__ a, const double* __restrict__ b,
-                                                     int n, double lam, double scale, double* __restrict__ y,
-                                                     double* __restrict__ wk) {
-  // Gaussian elimination with partial pivoting of T - lam I (one extra
-  // superdiagonal of fill-in), the row being eliminated carried in
-  // registers; stored as multipliers dl, reciprocal pivots rdm,
-  // superdiagonals du, du2 and the interchange flags sw (1.0 = swapped).
-  double* dl = wk;
-  double* rdm = wk + n;
-  double* du = wk + 2 * n;
-  double* du2 = wk + 3 * n;
-  double* sw = wk + 4 * n;
-  const double tiny = 1e-300 + 1e-15 * scale;
-  const int nb = n - 1;  // entries of b
-  double dm_c = a[0] - lam, du_c = b[0];
-  double q_b = b[0], q_a = a[1], q_bn = b[min(1, nb - 1)];
-  for (int i = 0; i < nb; ++i) {
-    const double dl_i = q_b, a_nx = q_a - lam, du_nx = i + 1 < nb ? q_bn : 0.0;
-    const int j = min(i + 1, nb - 1);
-    q_b = b[j];
-    q_a = a[j + 1];
-    q_bn = b[min(j + 1, nb - 1)];
-    const bool swp = fabs(dm_c) < fabs(dl_i);
-    const double pv = swp ? dl_i : (dm_c == 0.0 ? tiny : dm_c);
-    const double r = 1.0 / pv;
-    const double f = (swp ? dm_c : dl_i) * r;
-    const double du_s = swp ? a_nx : du_c;
-    dl[i] = f;
-    rdm[i] = r;
-    du[i] = du_s;
-    du2[i] = swp ? du_nx : 0.0;
-    sw[i] = swp ? 1.0 : 0.0;
-    dm_c = (swp ? du_c : a_nx) - f * du_s;
-    du_c = swp ? -f * du_nx : du_nx;
-  }
-  if (dm_c == 0.0) dm_c = tiny;
-  rdm[n - 1] = 1.0 / dm_c;
-  double inv = 1.0;  // scale of the right-hand side (the previous sweep's norm)
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    // L solve with the row interchanges: y <- L^-1 P (inv * rhs), rhs = ones
-    // on the first sweep and the previous solution on the second
-    double cur = sweep ? inv * y[0] : 1.0;
-    double q_f = dl[0], q_s = sw[0], q_n = sweep ? y[1] : 1.0;
-    for (int i = 0; i < nb; ++i) {
-      const double fv = q_f, nx = inv * q_n;
-      const bool swp = q_s != 0.0;
-      const int j = min(i + 1, nb - 1);
-      q_f = dl[j];
-      q_s = sw[j];
-      q_n = sweep ? y[j + 1] : 1.0;
-      y[i] = swp ? nx : cur;
-      cur = swp ? cur - fv * nx : nx - fv * cur;
-    }
-    // U solve, the squared norm alongside
-    double y2 = cur * rdm[n - 1];
-    y[n - 1] = y2;
-    double nrm = y2 * y2;
-    double y1 = (y[n - 2] - du[n - 2] * y2) * rdm[n - 2];
-    y[n - 2] = y1;
-    nrm += y1 * y1;
-    if (n >= 3) {
-      double q_y = y[n - 3], q_u = du[n - 3], q_u2 = du2[n - 3], q_r = rdm[n - 3];
-      for (int i = n - 3; i >= 0; --i) {
-        const double yv = q_y, uv = q_u, u2v = q_u2, rv = q_r;
-        const int j = max(i - 1, 0);
-        q_y = y[j];
-        q_u = du[j];
-        q_u2 = du2[j];
-        q_r = rdm[j];
-        const double yi = (yv - uv * y1 - u2v * y2) * rv;
-        y[i] = yi;
-        nrm += yi * yi;
-        y2 = y1;
-        y1 = yi;
-      }
-    }
-    inv = 1.0 / sqrt(nrm);
-  }
-  double q_y = y[0];
-  for (int i = 0; i < n; ++i) {
-    const double yv = q_y;
-    q_y = y[min(i + 1, n - 1)];
-    y[i] = inv * yv;
-  }
-}
-
-// Lowest eigenpair of the symmetric tridiagonal (a[0..n), b[0..n-1)) by the
-// whole workgroup: multisection with one point per thread (blockDim + 1
-// subintervals per round, the first point above the eigenvalue found from
-// the waves' ballots), then inverse iteration by thread 0.  Every thread
-// gets the eigenvalue; y (n doubles) is complete when it returns.
-__device__ __forceinline__ double tri_lowest_wg(const double* __restrict__ a, const double* __restrict__ b, int n,
-                                                double* __restrict__ y, double* __restrict__ wk,
-                                                unsigned long long* s_bal) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  const int npts = blockDim.x;
-  if (n == 1) {
-    if (tid == 0) y[0] = 1.0;
-    __syncthreads();
-    return a[0];
-  }
-  double lo = a[0], hi = a[0];
-  for (int i = 0; i < n; ++i) {
-    double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < n - 1 ? fabs(b[i]) : 0.0);
-    lo = fmin(lo, a[i] - r);
-    hi = fmax(hi, a[i] + r);
-  }
-  const double scale = fmax(fabs(lo), fabs(hi));
-  const double inv_seg = 1.0 / (double)(npts + 1);
-  for (int round = 0; round < 16 && hi - lo > 2e-16 * scale; ++round) {
-    const double x = lo + (hi - lo) * ((double)(tid + 1) * inv_seg);
-    const bool below = sturm_count(a, b, n, x) >= 1;  // lowest eigenvalue < x
-    const unsigned long long bal = __ballot(below);
-    if (lane == 0) s_bal[w] = bal;
-    __syncthreads();
-    // first point above the eigenvalue: one read per lane, then the first
-    // wave with a set bit (dependent shared-memory reads cost ~60 cycles each)
-    const unsigned long long mine = lane < nw ? s_bal[lane] : 0ull;
-    const unsigned long long nz = __ballot(mine != 0ull);
-    int f = npts;
-    if (nz) {
-      const int q = __ffsll(nz) - 1;
-      const unsigned long long bq = ((unsigned long long)__builtin_amdgcn_readlane((int)(mine >> 32), q) << 32) |
-                                    (unsigned)__builtin_amdgcn_readlane((int)(unsigned)mine, q);
-      f = q * 64 + __ffsll(bq) - 1;
-    }
-    __syncthreads();
-    const double nhi = f < npts ? lo + (hi - lo) * ((double)(f + 1) * inv_seg) : hi;
-    const double nlo = f > 0 ? lo + (hi - lo) * ((double)f * inv_seg) : lo;
-    if (nlo == lo && nhi == hi) break;  // the points no longer split the interval
-    lo = nlo;
-    hi = nhi;
-  }
-  const double lam = 0.5 * (lo + hi);
-  if (tid == 0) tri_inverse_iteration(a, b, n, lam, scale, y, wk);
-  __syncthreads();
-  return lam;
-}
-
 // ---------------------------------------------------------------- scatter, probe half
 
 // Per quarter of a scatter page (a page is one chosen column x one chunk of
@@ -729,6 +539,8 @@ __device__ inline void make_lists_group(uint64_t a, uint64_t b, int N, Lists& L,
   }
 }
 
+// ---------------------------------------------------------------- reduced problem
+
 struct EigArgs {
   const Slot* T;
   Slot* Tw;
@@ -817,23 +629,6 @@ __device__ void mc_matvec(const double* __restrict__ hii, int m, int off, double
     }
     if (lane == 0) s_y[0] = a00 * s_x[0] + p;
   }
-}
-
-// h[i] = V_i . w for i = 0..j: wave q forms the dot products i = q, q + 16,
-// ... over the whole vector (fixed order), so up to 16 run side by side.
-// w is read from shared memory.
-__device__ void mc_multidot(const double* V, int n, int j, const double* s_w, double* s_h) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wv; i <= j; i += nw) {
-    double p = 0.0;
-    for (int r = lane; r < n; r += 64) p += V[(size_t)i * n + r] * s_w[r];
-    for (int off = 32; off > 0; off >>= 1) {
-      double o = __shfl_xor(p, off);
-      p = (lane & off) ? (o + p) : (p + o);
-    }
-    if (lane == 0) s_h[i] = p;
-  }
-  __syncthreads();
 }
 
 // Membership of a slot in the chosen set, through an open-addressing set of
@@ -1087,8 +882,10 @@ __device__ inline double sym3_lowest(const double* g_in, const int* use, double*
   return a[best][best];
 }
 
-// The reduced problem for k > 64 by LOBPCG (locally optimal block
-// preconditioned conjugate gradient, one vector): from x = [nu; c_I] / |.|,
+// The reduced problem by LOBPCG (locally optimal block preconditioned
+// conjugate gradient, one vector), one workgroup of NT threads (512 for
+// k <= 64, 1024 above): from x = [nu; c_I] / |.| with a fixed pseudo-random
+// first search direction,
 // each iteration takes the Rayleigh-Ritz minimum of A over span{x, w, p}
 // with w = D^-1 (A x - theta x) the residual preconditioned by the diagonal
 // D = diag(A) - theta and p the previous step; p and then w are
@@ -1101,12 +898,20 @@ __device__ inline double sym3_lowest(const double* g_in, const int* use, double*
 // product per iteration; everything else is a handful of workgroup sums.
 constexpr int kLobpcgMax = 300;
 constexpr double kLobpcgTol = 1e-9;
+// a fixed value in [-1/2, 1/2) per row (splitmix64 of the row index)
+__device__ __forceinline__ double lobpcg_kick(int r) {
+  uint64_t z = (uint64_t)r * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1p-53 - 0.5;
+}
 
-template <int KM>
-__global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
+template <int KM, int NT>
+__global__ void __launch_bounds__(NT) k_mc_lobpcg(EigArgs A) {
   __shared__ double s_c[KM], s_b[KM], s_a0[KM], s_d[KM + 1];
   __shared__ double s_x[KM + 1], s_w[KM + 1], s_p[KM + 1], s_ax[KM + 1], s_aw[KM + 1], s_ap[KM + 1];
-  __shared__ double s_part[1024];
+  __shared__ double s_part[NT];
   __shared__ double s_red[16 * 8];
   __shared__ double s_g[9], s_y[3];
   __shared__ int s_use[3];
@@ -1151,7 +956,14 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
     if (tid == 0) ctl->stopped = 1;
     return;
   }
-  // x = [nu; c_I] normalised, Ax, theta
+  bool have_kick = false;
+  // x = [nu; c_I] normalised, and p = a fixed pseudo-random vector
+  // orthonormalised against it.  The current point alone can lie in an
+  // invariant subspace of A (with n_alpha = n_beta a chosen set closed under
+  // the spin flip keeps A's flip parity), from which the iteration would never
+  // reach a lowest eigenvector outside it; p gives every eigenvector weight
+  // in the first Rayleigh-Ritz space, which also holds x, so theta never
+  // exceeds the current point's Rayleigh quotient.
   {
     double v[1] = {0.0};
     for (int r = tid; r < n; r += blockDim.x) {
@@ -1161,12 +973,24 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
     }
     wg_sums<1>(v, s_red);
     const double nrm = sqrt(v[0]);
-    for (int r = tid; r < n; r += blockDim.x) s_x[r] = nrm > 0.0 ? s_x[r] / nrm : (r == 0 ? 1.0 : 0.0);
+    double q[2] = {0.0, 0.0};
     for (int r = tid; r < n; r += blockDim.x) {
-      s_p[r] = 0.0;
-      s_ap[r] = 0.0;
+      const double xr = nrm > 0.0 ? s_x[r] / nrm : (r == 0 ? 1.0 : 0.0);
+      const double kr = lobpcg_kick(r);
+      s_x[r] = xr;
+      s_p[r] = kr;
+      q[0] += xr * kr;
+      q[1] += kr * kr;
     }
+    wg_sums<2>(q, s_red);
+    // p - (x.p) x, normalised (|p'|^2 = |p|^2 - (x.p)^2 as |x| = 1)
+    const double pp = q[1] - q[0] * q[0];
+    const double ip = pp > 1e-28 ? 1.0 / sqrt(pp) : 0.0;
+    for (int r = tid; r < n; r += blockDim.x) s_p[r] = (s_p[r] - q[0] * s_x[r]) * ip;
+    have_kick = pp > 1e-28;
   }
+  __syncthreads();
+  mc_matvec(hii, m, off, a00, s_a0, s_p, s_ap, s_part);
   __syncthreads();
   mc_matvec(hii, m, off, a00, s_a0, s_x, s_ax, s_part);
   __syncthreads();
@@ -1177,7 +1001,7 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
     wg_sums<1>(v, s_red);
     theta = v[0];
   }
-  bool have_p = false;
+  bool have_p = have_kick;
   int iters = 0;
   for (int it = 0; it < kLobpcgMax; ++it) {
     // residual, its preconditioned form, and x . p (first Gram-Schmidt pass of p)
@@ -1321,286 +1145,8 @@ __global__ void __launch_bounds__(1024) k_mc_lobpcg(EigArgs A) {
   mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
 }
 
-constexpr int kEigSmall = 64;  // m up to this: the eigen step runs from shared memory
+constexpr int kEigSmall = 64;  // k up to this: the eigen launch has 512 threads, above 1024
 constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest run the probe half)
-
-// y = A x with H_II in shared memory, for m <= 64: lane i forms row off + i,
-// the wave's sum forms row 0.
-__device__ __forceinline__ void mc_matvec_wave(const double* sH, int m, int off, double a00,
-                                               const double* s_a0, const double* x, double* y) {
-  const int lane = threadIdx.x;
-  if (lane < m) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = 0;
-    for (; j + 3 < m; j += 4) {
-      a0 += sH[j * m + lane] * x[off + j];
-      a1 += sH[(j + 1) * m + lane] * x[off + j + 1];
-      a2 += sH[(j + 2) * m + lane] * x[off + j + 2];
-      a3 += sH[(j + 3) * m + lane] * x[off + j + 3];
-    }
-    for (; j < m; ++j) a0 += sH[j * m + lane] * x[off + j];
-    double sum = (a0 + a1) + (a2 + a3);
-    if (off) sum += s_a0[lane] * x[0];
-    y[off + lane] = sum;
-  }
-  if (off) {
-    double p = lane < m ? s_a0[lane] * x[1 + lane] : 0.0;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double q = __shfl_xor(p, o);
-      p = (lane & o) ? (q + p) : (p + q);
-    }
-    if (lane == 0) y[0] = a00 * x[0] + p;
-  }
-}
-
-// value of v held by lane l (l wave-uniform), as a scalar broadcast
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// DPP lane move of a double (both halves), lanes outside ROWS read 0
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long u = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xF, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Sum over the 64 lanes of a fully active wave in a fixed order, returned to
-// every lane: within quads (quad_perm 1,0,3,2 and 2,3,0,1), across the two
-// halves of each row of 16 (half mirror, mirror), then row 0 into row 1 and
-// row 2 into row 3 (broadcast of lane 15), rows 0-1 into rows 2-3
-// (broadcast of lane 31); lane 63 then holds the total.
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_move<0xB1, 0xF>(v);
-  v += dpp_move<0x4E, 0xF>(v);
-  v += dpp_move<0x141, 0xF>(v);
-  v += dpp_move<0x140, 0xF>(v);
-  v += dpp_move<0x142, 0xA>(v);
-  v += dpp_move<0x143, 0xC>(v);
-  return lane_value(v, 63);
-}
-
-constexpr int kLdA = kEigSmall + 1;  // leading dimension of the reduced matrix in shared memory
-constexpr int kEigWaves = 8;        // waves of the small eigen kernel
-
-// a - v qc - q vc: the rank-2 update of one element, one expression for the
-// stored matrix and for the next column every wave forms in registers
-__device__ __forceinline__ double rank2_update(double a, double v, double qc, double q, double vc) {
-  return a - v * qc - q * vc;
-}
-
-// Householder reduction of the symmetric n x n matrix sA (column-major,
-// leading dimension kLdA, n <= 65) to tridiagonal form T = Q^T A Q by the W
-// waves of the workgroup.  Step i reflects rows/columns i+1..n-1: lane l of
-// every wave owns row i+1+l of the trailing block (at most 64 rows) and every
-// wave forms the same reflector v from the column it holds in registers;
-// wave w takes the columns w, w+W, ... of the product p = tau A' v (partial
-// sums combined in shared memory, fixed order) and of the symmetric rank-2
-// update A' -= v q^T + q v^T, with the other lanes' values of v and q
-// broadcast through scalar registers.  Every wave also applies the update to
-// its own copy of column i+1 (read before anyone writes it), which is the
-// next step's column: the next reflector is formed before the barrier that
-// publishes the update.  Reflector i goes to sR[64 i ..], its factor to
-// tau[i]; d[0..n) and e[0..n-1) receive T.
-template <int W>
-__device__ void tridiagonalize_wg(double* __restrict__ sA, int n, double* __restrict__ sR,
-                                  double* __restrict__ d, double* __restrict__ e,
-                                  double* __restrict__ tau, double* __restrict__ s_p) {
-  constexpr int U = 64 / W;  // columns per wave at most
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // column 0, rows 1..n-1, lane l holding row 1+l
-  double x = n > 2 && lane < n - 1 ? sA[1 + lane] : 0.0;
-  double d_cur = sA[0];  // diagonal element of the current column
-  for (int i = 0; i + 2 < n; ++i) {
-    const int t = n - 1 - i;  // trailing order
-    const bool act = lane < t;
-    const int r = act ? i + 1 + lane : n - 1;  // rows past the end read a valid row
-    // identical in every wave (same values, same order): every branch below
-    // is uniform over the workgroup
-    const double s2 = wave_sum_dpp(x * x);
-    const double x0 = lane_value(x, 0);
-    const double sigma = s2 - x0 * x0;
-    double v = 0.0, tf = 0.0, alpha = x0;
-    if (sigma > 0.0) {
-      alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
-      v = lane == 0 ? x0 - alpha : x;
-      tf = 1.0 / (s2 - x0 * alpha);  // 2 / (v.v)
-    }
-    __syncthreads();  // the previous step's update is visible
-    double av[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) av[u] = sA[(i + 1 + min(w + u * W, t - 1)) * kLdA + r];
-    const double x1 = sA[(i + 1) * kLdA + r];  // column i+1 before this step's update
-    double pp = 0.0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = w + u * W;
-      const double vc = c < t ? lane_value(v, min(c, t - 1)) : 0.0;
-      pp += av[u] * vc;
-    }
-    s_p[w * 64 + lane] = act ? pp : 0.0;
-    __syncthreads();
-    double p = 0.0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) p += s_p[q * 64 + lane];
-    p *= tf;
-    const double K = 0.5 * tf * wave_sum_dpp(v * p);
-    const double q = p - K * v;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = w + u * W;
-      if (c < t) {
-        const double vc = lane_value(v, c), qc = lane_value(q, c);
-        if (act) sA[(i + 1 + c) * kLdA + r] = rank2_update(av[u], v, qc, q, vc);
-      }
-    }
-    // the next column: rows i+1.. of updated column i+1; row i+1 is its
-    // diagonal element, rows i+2.. move down one lane
-    const double xn = act ? rank2_update(x1, v, lane_value(q, 0), q, lane_value(v, 0)) : 0.0;
-    const double d_next = lane_value(xn, 0);
-    const double xs = __shfl_down(xn, 1);
-    x = lane + 1 < t ? xs : 0.0;
-    if (threadIdx.x == 0) {
-      d[i] = d_cur;
-      e[i] = alpha;
-      tau[i] = tf;
-    }
-    d_cur = d_next;
-    if (w == 0) sR[i * 64 + lane] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (n >= 2) {
-      d[n - 2] = sA[(n - 2) * kLdA + n - 2];
-      e[n - 2] = sA[(n - 2) * kLdA + n - 1];
-    }
-    d[n - 1] = sA[(n - 1) * kLdA + n - 1];
-  }
-  __syncthreads();
-}
-
-// The eigen step for m <= 64 (same mathematics as k_mc_lobpcg) in one
-// workgroup of kEigWaves waves.  H_II, the reduced matrix and the reflectors
-// sit in shared memory; the lowest eigenpair comes from a Householder
-// tridiagonalisation, the tridiagonal solver (multisection + inverse
-// iteration) and the back transformation, so it is exact to rounding with no
-// convergence test.
-__global__ void __launch_bounds__(64 * kEigWaves) k_mc_eig_small(EigArgs A) {
-  constexpr int NV = kEigSmall + 1;
-  __shared__ double sH[kEigSmall * kEigSmall];
-  __shared__ double sA[NV * kLdA];
-  __shared__ double sR[(NV - 2) * 64];
-  __shared__ double s_p[kEigWaves * 64];
-  __shared__ double s_c[NV], s_a0[NV], s_x[NV], s_w[NV];
-  __shared__ double s_red[kEigWaves];
-  __shared__ double s_d[NV], s_e[NV], s_tau[NV], s_y[NV];
-  __shared__ double s_wk[5 * NV];
-  __shared__ unsigned long long s_bal[kEigWaves];
-  if (blockIdx.x > 0) {
-    mc_probe_phase(A);
-    return;
-  }
-  Ctl* ctl = A.ctl;
-  if (A.st->skip) return;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int m = (int)min(A.st->n_sel, (unsigned long long)min(A.k, kEigSmall));
-  const double s = A.st->scale;
-  const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
-  double ci = 0.0, bi = 0.0;
-  if (tid < m) {
-    const Slot sl = A.T[A.sel_slot[tid]];
-    ci = s * sl.c;
-    bi = s * sl.b;
-    s_c[tid] = ci;
-  }
-  {
-    // H_II into shared memory, every thread's loads in flight together
-    constexpr int kPer = kEigSmall * kEigSmall / (64 * kEigWaves);
-    const int mm = m * m;
-    double hv[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int q = tid + u * 64 * kEigWaves;
-      hv[u] = q < mm ? A.hii[q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int q = tid + u * 64 * kEigWaves;
-      if (q < mm) sH[q] = hv[u];
-    }
-  }
-  __syncthreads();
-  // hc = H_II c_I (rows by wave 0)
-  mc_matvec_wave(sH, m, 0, 0.0, s_a0, s_c, s_w);
-  __syncthreads();
-  const double hc_i = tid < m ? s_w[tid] : 0.0;
-  const dd cc = wg_sum_dd(two_prod(ci, ci), s_red);
-  const dd cb = wg_sum_dd(two_prod(ci, bi), s_red);
-  const dd chc = wg_sum_dd(two_prod(ci, hc_i), s_red);
-  const dd nu2 = dd_add(mu, dd{-cc.hi, -cc.lo});
-  const dd num = dd_add(dd_add(al, dd{-2.0 * cb.hi, -2.0 * cb.lo}), chc);
-  const double nu2v = dd_val(nu2);
-  const int off = nu2v > kNu2Floor * dd_val(mu) ? 1 : 0;
-  const double nu = off ? sqrt(nu2v) : 0.0;
-  const double a00 = off ? dd_val(num) / nu2v : 0.0;
-  const int n = m + off;
-  if (n == 0) {
-    if (tid == 0) ctl->stopped = 1;
-    return;
-  }
-  // the reduced matrix [[a00, a0^T], [a0, H_II]] (or H_II alone): wave w
-  // fills columns w, w + W, ...; row 64 (n = 65) by lane 0
-  if (tid < m) s_a0[tid] = off ? (bi - hc_i) / nu : 0.0;
-  __syncthreads();
-  for (int c = tid >> 6; c < n; c += kEigWaves) {
-    const int cj = c - off;
-    for (int r = lane; r < n; r += 64) {
-      const int ri = r - off;
-      sA[c * kLdA + r] = ri < 0 ? (cj < 0 ? a00 : s_a0[cj]) : (cj < 0 ? s_a0[ri] : sH[cj * m + ri]);
-    }
-  }
-  __syncthreads();
-  tridiagonalize_wg<kEigWaves>(sA, n, sR, s_d, s_e, s_tau, s_p);
-  const double lam = tri_lowest_wg(s_d, s_e, n, s_y, s_wk, s_bal);
-  if (tid < 64) {
-    // x = Q y, applying H_(n-3) first; lane l holds row l, every lane also
-    // carries row 64 (present when n = 65)
-    double xl = lane < n ? s_y[lane] : 0.0;
-    double x64 = n > 64 ? s_y[64] : 0.0;
-    for (int i = n - 3; i >= 0; --i) {
-      const bool act = lane >= i + 1 && lane < n;
-      const double v = act ? sR[i * 64 + lane - i - 1] : 0.0;
-      const double v64 = n > 64 ? sR[i * 64 + 63 - i] : 0.0;
-      const double f = s_tau[i] * (wave_sum_dpp(v * xl) + v64 * x64);
-      xl -= f * v;
-      x64 -= f * v64;
-    }
-    // z = sqrt(-lambda) x
-    const double zscale = lam < 0.0 ? sqrt(-lam) : 0.0;
-    if (lane < n) s_x[lane] = zscale * xl;
-    if (lane == 0 && n > 64) s_x[64] = zscale * x64;
-  }
-  __syncthreads();
-  double zc_part = 0.0;
-  if (!off && tid < m) zc_part = s_x[tid] * s_c[tid];
-  const double zc = wg_sum(zc_part, s_red);
-  const double sgn = off ? (s_x[0] < 0.0 ? -1.0 : 1.0) : (zc < 0.0 ? -1.0 : 1.0);
-  const double gamma = off ? sgn * s_x[0] / nu : 1.0;
-  double eta_i = 0.0;
-  if (tid < m) eta_i = sgn * s_x[off + tid] - gamma * ci;
-  __syncthreads();
-  if (tid < m) s_x[tid] = eta_i;
-  __syncthreads();
-  mc_matvec_wave(sH, m, 0, 0.0, s_a0, s_x, s_w);
-  __syncthreads();
-  const double heta_i = tid < m ? s_w[tid] : 0.0;
-  mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, n, s_red);
-}
 
 // ---------------------------------------------------------------- scatter, apply half
 

@@ -1162,7 +1162,6 @@ struct cdfci_ctx {
   unsigned long long* ptime = nullptr;  // probe-half timestamps, 2 per timed step
   int64_t ptime_cap = 0;
   double* hii = nullptr;
-  double* lan = nullptr;
   double* chat = nullptr;       // c_hat of the chosen set after a step
   ScatRec* rec = nullptr;       // probe-half records, one per column entry of each chosen column
   unsigned* bitmap = nullptr;   // one bit per slot, clear between selections (bm_words words)
@@ -1697,7 +1696,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
   const uint64_t need_cand = pages * kPage;
   if (k > c->mc_kcap || need_cand > c->cand_cap) {
     // release and reallocate at the larger size
-    void* olds[] = {c->cand, c->cnt, c->gkey, c->dslot, c->hii, c->lan, c->sel_slot, c->sel_a, c->sel_b,
+    void* olds[] = {c->cand, c->cnt, c->gkey, c->dslot, c->hii, c->sel_slot, c->sel_a, c->sel_b,
                     c->eta, c->pstat, c->chat, c->rec};
     for (void* p : olds)
       if (p) (void)hipFree(p);
@@ -1708,7 +1707,6 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     HIP_TRY(hipMalloc(&c->gkey, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&c->dslot, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->hii, (size_t)kc * kc * sizeof(double)));
-    HIP_TRY(hipMalloc(&c->lan, (size_t)(kLanczosMax + 1) * (kc + 1) * sizeof(double)));
     HIP_TRY(hipMalloc(&c->sel_slot, (size_t)kc * sizeof(int64_t)));
     HIP_TRY(hipMalloc(&c->sel_a, (size_t)kc * sizeof(uint64_t)));
     HIP_TRY(hipMalloc(&c->sel_b, (size_t)kc * sizeof(uint64_t)));
@@ -1784,7 +1782,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   hipStream_t s = c->stream;
   const Ham H = ham_of(c);
   const int chunks = (int)((c->n_col + kPage - 1) / kPage);
-  EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->lan, c->eta, c->chat, k,
+  EigArgs ea{c->T, c->T, c->sel_slot, c->hii, c->mst, c->ctl, c->eta, c->chat, k,
              c->opts.dx_damping, c->opts.dx_threshold, dE,
              ProbeArgs{H, c->mask, c->sel_a, c->sel_b, c->cand, c->pstat, c->rec, c->n_col}, nullptr};
   ApplyArgs aa{H,      c->T,    c->mask,  c->sel_a, c->sel_b,           c->eta, c->mst, c->pstat,
@@ -2412,7 +2410,7 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
   void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->dslot, c->dcount, c->ptime, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
-                c->eta, c->pstat, c->hii, c->lan, c->bitmap, c->chat, c->rec};
+                c->eta, c->pstat, c->hii, c->bitmap, c->chat, c->rec};
   for (void* p : mc)
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -37,7 +37,7 @@ struct McState {
   double scale;                      // s in c = s * c_hat
   double inv_scale;                  // 1 / s after this step's update
   double gamma;
-  int lanczos_iters;
+  int eig_iters;                     // iterations of the last reduced problem
   int rescale;
   int skip;  // this step does nothing (an error is pending or the run stopped)
   unsigned arrive;                   // workgroups done with the current selection kernel
@@ -56,7 +56,6 @@ constexpr int kRadixBits = 11;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 6;  // digits at bits 53, 42, 31, 20, 9 (11 wide) and 0 (9 wide)
 constexpr int kMaxTies = 4096;
-constexpr int kLanczosMax = 64;
 constexpr int kSelBlocks = 1024;  // workgroups of the selection launches
 // nu^2 = ||c - E_I c_I||^2 is formed as mu - c_I.c_I.  mu is carried from
 // step to step while the stored c is rounded at every update, so the two
@@ -548,7 +547,6 @@ struct EigArgs {
   const double* hii;  // m x m, symmetric
   McState* st;
   Ctl* ctl;
-  double* lan;  // (kLanczosMax + 1) * (k + 1) scratch
   double* eta_out;
   double* chat_out;  // c_hat of the chosen determinants after the step
   int k;
@@ -804,7 +802,7 @@ __device__ void mc_step_finish(const EigArgs& A, int m, double s, dd mu, dd al, 
     A.st->scale = s_new;
     A.st->inv_scale = 1.0 / s_new;
     A.st->gamma = gamma;
-    A.st->lanczos_iters = iters;
+    A.st->eig_iters = iters;
     // doubles reach 2^1023: fold the scale into the table long before that
     A.st->rescale = fabs(log2(fabs(s_new))) > 400.0 ? 1 : 0;
     if (!(fabs(s_new) > 1e-250) || !(E == E)) ctl->error |= kErrNumeric;

@@ -155,6 +155,7 @@ def headline(api, synth_inputs, args):
         api.cdfci_step(ctx, k, args.iters)
     torch.cuda.synchronize()
     api.cdfci_set_timing(ctx, True)
+    sel0 = api.cdfci_mc_select_stats(ctx)
     steps = elements = probes = atomics = inserts = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -167,13 +168,14 @@ def headline(api, synth_inputs, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     phases = api.cdfci_mc_phase_times(ctx)
+    sel1 = api.cdfci_mc_select_stats(ctx)
     api.cdfci_set_timing(ctx, False)
     e_exact = api.cdfci_energy(ctx, exact=1)
     ctx.close()
     return {"k": k, "tune_rates_Ha_per_s": rates, "tune_seconds": t_tune, "wall": wall, "steps": steps,
             "elements": elements, "probes": probes, "atomics": atomics, "inserts": inserts,
             "energy": st["energy"], "energy_exact": e_exact, "occupied": st["occupied"],
-            "phases": phases}
+            "phases": phases, "select": {q: sel1[q] - sel0[q] for q in sel1}}
 
 
 def to_target(api, synth_inputs, args):
@@ -499,6 +501,9 @@ def main():
                      "whole_step_GBs": BYTES_PER_ELEMENT * H["elements"] / wall / 1e9},
         "phases_ms_per_step": {q: 1e3 * ph[q] / n_timed
                                for q in ("select", "hii", "eigen_probe", "apply", "finish", "probe")},
+        "selection": {"positions_per_step": H["select"]["positions"] / max(1, H["select"]["selections"]),
+                      "exactly_ranked_per_step": H["select"]["kept"] / max(1, H["select"]["selections"]),
+                      "full_rankings": H["select"]["fallbacks"], "selections": H["select"]["selections"]},
         "hash": {"probes": H["probes"], "fp64_atomics": H["atomics"], "inserts": H["inserts"],
                  "probes_per_entry": H["probes"] / max(1, H["elements"]),
                  "probes_per_s_in_probe_half": H["probes"] / max(1e-12, ph["probe"]),

@@ -243,6 +243,16 @@ int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates
 int cdfci_set_timing(cdfci_ctx* ctx, int on);
 int cdfci_mc_phase_times(cdfci_ctx* ctx, double* seconds, int64_t* steps);
 
+/* Measurement aid: running totals of the multicoordinate selections since
+ * the context's multicoordinate state was created (4 int64, host): [0]
+ * selections, [1] candidate positions holding a slot (a determinant reached
+ * from several chosen columns counted once per column), [2] distinct slots
+ * ranked exactly (those whose key is at least the bound the repeats allow),
+ * [3] selections that had to rank every candidate exactly.  Reads device
+ * state (synchronises the context's stream).  CDFCI_ERR_INVALID_ARG before
+ * the first k > 1 step. */
+int cdfci_mc_select_stats(cdfci_ctx* ctx, int64_t* counts);
+
 /* Restart (Sec. 4.1.3: checkpoints for termination and restart from stored
  * wavefunctions).  Replaces the context's state by the wavefunction
  * c = sum_i cv[i] e_{key i}: keys 2*count uint64 (alpha, beta) and cv count

@@ -152,6 +152,7 @@ SIGNATURES = [
     ("cdfci_random_access_rates", ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, _DP]),
     ("cdfci_set_timing", ctypes.c_int, [_P, ctypes.c_int]),
     ("cdfci_mc_phase_times", ctypes.c_int, [_P, _DP, _I64P]),
+    ("cdfci_mc_select_stats", ctypes.c_int, [_P, _I64P]),
     ("cdfci_mc_candidates", ctypes.c_int, [_P, _UP, _DP, _DP, _DP, ctypes.c_int64, _I64P, _DP]),
     ("cdfci_mc_selection", ctypes.c_int, [_P, _UP, _DP, ctypes.c_int64, _I64P]),
     ("cdfci_set_threshold", ctypes.c_int, [_P, ctypes.c_double]),

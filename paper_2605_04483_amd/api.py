@@ -330,6 +330,14 @@ def cdfci_mc_phase_times(ctx):
             "steps": n.value}
 
 
+def cdfci_mc_select_stats(ctx):
+    """Running totals of the multicoordinate selections (see include/cdfci.h)."""
+    v = np.zeros(4, np.int64)
+    _check(_lib.load().cdfci_mc_select_stats(ctx.handle, v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+           "cdfci_mc_select_stats")
+    return {"selections": int(v[0]), "positions": int(v[1]), "kept": int(v[2]), "fallbacks": int(v[3])}
+
+
 def cdfci_load(ctx, keys_alpha, keys_beta, c):
     """Restart from a stored wavefunction (keys and c as cdfci_export returns)."""
     ka = np.asarray(keys_alpha, dtype=np.uint64)

@@ -1142,11 +1142,12 @@ struct cdfci_ctx {
   McState* mst = nullptr;
   unsigned* cand = nullptr;  // candidate pages (kPage slot ids each)
   unsigned* cnt = nullptr;   // entries used per page
+  unsigned long long* pkey = nullptr;  // selection key of every candidate position (cand_cap)
   unsigned long long* gkey = nullptr;  // dense selection keys (cand_cap + one grid of slack)
   unsigned* dslot = nullptr;           // dense selection slots
   unsigned* dcount = nullptr;          // dense region lengths (kSelBlocks)
+  unsigned* ties = nullptr;            // keys equal to the threshold (grid gather, kMaxTies)
   unsigned* hist = nullptr;
-  unsigned* ties = nullptr;
   int64_t* sel_slot = nullptr;
   uint64_t* sel_a = nullptr;
   uint64_t* sel_b = nullptr;
@@ -1519,8 +1520,9 @@ int select_support(cdfci_ctx* c, int64_t top_n, CallBufs& bufs, int64_t** sel, i
   HIP_TRY(bufs.alloc(&sb, n));
   for (int pass = 0; pass < kRadixPasses; ++pass)
     k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, cand, cnt, SelBufs{gkey, dslot, dcount}, c->ctl, st, hist, pass, 1,
-                                          (int)n, nullptr, 0);
-  k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, SelBufs{gkey, dslot, dcount}, st, *sel, ties, sa, sb, (int)n);
+                                          (int)n);
+  k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, SelBufs{gkey, dslot, dcount}, st, *sel, ties, sa, sb, (int)n,
+                                              nullptr);
   HIP_TRY(hipGetLastError());
   unsigned long long got = 0;
   HIP_TRY(hipMemcpyAsync(&got, &st->n_sel, sizeof(got), hipMemcpyDeviceToHost, s));
@@ -1696,7 +1698,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
   const uint64_t need_cand = pages * kPage;
   if (k > c->mc_kcap || need_cand > c->cand_cap) {
     // release and reallocate at the larger size
-    void* olds[] = {c->cand, c->cnt, c->gkey, c->dslot, c->hii, c->sel_slot, c->sel_a, c->sel_b,
+    void* olds[] = {c->cand, c->cnt, c->pkey, c->gkey, c->dslot, c->hii, c->sel_slot, c->sel_a, c->sel_b,
                     c->eta, c->pstat, c->chat, c->rec};
     for (void* p : olds)
       if (p) (void)hipFree(p);
@@ -1704,6 +1706,7 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     const uint64_t cc = std::max(need_cand + need_cand / 4, c->cand_cap);
     HIP_TRY(hipMalloc(&c->cand, cc * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->cnt, (cc / kPage) * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->pkey, cc * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&c->gkey, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&c->dslot, (cc + (uint64_t)kSelBlocks * kPage) * sizeof(unsigned)));
     HIP_TRY(hipMalloc(&c->hii, (size_t)kc * kc * sizeof(double)));
@@ -1725,11 +1728,13 @@ static int mc_alloc(cdfci_ctx* c, int k, uint64_t occupied, bool* lost) {
     memset(&z, 0, sizeof(z));
     z.scale = 1.0;
     z.inv_scale = 1.0;
+    z.pred_d = -1;
     HIP_TRY(hipMemcpyAsync(c->mst, &z, sizeof(z), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMalloc(&c->hist, kRadixBins * sizeof(unsigned)));
-    HIP_TRY(hipMemsetAsync(c->hist, 0, kRadixBins * sizeof(unsigned), c->stream));
-    HIP_TRY(hipMalloc(&c->ties, kMaxTies * sizeof(unsigned)));
+    // two histograms: the selection's, and the second digits of k_mc_keys
+    HIP_TRY(hipMalloc(&c->hist, 2 * kRadixBins * sizeof(unsigned)));
+    HIP_TRY(hipMemsetAsync(c->hist, 0, 2 * kRadixBins * sizeof(unsigned), c->stream));
     HIP_TRY(hipMalloc(&c->dcount, kSelBlocks * sizeof(unsigned)));
+    HIP_TRY(hipMalloc(&c->ties, kMaxTies * sizeof(unsigned)));
     c->bm_words = (c->nslots / 32 + 1 + 3) & ~3ull;  // whole 16-byte vectors
     HIP_TRY(hipMalloc(&c->bitmap, c->bm_words * sizeof(unsigned)));
   }
@@ -1811,12 +1816,27 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   for (int64_t step = 0; step < nsteps; ++step) {
     HIP_TRY(mark(step, 0));
     ea.ptime = c->timing ? c->ptime + 2 * step : nullptr;
-    k_mc_begin<<<1, 1, 0, s>>>(c->mst, c->ctl);
-    for (int pass = 0; pass < kRadixPasses; ++pass)
-      k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, SelBufs{c->gkey, c->dslot, c->dcount}, c->ctl,
-                                            c->mst, c->hist, pass, 0, k, c->bitmap, c->bm_words);
-    k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, SelBufs{c->gkey, c->dslot, c->dcount}, c->mst, c->sel_slot,
-                                                c->ties, c->sel_a, c->sel_b, k);
+    // keys of every position, the bound the repeats allow, the exact pass
+    // (repeats dropped) over the keys above it, and the rest of the
+    // selection: one workgroup for k <= kTailMaxK, else the digit of pass 0
+    // in one workgroup and grid passes
+    const SelBufs sb{c->gkey, c->dslot, c->dcount};
+    k_mc_keys<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->pkey, c->ctl, c->mst, c->hist,
+                                         c->hist + kRadixBins);
+    k_mc_bound<<<1, 256, 0, s>>>(c->mst, c->ctl, c->hist, c->hist + kRadixBins, k);
+    k_mc_dedup<<<kSelBlocks, 256, 0, s>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 0);
+    k_mc_dedup<<<kSelBlocks, 256, 0, s>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 1);
+    if (k <= kTailMaxK) {
+      k_mc_tail<<<1, kTailThreads, 0, s>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
+                                           c->bitmap, 1);
+    } else {
+      k_mc_tail<<<1, kTailThreads, 0, s>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
+                                           c->bitmap, 0);
+      for (int pass = 1; pass < kRadixPasses; ++pass)
+        k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, sb, c->ctl, c->mst, c->hist, pass, 0, k);
+      k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, sb, c->mst, c->sel_slot, c->ties, c->sel_a, c->sel_b, k,
+                                                  c->bitmap);
+    }
     HIP_TRY(mark(step, 1));
     k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k, c->cnt, c->n_col);
     HIP_TRY(mark(step, 2));
@@ -1838,7 +1858,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     HIP_TRY(mark(step, 5));
     if (((step + 1) & 63) == 0) HIP_TRY(hipGetLastError());
   }
-  k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);  // inside the loop k_mc_begin does this
+  k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);  // inside the loop k_mc_bound does this
   HIP_TRY(hipEventRecord(c->ev1, s));
   HIP_TRY(hipGetLastError());
   Ctl h;
@@ -2409,7 +2429,7 @@ int cdfci_free(cdfci_ctx* c) {
   if (c->parts) (void)hipFree(c->parts);
   if (c->list) (void)hipFree(c->list);
   if (c->dscratch) (void)hipFree(c->dscratch);
-  void* mc[] = {c->mst, c->cand, c->cnt, c->gkey, c->dslot, c->dcount, c->ptime, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
+  void* mc[] = {c->mst, c->cand, c->cnt, c->pkey, c->gkey, c->dslot, c->dcount, c->ptime, c->hist, c->ties, c->sel_slot, c->sel_a, c->sel_b,
                 c->eta, c->pstat, c->hii, c->bitmap, c->chat, c->rec};
   for (void* p : mc)
     if (p) (void)hipFree(p);
@@ -3177,6 +3197,18 @@ int cdfci_mc_phase_times(cdfci_ctx* c, double* seconds, int64_t* steps) {
   if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
   for (int q = 0; q < 6; ++q) seconds[q] = c->t_phase_mc[q];
   if (steps) *steps = c->n_timed;
+  return 0;
+}
+
+int cdfci_mc_select_stats(cdfci_ctx* c, int64_t* counts) {
+  if (!c || !counts || !c->mst) return CDFCI_ERR_INVALID_ARG;
+  McState st;
+  HIP_TRY(hipMemcpyAsync(&st, c->mst, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  counts[0] = (int64_t)st.acc_sel;
+  counts[1] = (int64_t)st.acc_pos;
+  counts[2] = (int64_t)st.acc_kept;
+  counts[3] = (int64_t)st.acc_fallback;
   return 0;
 }
 

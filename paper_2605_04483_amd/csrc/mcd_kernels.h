@@ -43,13 +43,19 @@ struct McState {
   unsigned arrive;                   // workgroups done with the current selection kernel
   unsigned long long n_total;        // candidates of the coming selection
   unsigned long long last_sel;       // size of the last completed step's chosen set
+  unsigned long long lowkey;         // keys >= lowkey take the exact (de-duplicating) pass
+  int need_low;                      // the keys below lowkey are needed too
+  int pred_d;                        // top digit of the last step's boundary (-1: none)
+  // running totals of the selections (inspection): selections, candidate
+  // positions holding a slot, slots kept by the exact pass, second passes
+  unsigned long long acc_sel, acc_pos, acc_kept, acc_fallback;
 };
 
 constexpr int kPage = 256;
 // A candidate position that holds no slot (the entry is absent, zero, or in
-// the chosen set), and the selection key of a position the selection ignores
-// (no slot, or a slot already seen at an earlier position); a key of a real
-// candidate is the bit pattern of a non-negative double, so bit 63 is free.
+// the chosen set), and the selection key of a position that holds none; a key
+// of a real candidate is the bit pattern of a non-negative double, so bit 63
+// is free.
 constexpr unsigned kNoCand = 0xffffffffu;
 constexpr unsigned long long kKeyExcluded = 1ull << 63;
 constexpr int kRadixBits = 11;
@@ -70,30 +76,15 @@ __device__ __forceinline__ unsigned long long radix_digit_mask(int pass) {
   return pass < 5 ? 0x7FFull : 0x1FFull;
 }
 
-__device__ __forceinline__ unsigned long long g_key(const Slot& s, double mu) {
-  double g = fabs(4.0 * s.b + 4.0 * mu * s.c);
+__device__ __forceinline__ unsigned long long g_key_cb(double c, double b, double mu) {
+  double g = fabs(4.0 * b + 4.0 * mu * c);
   return (unsigned long long)__double_as_longlong(g);
 }
+__device__ __forceinline__ unsigned long long g_key(const Slot& s, double mu) { return g_key_cb(s.c, s.b, mu); }
 
 // |c| as an ordered key (selection of the largest coefficients)
 __device__ __forceinline__ unsigned long long c_key(const Slot& s) {
   return (unsigned long long)__double_as_longlong(fabs(s.c));
-}
-
-// start of a step: finish the previous step's scale fold (its k_mc_rescale
-// has completed), reset the selection's counters, then skip the step if an
-// error is pending or the stopping rule fired
-__global__ void k_mc_begin(McState* st, const Ctl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (st->rescale) {
-      st->scale = 1.0;
-      st->inv_scale = 1.0;
-      st->rescale = 0;
-    }
-    st->arrive = 0;
-    st->n_total = 0;
-    st->skip = (ctl->error || ctl->stopped) ? 1 : 0;
-  }
 }
 
 // all occupied slots become candidates (entering the multicoordinate mode):
@@ -120,7 +111,7 @@ __global__ void __launch_bounds__(256) k_mc_dense_pages(unsigned* cnt, McState* 
 }
 
 // clear the candidate bitmap and the gather counters (entering the
-// multicoordinate state; inside a step the selection's passes clear the bitmap)
+// multicoordinate state; inside a step k_mc_tail clears the words it used)
 __global__ void __launch_bounds__(256) k_mc_clear(unsigned* bitmap, uint64_t nwords, McState* st) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -269,27 +260,16 @@ __device__ __forceinline__ unsigned long long sel_region(unsigned long long n) {
 
 // One radix-select pass over the step's candidates; pass 0 also computes the
 // keys (|g|, or |c| when by_c is set), counts the candidates and compacts
-// them into the dense lists.  The last workgroup to finish chooses the digit.
-// With a bitmap (one bit per slot, clear on entry) pass 0 keeps only the first
-// position of each slot (a determinant reached from several columns) and
-// passes 1..5 clear a fifth of the bitmap each for the next selection (these
-// passes wait on latency, not bandwidth); without one the positions are taken
-// as distinct.
+// them into the dense lists, taking every position as a distinct candidate
+// (the selection of the largest |c| of the reverse pass).  The last
+// workgroup to finish chooses the digit.
 __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned* cand, const unsigned* cnt,
                                                   SelBufs D, const Ctl* ctl, McState* st, unsigned* hist,
-                                                  int pass, int by_c, int k, unsigned* bitmap, uint64_t nwords) {
+                                                  int pass, int by_c, int k) {
   __shared__ unsigned h[kRadixBins];
   __shared__ unsigned s_wn[4];
   __shared__ unsigned s_run;
   if (st->skip) return;
-  if (bitmap && pass > 0) {
-    const uint64_t nvec = nwords / 4;  // nwords is a multiple of 4
-    const uint64_t lo = nvec * (pass - 1) / (kRadixPasses - 1), hi = nvec * pass / (kRadixPasses - 1);
-    uint4* v = reinterpret_cast<uint4*>(bitmap);
-    for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
-         i += (uint64_t)gridDim.x * blockDim.x)
-      v[i] = make_uint4(0u, 0u, 0u, 0u);
-  }
   if (pass > 0 && (st->all || st->done)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
@@ -311,10 +291,6 @@ __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned*
       if (i < n && (i & (kPage - 1)) < cnt[i / kPage]) {
         sl = cand[i];
         keep = sl != kNoCand;
-        if (keep && bitmap) {
-          const unsigned bit = 1u << (sl & 31);
-          keep = !(atomicOr(&bitmap[sl >> 5], bit) & bit);
-        }
         if (keep) {
           key = by_c ? c_key(T[sl]) : g_key(T[sl], mu);
           atomicAdd(&h[(key >> sh) & dm], 1u);
@@ -352,13 +328,483 @@ __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned*
   if (last_workgroup(&st->arrive)) mc_scan_last(hist, st, k, pass);
 }
 
+// ---------------------------------------------------------------- keys first, then the exact pass near the top
+//
+// A slot reached from several chosen columns sits at several positions of the
+// candidate list with one key, and Alg. 2 ranks it once.  Dropping the repeats
+// costs a returning atomic per position, so it is done only where the ranking
+// is decided.  A column holds a determinant at most once, so a slot sits at
+// most last_sel + 1 times in the list (once per previous column and once in
+// the chosen set's own page; once when the list was built from the table):
+// the R = k (last_sel + 1) largest position keys hold at least k distinct
+// slots.  k_mc_keys forms every position's key (one random read of the
+// slot's c and b), counts the positions per top digit, repeats included, and
+// finds the digit d holding the R-th largest.  The bin of one top digit spans
+// two binades and can hold most of the positions, so k_mc_keys also counts
+// the positions of the previous step's boundary digit per second digit: when
+// the boundary stays in that bin (the usual case) the second digit holding
+// the R-th largest narrows the bound to 2^-10 of a binade.  The bound is the
+// key lowkey (d, or d and the second digit, followed by zeros); k_mc_dedup
+// keeps the first position of each slot among the keys >= lowkey, counting
+// them exactly, and the ranking of the lower keys is not needed (every slot
+// above them is kept).  Should fewer than k distinct slots be found there all
+// the same, a second k_mc_dedup covers the keys below.
+
+// The last workgroup (256 threads) of a histogram launch: the digit holding
+// the need-th largest key of a 2048-bin histogram (counted from the top), or
+// -1 when it holds fewer keys; *above = the keys in the bins above it and
+// *total = all of its keys.  Thread t reads bins 8t..8t+7 with agent-scope
+// loads.
+__device__ int digit_of_rank(const unsigned* hist, long long need, unsigned long long* above,
+                             unsigned long long* total) {
+  __shared__ unsigned long long s_wt[4];
+  __shared__ unsigned long long s_above;
+  __shared__ int s_d;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned hv[8];
+  unsigned long long run = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    hv[u] = __hip_atomic_load(&hist[tid * 8 + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    run += hv[u];
+  }
+  unsigned long long x = run;  // inclusive suffix over the wave's lanes
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_down(x, o);
+    if (lane + o < 64) x += y;
+  }
+  if (lane == 0) s_wt[w] = x;
+  if (tid == 0) s_d = -1;
+  __syncthreads();
+  unsigned long long acc = x - run;
+  for (int q = w + 1; q < 4; ++q) acc += s_wt[q];
+  for (int u = 7; u >= 0; --u) {
+    if ((long long)acc < need && (long long)(acc + hv[u]) >= need) {
+      s_d = tid * 8 + u;
+      s_above = acc;
+    }
+    acc += hv[u];
+  }
+  __syncthreads();
+  *above = s_d >= 0 ? s_above : 0ull;
+  *total = s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+  return s_d;
+}
+
+// The first kernel of a step: nothing runs when an error is pending or the
+// stopping rule fired (k_mc_bound records the same test as st->skip for the
+// rest of the step).
+__device__ __forceinline__ bool step_off(const Ctl* ctl) { return ctl->error || ctl->stopped; }
+
+// pkey[i] = the key of the slot at candidate position i (kKeyExcluded where
+// there is none); hist counts every position per top digit and hist2 the
+// positions of top digit pred_d per second digit.  Each thread takes four
+// positions a round so that four slot reads are in flight.  The keys are
+// formed from the stored c^, b^ (the lazy scale multiplies every key alike).
+__global__ void __launch_bounds__(256) k_mc_keys(const Slot* T, const unsigned* cand, const unsigned* cnt,
+                                                 unsigned long long* pkey, const Ctl* ctl, const McState* st,
+                                                 unsigned* hist, unsigned* hist2) {
+  constexpr int U = 4;
+  __shared__ unsigned h[kRadixBins], h2[kRadixBins];
+  if (step_off(ctl)) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kRadixBins; i += blockDim.x) {
+    h[i] = 0u;
+    h2[i] = 0u;
+  }
+  const unsigned long long pd = (unsigned long long)st->pred_d;  // all ones when there is none
+  __syncthreads();
+  const unsigned long long n = st->n_pages * kPage;
+  const double mu = ctl->mu_hi + ctl->mu_lo;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x * U;
+  for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x * U + tid; i0 < n; i0 += stride) {
+    unsigned sl[U];
+    double2 cb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned long long i = i0 + (unsigned long long)u * blockDim.x;
+      sl[u] = (i < n && (i & (kPage - 1)) < cnt[i / kPage]) ? cand[i] : kNoCand;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      cb[u] = sl[u] != kNoCand ? *reinterpret_cast<const double2*>(&T[sl[u]].c) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned long long i = i0 + (unsigned long long)u * blockDim.x;
+      if (i >= n) continue;
+      unsigned long long key = kKeyExcluded;
+      if (sl[u] != kNoCand) {
+        key = g_key_cb(cb[u].x, cb[u].y, mu);
+        const unsigned long long d = key >> radix_shift(0);
+        atomicAdd(&h[d], 1u);
+        if (d == pd) atomicAdd(&h2[(key >> radix_shift(1)) & radix_digit_mask(1)], 1u);
+      }
+      pkey[i] = key;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < kRadixBins; i += blockDim.x) {
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+    if (h2[i]) atomicAdd(&hist2[i], h2[i]);
+  }
+}
+
+// One workgroup of 256 threads after k_mc_keys: the start of the step (the
+// previous step's scale fold has completed; counters reset; st->skip), then
+// lowkey (0 when there are at most R positions) and pred_d from the two
+// histograms, which it clears.
+__global__ void __launch_bounds__(256) k_mc_bound(McState* st, const Ctl* ctl, unsigned* hist, unsigned* hist2,
+                                                  int k) {
+  const int tid = threadIdx.x;
+  const bool off = step_off(ctl);
+  if (tid == 0) {
+    if (st->rescale) {
+      st->scale = 1.0;
+      st->inv_scale = 1.0;
+      st->rescale = 0;
+    }
+    st->arrive = 0;
+    st->n_total = 0;
+    st->need_low = 0;
+    st->skip = off ? 1 : 0;
+  }
+  if (off) return;  // k_mc_keys did not run: the histograms are clear
+  const long long rank = (long long)k * (long long)(st->last_sel + 1);  // last_sel <= 1024
+  const unsigned long long pd = (unsigned long long)st->pred_d;
+  unsigned long long above = 0, total = 0;
+  const int d = digit_of_rank(hist, rank, &above, &total);  // -1: at most rank positions in all
+  int d2 = -1;
+  if (d >= 0 && (unsigned long long)d == pd) {  // uniform: d and pd are the same in every thread
+    unsigned long long above2 = 0, total2 = 0;
+    d2 = digit_of_rank(hist2, rank - (long long)above, &above2, &total2);
+  }
+  if (tid == 0) {
+    st->acc_pos += total;
+    unsigned long long lk = 0ull;
+    if (d >= 0) lk = (unsigned long long)d << radix_shift(0);
+    if (d2 >= 0) lk |= (unsigned long long)d2 << radix_shift(1);
+    st->lowkey = lk;
+    if (d >= 0) st->pred_d = d;
+  }
+  for (int i = tid; i < kRadixBins; i += blockDim.x) {
+    hist[i] = 0u;
+    hist2[i] = 0u;
+  }
+}
+
+// The exact pass over the positions whose key is >= lowkey (second = 0) or,
+// when the first launch found fewer than k distinct slots there, < lowkey
+// (second = 1; otherwise it returns at once).  A position is kept when its
+// bit in the bitmap was clear, i.e. it is the first position of its slot to
+// arrive; kept keys and slots go to the workgroup's dense region (the second
+// launch appends; D.count holds the lengths) and are counted in the
+// histogram of top digits (radix pass 0 of k_mc_tail); the first launch also
+// counts them in n_total, which the second reads.  Within a region the order
+// of the kept entries depends on the timing of the waves; nothing downstream
+// depends on it (the histograms count, the gather ranks ties by key).
+__global__ void __launch_bounds__(256) k_mc_dedup(const unsigned* cand, const unsigned long long* pkey, SelBufs D,
+                                                  McState* st, unsigned* hist, unsigned* bitmap, int k,
+                                                  int second) {
+  constexpr int U = 8;  // position keys a thread reads at once
+  __shared__ unsigned h[kRadixBins];
+  __shared__ unsigned s_run;
+  if (st->skip) return;
+  const int tid = threadIdx.x;
+  const unsigned long long lowkey = st->lowkey;
+  if (second) {  // n_total is the first launch's count (the second adds nothing to it)
+    if (!(st->n_total < (unsigned long long)k && lowkey > 0ull)) return;
+    if (blockIdx.x == 0 && tid == 0) st->need_low = 1;
+  }
+  for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
+  const unsigned start = second ? D.count[blockIdx.x] : 0u;
+  if (tid == 0) s_run = start;
+  __syncthreads();
+  const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long base = blockIdx.x * sel_region(n);
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  // the workgroup visits the positions of a grid-stride loop (the dense
+  // region's size assumes it), U strides at a time; the few kept entries
+  // take places in the region through a shared counter
+  for (unsigned long long i0 = (unsigned long long)blockIdx.x * blockDim.x + tid; i0 < n; i0 += stride * U) {
+    unsigned long long key[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned long long i = i0 + (unsigned long long)u * stride;
+      key[u] = i < n ? pkey[i] : kKeyExcluded;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (key[u] == kKeyExcluded || (key[u] >= lowkey) == (second != 0)) continue;
+      const unsigned sl = cand[i0 + (unsigned long long)u * stride];
+      const unsigned bit = 1u << (sl & 31);
+      if (atomicOr(&bitmap[sl >> 5], bit) & bit) continue;  // an earlier position holds the slot
+      atomicAdd(&h[key[u] >> radix_shift(0)], 1u);
+      const unsigned at = atomicAdd(&s_run, 1u);
+      D.key[base + at] = key[u];
+      D.slot[base + at] = sl;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < kRadixBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+  if (tid == 0) {
+    D.count[blockIdx.x] = s_run;
+    if (!second && s_run > start) atomicAdd(&st->n_total, (unsigned long long)(s_run - start));
+  }
+}
+
+// The rest of the selection in one workgroup (kTailThreads threads; thread t
+// reads the dense region of dedup workgroup t): the radix passes over the
+// kept keys, pass 0 from the histogram the exact pass filled (which it
+// clears); the chosen set (keys above the threshold, or every kept key when
+// there are at most k); the keys equal to the threshold ranked by
+// determinant key when only some of them are taken; the chosen set's keys;
+// and the bitmap words of the kept slots cleared for the next selection
+// (every set bit belongs to a kept slot).  With full = 0 it only chooses the
+// digit of pass 0 and leaves the state of the radix select in McState for
+// the grid passes 1..5 (k_mc_radix) and the grid gather (k_mc_gather_ties),
+// which serve large k: one workgroup's histogram atomics then crowd into a
+// few bins.
+constexpr int kTailThreads = 1024;
+static_assert(kTailThreads == kSelBlocks, "one dense region per tail thread");
+
+// Block-wide: the digit whose bin (of nb, in LDS) holds the need-th largest
+// key, the keys in the bins above it, and its count; every thread gets them.
+__device__ void tail_find(const unsigned* h, int nb, long long need, int* d_out,
+                          unsigned long long* above_out, unsigned* hd_out) {
+  __shared__ unsigned long long s_wt[kTailThreads / 64];
+  __shared__ unsigned long long s_above;
+  __shared__ unsigned s_hd;
+  __shared__ int s_d;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int per = (nb + blockDim.x - 1) / blockDim.x;  // 2 (11-bit digits) or 1 (the last, 9-bit digit)
+  unsigned hv[2] = {0u, 0u};
+  unsigned long long run = 0;
+  for (int u = 0; u < per; ++u) {
+    const int b = tid * per + u;
+    hv[u] = b < nb ? h[b] : 0u;
+    run += hv[u];
+  }
+  unsigned long long x = run;  // inclusive suffix over the wave's lanes
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_down(x, o);
+    if (lane + o < 64) x += y;
+  }
+  if (lane == 0) s_wt[w] = x;
+  if (tid == 0) s_d = -1;
+  __syncthreads();
+  unsigned long long acc = x - run;
+  for (int q = w + 1; q < nw; ++q) acc += s_wt[q];
+  for (int u = per - 1; u >= 0; --u) {
+    if ((long long)acc < need && (long long)(acc + hv[u]) >= need) {
+      s_d = tid * per + u;
+      s_above = acc;
+      s_hd = hv[u];
+    }
+    acc += hv[u];
+  }
+  __syncthreads();
+  *d_out = s_d;
+  *above_out = s_above;
+  *hd_out = s_hd;
+  __syncthreads();
+}
+
+// Entries of the thread's dense region, eight loads in flight.
+template <class F>
+__device__ __forceinline__ void tail_sweep(const SelBufs& D, unsigned long long base, unsigned cnt, F&& f) {
+  for (unsigned j0 = 0; j0 < cnt; j0 += 8) {
+    unsigned long long kk[8];
+    unsigned ss[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      kk[u] = j0 + u < cnt ? D.key[base + j0 + u] : 0ull;
+      ss[u] = j0 + u < cnt ? D.slot[base + j0 + u] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < cnt) f(kk[u], ss[u]);
+  }
+}
+
+constexpr int kTailList = 2048;  // bucket entries the tail keeps in LDS
+constexpr int kTailMaxK = 256;   // larger k: pass 0 in the tail, passes 1..5 and the gather on the grid
+
+__global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs D, McState* st, unsigned* hist,
+                                                          int64_t* sel_slot, uint64_t* sel_a, uint64_t* sel_b,
+                                                          int k, unsigned* bitmap, int full) {
+  __shared__ unsigned h[kRadixBins];
+  __shared__ unsigned s_ties[kMaxTies];
+  __shared__ unsigned long long s_lk[kTailList];
+  __shared__ unsigned s_ls[kTailList];
+  __shared__ int64_t s_sel[1024];  // k <= 1024
+  __shared__ unsigned long long s_red[kTailThreads / 64];
+  __shared__ unsigned s_nsel, s_ntie, s_nl;
+  if (st->skip) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const unsigned long long n = st->n_pages * kPage;
+  const unsigned long long stride = (unsigned long long)kSelBlocks * 256;  // the dedup launches' grid
+  const unsigned long long base = (unsigned long long)tid * ((n + stride - 1) / stride * 256);
+  const unsigned cnt = D.count[tid];
+  // kept entries in all
+  unsigned long long tsum = cnt;
+  for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o);
+  if (lane == 0) s_red[w] = tsum;
+  for (int i = tid; i < kRadixBins; i += blockDim.x) {
+    h[i] = hist[i];
+    hist[i] = 0u;
+  }
+  if (tid == 0) {
+    s_nsel = 0u;
+    s_ntie = 0u;
+    s_nl = 0u;
+  }
+  __syncthreads();
+  unsigned long long total = 0;
+  for (int q = 0; q < nw; ++q) total += s_red[q];
+  const bool all = total <= (unsigned long long)k;
+  bool done = all, cleared = false, inl = false;
+  unsigned long long P = 0, M = 0;
+  long long need = k;
+  unsigned hd = 0;
+  if (!full) {  // pass 0 only; the grid passes go on from McState
+    unsigned long long above = 0;
+    if (!all) {
+      int d;
+      tail_find(h, kRadixBins, need, &d, &above, &hd);
+      P = (unsigned long long)d << radix_shift(0);
+      M = radix_digit_mask(0) << radix_shift(0);
+      need -= (long long)above;
+      done = (long long)hd == need;
+    }
+    if (tid == 0) {
+      st->prefix = P;
+      st->pmask = M;
+      st->n_above = above;
+      st->need = need;
+      st->all = all ? 1 : 0;
+      st->done = done ? 1 : 0;
+      st->n_total = total;
+      st->n_sel = 0;
+      st->n_tie = 0;
+      st->arrive = 0;
+      st->acc_sel += 1;
+      st->acc_kept += total;
+      st->acc_fallback += st->need_low ? 1 : 0;
+    }
+    return;
+  }
+  auto clear_word = [&](unsigned sl) {
+    if (bitmap) bitmap[sl >> 5] = 0u;  // every set bit belongs to a kept slot
+  };
+  // radix select of the k-th largest kept key; once the bucket holding it
+  // fits in LDS, the keys above it join the chosen set and the bucket moves
+  // to LDS, where the remaining passes and the gather run
+  for (int pass = 0; pass < kRadixPasses && !done; ++pass) {
+    const int sh = radix_shift(pass);
+    const unsigned long long dm = radix_digit_mask(pass);
+    if (pass > 0) {
+      if (!inl && hd <= (unsigned)kTailList) {
+        tail_sweep(D, base, cnt, [&](unsigned long long key, unsigned sl) {
+          if (!cleared) clear_word(sl);
+          const unsigned long long km = key & M;
+          if (km > P) {
+            const unsigned q = atomicAdd(&s_nsel, 1u);
+            if (q < (unsigned)k) s_sel[q] = sl;
+          } else if (km == P) {
+            const unsigned t = atomicAdd(&s_nl, 1u);
+            if (t < (unsigned)kTailList) {
+              s_lk[t] = key;
+              s_ls[t] = sl;
+            }
+          }
+        });
+        cleared = true;
+        inl = true;
+      }
+      __syncthreads();
+      for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
+      __syncthreads();
+      if (inl) {
+        for (unsigned t = tid; t < s_nl; t += blockDim.x)
+          if ((s_lk[t] & M) == P) atomicAdd(&h[(s_lk[t] >> sh) & dm], 1u);
+      } else {
+        tail_sweep(D, base, cnt, [&](unsigned long long key, unsigned sl) {
+          if (!cleared) clear_word(sl);
+          if ((key & M) == P) atomicAdd(&h[(key >> sh) & dm], 1u);
+        });
+        cleared = true;
+      }
+      __syncthreads();
+    }
+    int d;
+    unsigned long long above;
+    tail_find(h, (int)dm + 1, need, &d, &above, &hd);
+    P |= (unsigned long long)d << sh;
+    M |= dm << sh;
+    need -= (long long)above;
+    done = (long long)hd == need;
+  }
+  // the rest of the chosen set: keys above the threshold, and the bucket
+  // when all of it is taken; otherwise the keys equal to the threshold are
+  // ties (every key then has all 64 bits fixed)
+  auto gather = [&](unsigned long long key, unsigned sl) {
+    const unsigned long long km = key & M;
+    if (all || km > P || (done && km == P)) {
+      const unsigned q = atomicAdd(&s_nsel, 1u);
+      if (q < (unsigned)k) s_sel[q] = sl;
+    } else if (km == P) {
+      const unsigned t = atomicAdd(&s_ntie, 1u);
+      if (t < (unsigned)kMaxTies) s_ties[t] = sl;
+    }
+  };
+  if (inl) {
+    for (unsigned t = tid; t < s_nl; t += blockDim.x) gather(s_lk[t], s_ls[t]);
+  } else {
+    tail_sweep(D, base, cnt, [&](unsigned long long key, unsigned sl) {
+      if (!cleared) clear_word(sl);
+      gather(key, sl);
+    });
+  }
+  __syncthreads();
+  unsigned nsel = min(s_nsel, (unsigned)k);
+  if (!done) {  // take need of the ties, smallest determinant keys first
+    const int nt = (int)min(s_ntie, (unsigned)kMaxTies);
+    for (int i = tid; i < nt; i += blockDim.x) {
+      const Slot si = T[s_ties[i]];
+      int rank = 0;
+      for (int j = 0; j < nt; ++j) {
+        const Slot sj = T[s_ties[j]];
+        if (key_less(sj.ka, sj.kb, si.ka, si.kb)) ++rank;
+      }
+      if (rank < need && nsel + rank < (unsigned)k) s_sel[nsel + rank] = s_ties[i];
+    }
+    nsel += (unsigned)min((long long)nt, need);
+    __syncthreads();
+  }
+  const int m = (int)min(nsel, (unsigned)k);
+  for (int i = tid; i < m; i += blockDim.x) {
+    const int64_t sl = s_sel[i];
+    sel_slot[i] = sl;
+    const Slot v = T[sl];
+    sel_a[i] = v.ka;
+    sel_b[i] = v.kb;
+  }
+  if (tid == 0) {
+    st->n_sel = (unsigned long long)m;
+    st->acc_sel += 1;
+    st->acc_kept += total;
+    st->acc_fallback += st->need_low ? 1 : 0;
+  }
+}
+
 // Gather: chosen candidates -> sel_slot, keys equal to the threshold ->
 // ties; the last workgroup resolves the ties by key order and fills the keys
 // of the chosen set.  Slots shared between workgroups go through
 // agent-scope atomics (the XCDs' L2 caches are not coherent).
 __global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, SelBufs D, McState* st,
                                                         int64_t* sel_slot, unsigned* ties, uint64_t* sel_a,
-                                                        uint64_t* sel_b, int k) {
+                                                        uint64_t* sel_b, int k, unsigned* bitmap) {
   if (st->skip) return;
   const int tid = threadIdx.x;
   const unsigned long long n = st->n_pages * kPage;
@@ -369,6 +815,7 @@ __global__ void __launch_bounds__(256) k_mc_gather_ties(const Slot* T, SelBufs D
   for (unsigned j = tid; j < nb; j += blockDim.x) {
     const unsigned long long km = D.key[base + j] & M;
     const unsigned sl = D.slot[base + j];
+    if (bitmap) bitmap[sl >> 5] = 0u;  // every set bit belongs to a kept slot
     const bool take = all || km > P || (done && km == P);
     if (take) {
       const unsigned long long q = atomicAdd(&st->n_sel, 1ull);
@@ -886,7 +1333,11 @@ __device__ inline double sym3_lowest(const double* g_in, const int* use, double*
 // first search direction,
 // each iteration takes the Rayleigh-Ritz minimum of A over span{x, w, p}
 // with w = D^-1 (A x - theta x) the residual preconditioned by the diagonal
-// D = diag(A) - theta and p the previous step; p and then w are
+// D = |diag(A) - theta| (floored at 1e-8 (|theta| + 1)) and p the previous
+// step.  D must be positive: LOBPCG needs a positive definite
+// preconditioner, and the signed diag(A) - theta is indefinite once theta
+// has passed a diagonal entry, where the iteration can stall on that
+// coordinate for hundreds of iterations.  p and then w are
 // orthonormalised against the others (Gram-Schmidt twice, the products with
 // A transformed alike) before the 3 x 3 eigenproblem, so the Ritz pair stays
 // accurate to rounding.  Stops at |A x - theta x| <= 1e-9 |theta| or after
@@ -1009,9 +1460,7 @@ __global__ void __launch_bounds__(NT) k_mc_lobpcg(EigArgs A) {
       const double res = s_ax[r] - theta * s_x[r];
       v[0] += res * res;
       v[1] += s_x[r] * s_p[r];
-      double dn = s_d[r] - theta;
-      if (fabs(dn) < dfloor) dn = dn < 0.0 ? -dfloor : dfloor;
-      s_w[r] = res / dn;
+      s_w[r] = res / fmax(fabs(s_d[r] - theta), dfloor);
     }
     wg_sums<2>(v, s_red);
     iters = it;

@@ -1843,7 +1843,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     // workgroup 0 solves the reduced problem; the others run the probe half
     // of the scatter
     if (k <= kEigSmall)
-      k_mc_lobpcg<kEigSmall, 512><<<kEigGrid, 512, 0, s>>>(ea);
+      k_mc_lobpcg<kEigSmall, 512><<<kEigGridSmall, 512, 0, s>>>(ea);
     else if (k <= 256)
       k_mc_lobpcg<256, 1024><<<kEigGrid, 1024, 0, s>>>(ea);
     else

@@ -1357,7 +1357,8 @@ __device__ __forceinline__ double lobpcg_kick(int r) {
 }
 
 template <int KM, int NT>
-__global__ void __launch_bounds__(NT) k_mc_lobpcg(EigArgs A) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 4 : 1)))
+k_mc_lobpcg(EigArgs A) {
   __shared__ double s_c[KM], s_b[KM], s_a0[KM], s_d[KM + 1];
   __shared__ double s_x[KM + 1], s_w[KM + 1], s_p[KM + 1], s_ax[KM + 1], s_aw[KM + 1], s_ap[KM + 1];
   __shared__ double s_part[NT];
@@ -1593,7 +1594,11 @@ __global__ void __launch_bounds__(NT) k_mc_lobpcg(EigArgs A) {
 }
 
 constexpr int kEigSmall = 64;  // k up to this: the eigen launch has 512 threads, above 1024
-constexpr int kEigGrid = 256;   // workgroups of an eigen launch (1 solves, the rest run the probe half)
+// workgroups of an eigen launch (1 solves, the rest run the probe half):
+// two per compute unit for k <= kEigSmall (512 threads, at most 128 VGPRs,
+// so the probe half has 16 waves per compute unit), one above (1024 threads)
+constexpr int kEigGrid = 256;
+constexpr int kEigGridSmall = 512;
 
 // ---------------------------------------------------------------- scatter, apply half
 

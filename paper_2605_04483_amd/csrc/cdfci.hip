@@ -1812,50 +1812,59 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     }
     k_ptime_init<<<(unsigned)std::min<int64_t>((nsteps + 255) / 256, 1024), 256, 0, s>>>(c->ptime, nsteps);
   }
-  HIP_TRY(hipEventRecord(c->ev0, s));
-  for (int64_t step = 0; step < nsteps; ++step) {
-    HIP_TRY(mark(step, 0));
+  // one step's launches on stream q, with the phase events when timing
+  auto launch_step = [&](hipStream_t q, int64_t step) -> hipError_t {
+    hipError_t e = hipSuccess;
+    auto mk = [&](int which) {
+      if (e == hipSuccess) e = mark(step, which);
+    };
+    mk(0);
     ea.ptime = c->timing ? c->ptime + 2 * step : nullptr;
     // keys of every position, the bound the repeats allow, the exact pass
     // (repeats dropped) over the keys above it, and the rest of the
     // selection: one workgroup for k <= kTailMaxK, else the digit of pass 0
     // in one workgroup and grid passes
     const SelBufs sb{c->gkey, c->dslot, c->dcount};
-    k_mc_keys<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, c->pkey, c->ctl, c->mst, c->hist,
+    k_mc_keys<<<kSelBlocks, 256, 0, q>>>(c->T, c->cand, c->cnt, c->pkey, c->ctl, c->mst, c->hist,
                                          c->hist + kRadixBins);
-    k_mc_bound<<<1, 256, 0, s>>>(c->mst, c->ctl, c->hist, c->hist + kRadixBins, k);
-    k_mc_dedup<<<kSelBlocks, 256, 0, s>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 0);
-    k_mc_dedup<<<kSelBlocks, 256, 0, s>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 1);
+    k_mc_bound<<<1, 256, 0, q>>>(c->mst, c->ctl, c->hist, c->hist + kRadixBins, k);
+    k_mc_dedup<<<kSelBlocks, 256, 0, q>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 0);
+    k_mc_dedup<<<kSelBlocks, 256, 0, q>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 1);
     if (k <= kTailMaxK) {
-      k_mc_tail<<<1, kTailThreads, 0, s>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
+      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
                                            c->bitmap, 1);
     } else {
-      k_mc_tail<<<1, kTailThreads, 0, s>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
+      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
                                            c->bitmap, 0);
       for (int pass = 1; pass < kRadixPasses; ++pass)
-        k_mc_radix<<<kSelBlocks, 256, 0, s>>>(c->T, c->cand, c->cnt, sb, c->ctl, c->mst, c->hist, pass, 0, k);
-      k_mc_gather_ties<<<kSelBlocks, 256, 0, s>>>(c->T, sb, c->mst, c->sel_slot, c->ties, c->sel_a, c->sel_b, k,
+        k_mc_radix<<<kSelBlocks, 256, 0, q>>>(c->T, c->cand, c->cnt, sb, c->ctl, c->mst, c->hist, pass, 0, k);
+      k_mc_gather_ties<<<kSelBlocks, 256, 0, q>>>(c->T, sb, c->mst, c->sel_slot, c->ties, c->sel_a, c->sel_b, k,
                                                   c->bitmap);
     }
-    HIP_TRY(mark(step, 1));
-    k_mc_hii<<<k, 256, 0, s>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k, c->cnt, c->n_col);
-    HIP_TRY(mark(step, 2));
+    mk(1);
+    k_mc_hii<<<k, 256, 0, q>>>(H, c->sel_a, c->sel_b, c->mst, c->hii, k, c->cnt, c->n_col);
+    mk(2);
     // workgroup 0 solves the reduced problem; the others run the probe half
     // of the scatter
     if (k <= kEigSmall)
-      k_mc_lobpcg<kEigSmall, 512><<<kEigGridSmall, 512, 0, s>>>(ea);
+      k_mc_lobpcg<kEigSmall, 512><<<kEigGridSmall, 512, 0, q>>>(ea);
     else if (k <= 256)
-      k_mc_lobpcg<256, 1024><<<kEigGrid, 1024, 0, s>>>(ea);
+      k_mc_lobpcg<256, 1024><<<kEigGrid, 1024, 0, q>>>(ea);
     else
-      k_mc_lobpcg<kMaxK, 1024><<<kEigGrid, 1024, 0, s>>>(ea);
-    HIP_TRY(mark(step, 3));
-    k_mc_apply<<<dim3(chunks, k), 256, 0, s>>>(aa);
-    HIP_TRY(mark(step, 4));
-    k_mc_colsum<<<k, 64, 0, s>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k, c->hii, c->chat);
-    k_mc_finish<<<1, 1024, 0, s>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->cand, c->cnt, c->mst,
+      k_mc_lobpcg<kMaxK, 1024><<<kEigGrid, 1024, 0, q>>>(ea);
+    mk(3);
+    k_mc_apply<<<dim3(chunks, k), 256, 0, q>>>(aa);
+    mk(4);
+    k_mc_colsum<<<k, 64, 0, q>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k, c->hii, c->chat);
+    k_mc_finish<<<1, 1024, 0, q>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->cand, c->cnt, c->mst,
                                    c->ctl, c->max_entries, page0, k);
-    k_mc_rescale<<<256, 256, 0, s>>>(c->T, c->nslots, c->mst, 0);
-    HIP_TRY(mark(step, 5));
+    k_mc_rescale<<<256, 256, 0, q>>>(c->T, c->nslots, c->mst, 0);
+    mk(5);
+    return e;
+  };
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  for (int64_t step = 0; step < nsteps; ++step) {
+    HIP_TRY(launch_step(s, step));
     if (((step + 1) & 63) == 0) HIP_TRY(hipGetLastError());
   }
   k_mc_rescale_done<<<1, 1, 0, s>>>(c->mst, 0);  // inside the loop k_mc_bound does this

@@ -135,3 +135,31 @@ def test_mcd_compressed_energy_descends(api):
     assert np.all(np.diff(E) <= 1e-9 * abs(E[0]))
     assert abs(api.cdfci_energy(ctx, exact=1) - st["energy"]) < 1e-7 * abs(st["energy"])
     ctx.close()
+
+
+def test_mcd_multi_step_call_matches_per_step_energies(api):
+    """cdfci_step over several steps and cdfci_step_energies (which also
+    records every step's energy) from the same start (8 orbitals, 4+3,
+    m = 16) agree after 12 steps and again after 12 more at another
+    threshold, to the rounding the order of the atomics leaves; and the first
+    run matches the oracle at step 12."""
+    N, na, nb = 8, 4, 3
+    h, eri = synth_inputs.ab_initio(N, 24, 7)
+    keys, c0 = ocd.init_single(h, eri, na, nb)
+    orc = omc.mcdfci_run(h, eri, keys, c0, 16, max_steps=12)
+    ends = {}
+    for mode in ("multi", "per_step"):
+        ctx = api.cdfci_init(h, eri, na, nb, table_slots=1 << 14)
+        got = []
+        for tau in (0.0, 1e-7):
+            api.cdfci_set_threshold(ctx, tau)
+            if mode == "multi":
+                got.append(api.cdfci_step(ctx, 16, 12)["energy"])
+            else:
+                E, _ = api.cdfci_step_energies(ctx, 16, 12)
+                got.append(E[-1])
+        ends[mode] = got
+        ctx.close()
+    for a, b in zip(ends["multi"], ends["per_step"]):
+        assert abs(a - b) <= 1e-9 * abs(b), (ends["multi"], ends["per_step"])
+    assert abs(ends["multi"][0] - orc.energies[-1]) <= 1e-9 * abs(orc.energies[-1])

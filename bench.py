@@ -508,7 +508,7 @@ def main():
                      "algorithmic_bytes_per_launch": BYTES_PER_ELEMENT * per_launch,
                      "whole_step_GBs": BYTES_PER_ELEMENT * H["elements"] / wall / 1e9},
         "phases_ms_per_step": {q: 1e3 * ph[q] / n_timed
-                               for q in ("select", "hii", "eigen_probe", "apply", "finish", "probe")},
+                               for q in ("select", "hii", "eigen_probe", "apply", "finish", "probe", "solve")},
         "ms_per_step_with_phase_events": 1e3 * H["wall_with_phase_events"] / args.steps,
         "selection": {"positions_per_step": H["select"]["positions"] / max(1, H["select"]["selections"]),
                       "exactly_ranked_per_step": H["select"]["kept"] / max(1, H["select"]["selections"]),

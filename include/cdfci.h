@@ -237,9 +237,10 @@ int cdfci_random_access_rates(uint64_t table_slots, int64_t n_ops, double* rates
  * device seconds of [0] selection (begin, radix passes, gather), [1] H_II,
  * [2] the launch of the reduced eigenproblem, whose other workgroups run the
  * probe half of the column scatter, [3] the apply half of the scatter, [4]
- * finish and rescale, and [5] the probe half alone (from its first
- * workgroup's start to its last one's end, device wall clock) (6 doubles),
- * and in *steps (may be NULL) the steps timed. */
+ * finish and rescale, [5] the probe half alone (from its first
+ * workgroup's start to its last one's end, device wall clock) and [6] the
+ * reduced problem's workgroup alone (device wall clock) (7 doubles), and in
+ * *steps (may be NULL) the steps timed. */
 int cdfci_set_timing(cdfci_ctx* ctx, int on);
 int cdfci_mc_phase_times(cdfci_ctx* ctx, double* seconds, int64_t* steps);
 

@@ -323,11 +323,11 @@ def cdfci_set_timing(ctx, on=True):
 
 def cdfci_mc_phase_times(ctx):
     """Summed device seconds per phase of the timed multicoordinate steps."""
-    t = np.zeros(6)
+    t = np.zeros(7)
     n = ctypes.c_int64(0)
     _check(_lib.load().cdfci_mc_phase_times(ctx.handle, _dp(t), ctypes.byref(n)), "cdfci_mc_phase_times")
     return {"select": t[0], "hii": t[1], "eigen_probe": t[2], "apply": t[3], "finish": t[4], "probe": t[5],
-            "steps": n.value}
+            "solve": t[6], "steps": n.value}
 
 
 def cdfci_mc_select_stats(ctx):

@@ -1158,9 +1158,9 @@ struct cdfci_ctx {
   int timing = 0;
   std::vector<hipEvent_t> tev;
   // select, H_II, reduced problem with the probe half, apply half, finish; probe half alone
-  double t_phase_mc[6] = {0, 0, 0, 0, 0, 0};
+  double t_phase_mc[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t n_timed = 0;
-  unsigned long long* ptime = nullptr;  // probe-half timestamps, 2 per timed step
+  unsigned long long* ptime = nullptr;  // probe-half and solver timestamps, 4 per timed step
   int64_t ptime_cap = 0;
   double* hii = nullptr;
   double* chat = nullptr;       // c_hat of the chosen set after a step
@@ -1807,7 +1807,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     if (c->ptime_cap < nsteps) {
       if (c->ptime) (void)hipFree(c->ptime);
       c->ptime = nullptr;
-      HIP_TRY(hipMalloc(&c->ptime, (size_t)2 * nsteps * sizeof(unsigned long long)));
+      HIP_TRY(hipMalloc(&c->ptime, (size_t)4 * nsteps * sizeof(unsigned long long)));
       c->ptime_cap = nsteps;
     }
     k_ptime_init<<<(unsigned)std::min<int64_t>((nsteps + 255) / 256, 1024), 256, 0, s>>>(c->ptime, nsteps);
@@ -1819,7 +1819,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
       if (e == hipSuccess) e = mark(step, which);
     };
     mk(0);
-    ea.ptime = c->timing ? c->ptime + 2 * step : nullptr;
+    ea.ptime = c->timing ? c->ptime + 4 * step : nullptr;
     // keys of every position, the bound the repeats allow, the exact pass
     // (repeats dropped) over the keys above it, and the rest of the
     // selection: one workgroup for k <= kTailMaxK, else the digit of pass 0
@@ -1877,7 +1877,7 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const int64_t done = h.steps - before.steps;
   if (c->timing && nsteps > 0) {
-    std::vector<unsigned long long> pt((size_t)2 * nsteps);
+    std::vector<unsigned long long> pt((size_t)4 * nsteps);
     HIP_TRY(hipMemcpy(pt.data(), c->ptime, pt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     int dev = 0, khz = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -1888,8 +1888,10 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
         HIP_TRY(hipEventElapsedTime(&t, c->tev[(size_t)(6 * step + q)], c->tev[(size_t)(6 * step + q + 1)]));
         c->t_phase_mc[q] += 1e-3 * t;
       }
-      const unsigned long long t0 = pt[(size_t)(2 * step)], t1 = pt[(size_t)(2 * step + 1)];
+      const unsigned long long t0 = pt[(size_t)(4 * step)], t1 = pt[(size_t)(4 * step + 1)];
       if (t0 != ~0ull && t1 > t0 && khz > 0) c->t_phase_mc[5] += (double)(t1 - t0) / (1e3 * khz);
+      const unsigned long long t2 = pt[(size_t)(4 * step + 2)], t3 = pt[(size_t)(4 * step + 3)];
+      if (t3 > t2 && t2 > 0 && khz > 0) c->t_phase_mc[6] += (double)(t3 - t2) / (1e3 * khz);
       ++c->n_timed;
     }
   }
@@ -3204,7 +3206,7 @@ int cdfci_set_timing(cdfci_ctx* c, int on) {
 
 int cdfci_mc_phase_times(cdfci_ctx* c, double* seconds, int64_t* steps) {
   if (!c || !seconds) return CDFCI_ERR_INVALID_ARG;
-  for (int q = 0; q < 6; ++q) seconds[q] = c->t_phase_mc[q];
+  for (int q = 0; q < 7; ++q) seconds[q] = c->t_phase_mc[q];
   if (steps) *steps = c->n_timed;
   return 0;
 }

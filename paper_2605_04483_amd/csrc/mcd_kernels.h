@@ -1000,7 +1000,9 @@ struct EigArgs {
   double theta, dx_tol;
   double* tr_E;  // optional per-step energy trace
   ProbeArgs P;   // the probe half, run by the other workgroups
-  unsigned long long* ptime;  // optional: [0] first start, [1] last end of the probe half (wall clock)
+  // optional (wall clock): [0] first start, [1] last end of the probe half,
+  // [2] start, [3] end of the reduced problem's workgroup
+  unsigned long long* ptime;
 };
 
 // The reduced matrix A (order n = m + off, off = 1 when the c~ column exists):
@@ -1203,8 +1205,10 @@ __device__ void mc_probe_phase(const EigArgs& A) {
 // per-step probe-half timestamps: first start (min) and last end (max)
 __global__ void k_ptime_init(unsigned long long* ptime, int64_t nsteps) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsteps; i += (int64_t)gridDim.x * blockDim.x) {
-    ptime[2 * i] = ~0ull;
-    ptime[2 * i + 1] = 0ull;
+    ptime[4 * i] = ~0ull;
+    ptime[4 * i + 1] = 0ull;
+    ptime[4 * i + 2] = 0ull;
+    ptime[4 * i + 3] = 0ull;
   }
 }
 
@@ -1372,6 +1376,7 @@ k_mc_lobpcg(EigArgs A) {
   Ctl* ctl = A.ctl;
   if (A.st->skip) return;
   const int tid = threadIdx.x;
+  if (A.ptime && tid == 0) A.ptime[2] = wall_clock64();
   const int m = (int)min(A.st->n_sel, (unsigned long long)A.k);
   const double s = A.st->scale;
   const dd mu{ctl->mu_hi, ctl->mu_lo}, al{ctl->al_hi, ctl->al_lo};
@@ -1591,6 +1596,10 @@ k_mc_lobpcg(EigArgs A) {
   __syncthreads();
   const double heta_i = tid < m ? s_w[tid] : 0.0;
   mc_step_finish(A, m, s, mu, al, gamma, eta_i, ci, bi, heta_i, iters, s_red);
+  if (A.ptime) {
+    __syncthreads();
+    if (tid == 0) A.ptime[3] = wall_clock64();
+  }
 }
 
 constexpr int kEigSmall = 64;  // k up to this: the eigen launch has 512 threads, above 1024

@@ -1855,9 +1855,8 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     mk(3);
     k_mc_apply<<<dim3(chunks, k), 256, 0, q>>>(aa);
     mk(4);
-    k_mc_colsum<<<k, 64, 0, q>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->mst, k, c->hii, c->chat);
-    k_mc_finish<<<1, 1024, 0, q>>>(c->T, c->sel_slot, c->pstat + c->pstat_cap, c->cand, c->cnt, c->mst,
-                                   c->ctl, c->max_entries, page0, k);
+    k_mc_colfinish<<<k, 256, 0, q>>>(c->pstat, chunks, c->pstat + c->pstat_cap, c->hii, c->chat, c->T,
+                                     c->sel_slot, c->cand, c->cnt, c->mst, c->ctl, c->max_entries, page0, k);
     k_mc_rescale<<<256, 256, 0, q>>>(c->T, c->nslots, c->mst, 0);
     mk(5);
     return e;

@@ -49,6 +49,7 @@ struct McState {
   // running totals of the selections (inspection): selections, candidate
   // positions holding a slot, slots kept by the exact pass, second passes
   unsigned long long acc_sel, acc_pos, acc_kept, acc_fallback;
+  unsigned arrive_cols;              // workgroups of k_mc_colfinish done (the last one resets it)
 };
 
 constexpr int kPage = 256;
@@ -1695,87 +1696,113 @@ __global__ void __launch_bounds__(256) k_mc_apply(ApplyArgs A) {
   }
 }
 
-// One wave per chosen column: colstat[i] = its scatter pages summed in a
-// fixed order (the part of the recalculated b_i from entries outside the
-// chosen set, and the column's counts) plus (H_II c_hat_I)_i, the part from
-// the chosen set with its new coefficients.
-__global__ void __launch_bounds__(64) k_mc_colsum(const PageStat* pstat, int chunks, PageStat* colstat,
-                                                  const McState* st, int k, const double* hii,
-                                                  const double* chat) {
-  if (st->skip) return;
-  const int m = (int)min(st->n_sel, (unsigned long long)k);
-  const int i = blockIdx.x;
-  if (i >= m) return;
-  const int lane = threadIdx.x;
-  double r = 0.0, rh = 0.0;
-  unsigned pr = 0, at = 0, in = 0;
-  int er = 0;
-  for (int x = lane; x < 4 * chunks; x += 64) {
-    const PageStat q = pstat[(size_t)i * chunks * 4 + x];
-    r += q.recalc;
-    pr += q.probes;
-    at += q.atomics;
-    in += q.inserts;
-    er |= q.err;
-  }
-  for (int q = lane; q < m; q += 64) rh += hii[(size_t)i * m + q] * chat[q];
-  r += rh;
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(r, off);
-    r = (lane & off) ? (o + r) : (r + o);
-    pr += __shfl_xor(pr, off);
-    at += __shfl_xor(at, off);
-    in += __shfl_xor(in, off);
-    er |= __shfl_xor(er, off);
-  }
-  if (lane == 0) colstat[i] = PageStat{r, pr, at, in, er};
+// The chosen columns' sums and the end of the step in one launch of k
+// workgroups of 256 threads.  Workgroup i < m sums column i's quarter-page
+// partials (the part of the recalculated b_i from entries outside the chosen
+// set, and the column's counts) in a fixed order, adds (H_II c_hat_I)_i, the
+// part from the chosen set with its new coefficients, and stores the result
+// in colstat[i] with agent-scope stores.  The last workgroup to arrive then
+// sets b_hat_I from them, puts I on its own candidate pages after the
+// scatter pages, adds up the scatter's counts and checks the occupancy.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// b_hat_I <- recalculated values (from the column sums); I joins the
-// candidates (own pages after the scatter pages); the scatter's counts;
-// occupancy check
-__global__ void __launch_bounds__(1024) k_mc_finish(Slot* T, const int64_t* sel_slot, const PageStat* colstat,
-                                                    unsigned* cand, unsigned* cnt, McState* st, Ctl* ctl,
-                                                    uint64_t max_entries, unsigned page0, int k) {
-  __shared__ unsigned s_n;
+__global__ void __launch_bounds__(256) k_mc_colfinish(const PageStat* pstat, int chunks, PageStat* colstat,
+                                                      const double* hii, const double* chat, Slot* T,
+                                                      const int64_t* sel_slot, unsigned* cand, unsigned* cnt,
+                                                      McState* st, Ctl* ctl, uint64_t max_entries, unsigned page0,
+                                                      int k) {
+  __shared__ double s_r[4];
+  __shared__ unsigned s_pr[4], s_at[4], s_in[4];
+  __shared__ int s_er[4];
   __shared__ unsigned long long s_cnt[3];
   __shared__ int s_err;
   if (st->skip) return;
   const int m = (int)min(st->n_sel, (unsigned long long)k);
-  if (threadIdx.x == 0) {
-    s_n = 0;
-    s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
-    s_err = 0;
-  }
-  __syncthreads();
-  // the scatter's counts over the chosen columns
-  {
-    unsigned long long pr = 0, at = 0, in = 0;
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (i < m) {
+    double r = 0.0, rh = 0.0;
+    unsigned pr = 0, at = 0, in = 0;
     int er = 0;
-    for (int p = threadIdx.x; p < m; p += blockDim.x) {
-      const PageStat q = colstat[p];
+    for (int x = tid; x < 4 * chunks; x += blockDim.x) {
+      const PageStat q = pstat[(size_t)i * chunks * 4 + x];
+      r += q.recalc;
       pr += q.probes;
       at += q.atomics;
       in += q.inserts;
       er |= q.err;
+    }
+    for (int q = tid; q < m; q += blockDim.x) rh += hii[(size_t)i * m + q] * chat[q];
+    r += rh;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(r, off);
+      r = (lane & off) ? (o + r) : (r + o);
+      pr += __shfl_xor(pr, off);
+      at += __shfl_xor(at, off);
+      in += __shfl_xor(in, off);
+      er |= __shfl_xor(er, off);
+    }
+    if (lane == 0) {
+      s_r[w] = r;
+      s_pr[w] = pr;
+      s_at[w] = at;
+      s_in[w] = in;
+      s_er[w] = er;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      PageStat* o = &colstat[i];
+      st_agent(&o->recalc, (s_r[0] + s_r[1]) + (s_r[2] + s_r[3]));
+      st_agent(&o->probes, s_pr[0] + s_pr[1] + s_pr[2] + s_pr[3]);
+      st_agent(&o->atomics, s_at[0] + s_at[1] + s_at[2] + s_at[3]);
+      st_agent(&o->inserts, s_in[0] + s_in[1] + s_in[2] + s_in[3]);
+      st_agent(reinterpret_cast<unsigned*>(&o->err), (unsigned)(s_er[0] | s_er[1] | s_er[2] | s_er[3]));
+    }
+  }
+  if (!last_workgroup(&st->arrive_cols)) return;
+  if (tid == 0) {
+    s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
+    s_err = 0;
+  }
+  __syncthreads();
+  {
+    unsigned long long pr = 0, at = 0, in = 0;
+    int er = 0;
+    for (int p = tid; p < m; p += blockDim.x) {
+      const PageStat* q = &colstat[p];
+      pr += ld_agent(&q->probes);
+      at += ld_agent(&q->atomics);
+      in += ld_agent(&q->inserts);
+      er |= (int)ld_agent(reinterpret_cast<const unsigned*>(&q->err));
     }
     if (pr) atomicAdd(&s_cnt[0], pr);
     if (at) atomicAdd(&s_cnt[1], at);
     if (in) atomicAdd(&s_cnt[2], in);
     if (er) atomicOr(&s_err, er);
   }
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const int64_t slot = sel_slot[i];
-    T[slot].b = colstat[i].recalc;
-    cand[(size_t)page0 * kPage + i] = (unsigned)slot;  // the scatter pages never hold the chosen set
+  for (int p = tid; p < m; p += blockDim.x) {
+    const int64_t slot = sel_slot[p];
+    T[slot].b = ld_agent(&colstat[p].recalc);
+    cand[(size_t)page0 * kPage + p] = (unsigned)slot;  // the scatter pages never hold the chosen set
   }
-  if (threadIdx.x == 0) s_n = (unsigned)m;
-  __syncthreads();
   const unsigned npg = (unsigned)((k + kPage - 1) / kPage);
-  for (unsigned p = threadIdx.x; p < npg; p += blockDim.x)
-    cnt[page0 + p] = s_n > p * kPage ? min((unsigned)kPage, s_n - p * kPage) : 0u;
+  for (unsigned p = tid; p < npg; p += blockDim.x)
+    cnt[page0 + p] = (unsigned)m > p * kPage ? min((unsigned)kPage, (unsigned)m - p * kPage) : 0u;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
+    st->arrive_cols = 0;
     st->last_sel = (unsigned long long)m;
     st->n_sel = 0;
     st->n_pages = (unsigned long long)page0 + npg;

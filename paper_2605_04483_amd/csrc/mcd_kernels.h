@@ -3,20 +3,20 @@
 //
 // One step is a fixed sequence of launches with no host synchronisation:
 //   select   top-k of |4 b_j + 4 mu c_j| over the step's candidates (the union
-//            of the previous step's columns, deduplicated): MSB radix select
-//            on the bit pattern of the non-negative double |g| (one launch per
-//            digit, the last workgroup choosing the digit), exact ties at the
-//            threshold to the smaller key;
+//            of the previous step's columns, each determinant once): every
+//            candidate position's key, a bound below which fewer than k
+//            distinct determinants cannot lie, repeats dropped above it, then
+//            an MSB radix select on the bit pattern of the non-negative double
+//            |g| (in one workgroup, or grid passes for large k), exact ties at
+//            the threshold to the smaller key;
 //   H_II     pairwise Slater-Condon entries among the chosen determinants;
 //   reduced  A = Q^T H Q with Q = [c~, E_I] (eq. (def-z)); its lowest
-//            eigenpair (k <= 64: Householder tridiagonalisation in shared
-//            memory; larger k: LOBPCG started from the current point
-//            [nu; c_I]); gamma, eta; mu and alpha.  The same launch's other
-//            workgroups run the probe half of the scatter, which needs the
-//            chosen set but not eta: the k columns enumerated, their entries
-//            looked up once, stored entries marked in a slot bitmap and
-//            written to the unit's own candidate page, recalculation sums for
-//            b_I, one record per entry;
+//            eigenpair by LOBPCG started from the current point [nu; c_I];
+//            gamma, eta; mu and alpha.  The same launch's other workgroups
+//            run the probe half of the scatter, which needs the chosen set but
+//            not eta: the k columns enumerated, their entries looked up once,
+//            each entry's slot written at its own candidate position,
+//            recalculation sums for b_I, one record per entry;
 //   apply    b += H_{:,I} eta from the records with the compression rule
 //            (inserting the absent entries whose increment is kept);
 //   finish   b_I <- recalculated values, I appended to the candidates.

@@ -512,7 +512,7 @@ def main():
         "ms_per_step_with_phase_events": 1e3 * H["wall_with_phase_events"] / args.steps,
         "selection": {"positions_per_step": H["select"]["positions"] / max(1, H["select"]["selections"]),
                       "exactly_ranked_per_step": H["select"]["kept"] / max(1, H["select"]["selections"]),
-                      "full_rankings": H["select"]["fallbacks"], "selections": H["select"]["selections"]},
+                      "bound_failures": H["select"]["fallbacks"], "selections": H["select"]["selections"]},
         "hash": {"probes": H["probes"], "fp64_atomics": H["atomics"], "inserts": H["inserts"],
                  "probes_per_entry": H["probes"] / max(1, H["elements"]),
                  "probes_per_s_in_probe_half": H["probes"] / max(1e-12, ph["probe"]),

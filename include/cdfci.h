@@ -43,6 +43,7 @@ extern "C" {
 #define CDFCI_ERR_BARRIER -6       /* a device-wide barrier exceeded its spin limit */
 #define CDFCI_ERR_WORKSPACE -7     /* caller workspace too small */
 #define CDFCI_ERR_NUMERIC -8       /* a multicoordinate step produced a non-finite value */
+#define CDFCI_ERR_INTERNAL -9      /* an internal consistency check failed (cdfci_last_error says which) */
 
 typedef struct cdfci_ctx cdfci_ctx; /* opaque, library-owned */
 
@@ -249,8 +250,9 @@ int cdfci_mc_phase_times(cdfci_ctx* ctx, double* seconds, int64_t* steps);
  * selections, [1] candidate positions holding a slot (a determinant reached
  * from several chosen columns counted once per column), [2] distinct slots
  * ranked exactly (those whose key is at least the bound the repeats allow),
- * [3] selections that had to rank every candidate exactly.  Reads device
- * state (synchronises the context's stream).  CDFCI_ERR_INVALID_ARG before
+ * [3] selections whose bound held fewer than k distinct determinants
+ * (never expected; such a selection stops the run with CDFCI_ERR_INTERNAL).
+ * Reads device state (synchronises the context's stream).  CDFCI_ERR_INVALID_ARG before
  * the first k > 1 step. */
 int cdfci_mc_select_stats(cdfci_ctx* ctx, int64_t* counts);
 

@@ -14,6 +14,7 @@ CDFCI_ERR_HIP = -5
 CDFCI_ERR_BARRIER = -6
 CDFCI_ERR_WORKSPACE = -7
 CDFCI_ERR_NUMERIC = -8
+CDFCI_ERR_INTERNAL = -9
 
 
 class cdfci_opts(ctypes.Structure):

@@ -1226,6 +1226,11 @@ int check_error(cdfci_ctx* c, const Ctl& h) {
     c->poisoned = true;
     return CDFCI_ERR_NUMERIC;
   }
+  if (h.error & kErrSelect) {
+    c->poisoned = true;
+    g_last_error = "a multicoordinate selection's bound held fewer than k distinct determinants";
+    return CDFCI_ERR_INTERNAL;
+  }
   if (h.occupied > c->max_entries) {
     c->poisoned = true;
     return CDFCI_ERR_TABLE_FULL;
@@ -1828,14 +1833,13 @@ static int run_mc(cdfci_ctx* c, int k, int64_t nsteps, double* trE, cdfci_stats*
     k_mc_keys<<<kSelBlocks, 256, 0, q>>>(c->T, c->cand, c->cnt, c->pkey, c->ctl, c->mst, c->hist,
                                          c->hist + kRadixBins);
     k_mc_bound<<<1, 256, 0, q>>>(c->mst, c->ctl, c->hist, c->hist + kRadixBins, k);
-    k_mc_dedup<<<kSelBlocks, 256, 0, q>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 0);
-    k_mc_dedup<<<kSelBlocks, 256, 0, q>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap, k, 1);
+    k_mc_dedup<<<kSelBlocks, 256, 0, q>>>(c->cand, c->pkey, sb, c->mst, c->hist, c->bitmap);
     if (k <= kTailMaxK) {
-      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
-                                           c->bitmap, 1);
+      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->ctl, c->hist, c->sel_slot, c->sel_a, c->sel_b,
+                                           k, c->bitmap, 1);
     } else {
-      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->hist, c->sel_slot, c->sel_a, c->sel_b, k,
-                                           c->bitmap, 0);
+      k_mc_tail<<<1, kTailThreads, 0, q>>>(c->T, sb, c->mst, c->ctl, c->hist, c->sel_slot, c->sel_a, c->sel_b,
+                                           k, c->bitmap, 0);
       for (int pass = 1; pass < kRadixPasses; ++pass)
         k_mc_radix<<<kSelBlocks, 256, 0, q>>>(c->T, c->cand, c->cnt, sb, c->ctl, c->mst, c->hist, pass, 0, k);
       k_mc_gather_ties<<<kSelBlocks, 256, 0, q>>>(c->T, sb, c->mst, c->sel_slot, c->ties, c->sel_a, c->sel_b, k,
@@ -3189,6 +3193,7 @@ const char* cdfci_strerror(int code) {
     case CDFCI_ERR_BARRIER: return "device-wide barrier timed out";
     case CDFCI_ERR_WORKSPACE: return "workspace too small or misaligned";
     case CDFCI_ERR_NUMERIC: return "non-finite value in a multicoordinate step";
+    case CDFCI_ERR_INTERNAL: return "internal consistency check failed";
     default: return "unknown error";
   }
 }

@@ -28,6 +28,7 @@ constexpr int kErrTableFull = 1;
 constexpr int kErrBarrier = 2;
 constexpr int kErrPublish = 4;
 constexpr int kErrNumeric = 8;
+constexpr int kErrSelect = 16;  // a selection's bound held fewer than k distinct determinants
 
 struct alignas(32) Slot {
   uint64_t ka, kb;

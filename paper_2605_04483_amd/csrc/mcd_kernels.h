@@ -44,10 +44,9 @@ struct McState {
   unsigned long long n_total;        // candidates of the coming selection
   unsigned long long last_sel;       // size of the last completed step's chosen set
   unsigned long long lowkey;         // keys >= lowkey take the exact (de-duplicating) pass
-  int need_low;                      // the keys below lowkey are needed too
   int pred_d;                        // top digit of the last step's boundary (-1: none)
   // running totals of the selections (inspection): selections, candidate
-  // positions holding a slot, slots kept by the exact pass, second passes
+  // positions holding a slot, slots kept by the exact pass, bound failures
   unsigned long long acc_sel, acc_pos, acc_kept, acc_fallback;
   unsigned arrive_cols;              // workgroups of k_mc_colfinish done (the last one resets it)
 };
@@ -338,7 +337,7 @@ __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned*
 // most last_sel + 1 times in the list (once per previous column and once in
 // the chosen set's own page; once when the list was built from the table):
 // the R = k (last_sel + 1) largest position keys hold at least k distinct
-// slots.  k_mc_keys forms every position's key (one random read of the
+// slots (when all positions are fewer than R, every one is ranked).  k_mc_keys forms every position's key (one random read of the
 // slot's c and b), counts the positions per top digit, repeats included, and
 // finds the digit d holding the R-th largest.  The bin of one top digit spans
 // two binades and can hold most of the positions, so k_mc_keys also counts
@@ -348,8 +347,9 @@ __global__ void __launch_bounds__(256) k_mc_radix(const Slot* T, const unsigned*
 // key lowkey (d, or d and the second digit, followed by zeros); k_mc_dedup
 // keeps the first position of each slot among the keys >= lowkey, counting
 // them exactly, and the ranking of the lower keys is not needed (every slot
-// above them is kept).  Should fewer than k distinct slots be found there all
-// the same, a second k_mc_dedup covers the keys below.
+// above them is kept).  k_mc_tail checks the count: fewer than k distinct
+// slots above a nonzero bound would mean the bound failed, and the step then
+// stops with kErrSelect instead of choosing from an incomplete set.
 
 // The last workgroup (256 threads) of a histogram launch: the digit holding
 // the need-th largest key of a 2048-bin histogram (counted from the top), or
@@ -466,7 +466,6 @@ __global__ void __launch_bounds__(256) k_mc_bound(McState* st, const Ctl* ctl, u
     }
     st->arrive = 0;
     st->n_total = 0;
-    st->need_low = 0;
     st->skip = off ? 1 : 0;
   }
   if (off) return;  // k_mc_keys did not run: the histograms are clear
@@ -493,32 +492,23 @@ __global__ void __launch_bounds__(256) k_mc_bound(McState* st, const Ctl* ctl, u
   }
 }
 
-// The exact pass over the positions whose key is >= lowkey (second = 0) or,
-// when the first launch found fewer than k distinct slots there, < lowkey
-// (second = 1; otherwise it returns at once).  A position is kept when its
-// bit in the bitmap was clear, i.e. it is the first position of its slot to
-// arrive; kept keys and slots go to the workgroup's dense region (the second
-// launch appends; D.count holds the lengths) and are counted in the
-// histogram of top digits (radix pass 0 of k_mc_tail); the first launch also
-// counts them in n_total, which the second reads.  Within a region the order
-// of the kept entries depends on the timing of the waves; nothing downstream
-// depends on it (the histograms count, the gather ranks ties by key).
+// The exact pass over the positions whose key is >= lowkey.  A position is
+// kept when its bit in the bitmap was clear, i.e. it is the first position of
+// its slot to arrive; kept keys and slots go to the workgroup's dense region
+// (D.count holds the lengths) and are counted in the histogram of top digits
+// (radix pass 0 of k_mc_tail).  Within a region the order of the kept entries
+// depends on the timing of the waves; nothing downstream depends on it (the
+// histograms count, the gather ranks ties by key).
 __global__ void __launch_bounds__(256) k_mc_dedup(const unsigned* cand, const unsigned long long* pkey, SelBufs D,
-                                                  McState* st, unsigned* hist, unsigned* bitmap, int k,
-                                                  int second) {
+                                                  McState* st, unsigned* hist, unsigned* bitmap) {
   constexpr int U = 8;  // position keys a thread reads at once
   __shared__ unsigned h[kRadixBins];
   __shared__ unsigned s_run;
   if (st->skip) return;
   const int tid = threadIdx.x;
   const unsigned long long lowkey = st->lowkey;
-  if (second) {  // n_total is the first launch's count (the second adds nothing to it)
-    if (!(st->n_total < (unsigned long long)k && lowkey > 0ull)) return;
-    if (blockIdx.x == 0 && tid == 0) st->need_low = 1;
-  }
   for (int i = tid; i < kRadixBins; i += blockDim.x) h[i] = 0u;
-  const unsigned start = second ? D.count[blockIdx.x] : 0u;
-  if (tid == 0) s_run = start;
+  if (tid == 0) s_run = 0u;
   __syncthreads();
   const unsigned long long n = st->n_pages * kPage;
   const unsigned long long base = blockIdx.x * sel_region(n);
@@ -535,7 +525,7 @@ __global__ void __launch_bounds__(256) k_mc_dedup(const unsigned* cand, const un
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (key[u] == kKeyExcluded || (key[u] >= lowkey) == (second != 0)) continue;
+      if (key[u] == kKeyExcluded || key[u] < lowkey) continue;
       const unsigned sl = cand[i0 + (unsigned long long)u * stride];
       const unsigned bit = 1u << (sl & 31);
       if (atomicOr(&bitmap[sl >> 5], bit) & bit) continue;  // an earlier position holds the slot
@@ -548,10 +538,7 @@ __global__ void __launch_bounds__(256) k_mc_dedup(const unsigned* cand, const un
   __syncthreads();
   for (int i = tid; i < kRadixBins; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
-  if (tid == 0) {
-    D.count[blockIdx.x] = s_run;
-    if (!second && s_run > start) atomicAdd(&st->n_total, (unsigned long long)(s_run - start));
-  }
+  if (tid == 0) D.count[blockIdx.x] = s_run;
 }
 
 // The rest of the selection in one workgroup (kTailThreads threads; thread t
@@ -631,9 +618,9 @@ __device__ __forceinline__ void tail_sweep(const SelBufs& D, unsigned long long 
 constexpr int kTailList = 2048;  // bucket entries the tail keeps in LDS
 constexpr int kTailMaxK = 256;   // larger k: pass 0 in the tail, passes 1..5 and the gather on the grid
 
-__global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs D, McState* st, unsigned* hist,
-                                                          int64_t* sel_slot, uint64_t* sel_a, uint64_t* sel_b,
-                                                          int k, unsigned* bitmap, int full) {
+__global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs D, McState* st, Ctl* ctl,
+                                                          unsigned* hist, int64_t* sel_slot, uint64_t* sel_a,
+                                                          uint64_t* sel_b, int k, unsigned* bitmap, int full) {
   __shared__ unsigned h[kRadixBins];
   __shared__ unsigned s_ties[kMaxTies];
   __shared__ unsigned long long s_lk[kTailList];
@@ -663,6 +650,18 @@ __global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs
   __syncthreads();
   unsigned long long total = 0;
   for (int q = 0; q < nw; ++q) total += s_red[q];
+  if (total < (unsigned long long)k && st->lowkey > 0ull) {
+    // the bound held fewer than k distinct slots, which the repeat count
+    // rules out: stop the run rather than choose from an incomplete set
+    for (unsigned j = 0; j < cnt; ++j)
+      if (bitmap) bitmap[D.slot[base + j] >> 5] = 0u;
+    if (tid == 0) {
+      ctl->error |= kErrSelect;
+      st->skip = 1;  // the rest of this step does nothing
+      st->acc_fallback += 1;
+    }
+    return;
+  }
   const bool all = total <= (unsigned long long)k;
   bool done = all, cleared = false, inl = false;
   unsigned long long P = 0, M = 0;
@@ -691,7 +690,6 @@ __global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs
       st->arrive = 0;
       st->acc_sel += 1;
       st->acc_kept += total;
-      st->acc_fallback += st->need_low ? 1 : 0;
     }
     return;
   }
@@ -795,7 +793,6 @@ __global__ void __launch_bounds__(kTailThreads) k_mc_tail(const Slot* T, SelBufs
     st->n_sel = (unsigned long long)m;
     st->acc_sel += 1;
     st->acc_kept += total;
-    st->acc_fallback += st->need_low ? 1 : 0;
   }
 }
 

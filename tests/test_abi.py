@@ -67,6 +67,22 @@ def test_strerror_without_gpu():
     assert L.cdfci_strerror(0).decode() == "ok"
 
 
+def test_every_declared_error_code_has_its_own_message():
+    """Each CDFCI_ERR_* of include/cdfci.h is mirrored in the binding and
+    has a message of its own (no code falls through to "unknown error")."""
+    text = open(os.path.join(ROOT, "include", "cdfci.h")).read()
+    codes = dict(re.findall(r"#define (CDFCI_ERR_[A-Z_]+) (-\d+)", text))
+    assert len(codes) >= 9
+    L = _lib.load()
+    msgs = set()
+    for name, value in codes.items():
+        assert getattr(_lib, name) == int(value), name
+        m = L.cdfci_strerror(int(value)).decode()
+        assert m != "unknown error", name
+        msgs.add(m)
+    assert len(msgs) == len(codes)
+
+
 def test_host_side_argument_errors_without_gpu():
     """Argument checks that return before any device call."""
     L = _lib.load()
